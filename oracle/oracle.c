@@ -1,0 +1,381 @@
+/*
+ * Plain FP64 CPU oracle for fast-marching-based back projection
+ * (Wang & Jing, "A fast marching method based back projection algorithm for
+ * photoacoustic tomography in heterogeneous media").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * definition that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it.  It shares
+ * no code, header, table or helper with the GPU library.
+ *
+ * What it computes, in the paper's order:
+ *   1. orc_seed + orc_fmm: the first-arrival time T solving |grad T| = 1/c
+ *      (Section II-B, the eikonal equation) from a point source, by the fast
+ *      marching method: repeatedly accept the trial node with the smallest
+ *      arrival time and update its neighbours (Section II-B).  The local
+ *      update is the first-order upwind (Godunov) discretisation; the paper's
+ *      second-order one-sided difference is not used here.
+ *   2. orc_tables: one such map per sensor, the sensor acting as the point
+ *      source by reciprocity (Section II-B, last paragraph), sampled at the
+ *      region-of-interest pixels -> the delay table t_{i,j}.
+ *   3. orc_filter: b_i(t) = p_i(t) - t dp_i/dt, the bracket of the back
+ *      projection equation (Section II-C, Eq. BP), on the sample grid.
+ *   4. orc_gather: P(r_j) = sum_i w_i b_i(t_{i,j}) with linear interpolation
+ *      in time (Section II-C, Eq. BP; weights default to 1 as in the paper).
+ *   5. orc_table_to_q16 / orc_gather_q16: the same gather from a delay table
+ *      stored as a 16.16 fixed-point fractional sample index.
+ *
+ * Readings where the paper is silent (all FP64):
+ *   - nodes carry the speed; missing neighbours beyond the grid edge are +inf;
+ *     4-neighbour stencil with isotropic spacing h;
+ *   - the source is seeded by freezing every node within r0 of it at the
+ *     straight-ray time |x_k - s| / c(n*), n* the node nearest the source;
+ *   - derivative by central differences, one-sided at both ends; t_n = t0 + n dt;
+ *   - a delay outside [t0, t0 + (N-1) dt] or non-finite contributes zero; at
+ *     u = N-1 the last interval is used with weight 1.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <fenv.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_FAR 0
+#define ORC_TRIAL 1
+#define ORC_KNOWN 2
+
+/* ------------------------------------------------------------------ heap */
+typedef struct { double key; int32_t idx; } orc_item;
+typedef struct { orc_item *a; long n, cap; } orc_heap;
+
+static int item_less(orc_item x, orc_item y) {
+    return x.key < y.key || (x.key == y.key && x.idx < y.idx);
+}
+
+static int heap_push(orc_heap *h, double key, int32_t idx) {
+    if (h->n == h->cap) {
+        long nc = h->cap ? 2 * h->cap : 1024;
+        orc_item *na = (orc_item *)realloc(h->a, (size_t)nc * sizeof(orc_item));
+        if (!na) return -1;
+        h->a = na; h->cap = nc;
+    }
+    long i = h->n++;
+    orc_item it = { key, idx };
+    while (i > 0) {
+        long p = (i - 1) / 2;
+        if (!item_less(it, h->a[p])) break;
+        h->a[i] = h->a[p];
+        i = p;
+    }
+    h->a[i] = it;
+    return 0;
+}
+
+static orc_item heap_pop(orc_heap *h) {
+    orc_item top = h->a[0];
+    orc_item last = h->a[--h->n];
+    long i = 0;
+    for (;;) {
+        long l = 2 * i + 1, r = l + 1, m = i;
+        orc_item mv = last;
+        if (l < h->n && item_less(h->a[l], mv)) { m = l; mv = h->a[l]; }
+        if (r < h->n && item_less(h->a[r], mv)) { m = r; mv = h->a[r]; }
+        if (m == i) break;
+        h->a[i] = h->a[m];
+        i = m;
+    }
+    if (h->n > 0) h->a[i] = last;
+    return top;
+}
+
+/* ------------------------------------------------------------- eikonal */
+
+/* First-order Godunov update of one node from the smallest accepted neighbour
+ * along x (a) and along y (b); fh = slowness * h.  Written in the incremental
+ * form m + (d + sqrt(2 fh^2 - d^2)) / 2, which equals the textbook root
+ * ((a + b) + sqrt(2 fh^2 - (a - b)^2)) / 2 of (T-a)^2 + (T-b)^2 = fh^2. */
+static double godunov(double a, double b, double fh) {
+    double m = a < b ? a : b;
+    if (isinf(m)) return INFINITY;
+    double d = fabs(a - b);
+    if (isinf(d) || d >= fh) return m + fh;
+    return m + 0.5 * (d + sqrt(2.0 * fh * fh - d * d));
+}
+
+/* Fast marching over the whole grid.
+ * slow[k]  : slowness 1/c at node k (s/m)
+ * frozen[k]: nonzero for source nodes whose T[k] is given on entry
+ * T[k]     : out (in for frozen nodes), seconds
+ * Returns 0, or -1 on allocation failure.  *npop receives the accepted count. */
+int orc_fmm(int nx, int ny, double h, const double *slow, const unsigned char *frozen,
+            double *T, long *npop) {
+    long n = (long)nx * ny;
+    unsigned char *state = (unsigned char *)calloc((size_t)n, 1);
+    orc_heap hp = { 0, 0, 0 };
+    if (!state) return -1;
+    for (long k = 0; k < n; ++k) {
+        if (frozen[k]) state[k] = ORC_KNOWN;
+        else T[k] = INFINITY;
+    }
+    long pops = 0;
+    int rc = 0;
+    /* initial trial band: every non-frozen neighbour of a frozen node */
+    for (long k = 0; k < n && rc == 0; ++k) {
+        if (!frozen[k]) continue;
+        int i = (int)(k % nx), j = (int)(k / nx);
+        const int di[4] = { -1, 1, 0, 0 }, dj[4] = { 0, 0, -1, 1 };
+        for (int q = 0; q < 4; ++q) {
+            int ii = i + di[q], jj = j + dj[q];
+            if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+            long m = (long)jj * nx + ii;
+            if (state[m] == ORC_KNOWN) continue;
+            state[m] = ORC_TRIAL;
+        }
+    }
+    /* compute trial values of the initial band in index order */
+    for (long m = 0; m < n && rc == 0; ++m) {
+        if (state[m] != ORC_TRIAL) continue;
+        int i = (int)(m % nx), j = (int)(m / nx);
+        double a = INFINITY, b = INFINITY;
+        if (i > 0 && state[m - 1] == ORC_KNOWN) a = fmin(a, T[m - 1]);
+        if (i < nx - 1 && state[m + 1] == ORC_KNOWN) a = fmin(a, T[m + 1]);
+        if (j > 0 && state[m - nx] == ORC_KNOWN) b = fmin(b, T[m - nx]);
+        if (j < ny - 1 && state[m + nx] == ORC_KNOWN) b = fmin(b, T[m + nx]);
+        T[m] = godunov(a, b, slow[m] * h);
+        if (heap_push(&hp, T[m], (int32_t)m)) rc = -1;
+    }
+    while (rc == 0 && hp.n > 0) {
+        orc_item it = heap_pop(&hp);
+        long k = it.idx;
+        if (state[k] == ORC_KNOWN || it.key != T[k]) continue; /* stale entry */
+        state[k] = ORC_KNOWN;
+        ++pops;
+        int i = (int)(k % nx), j = (int)(k / nx);
+        const int di[4] = { -1, 1, 0, 0 }, dj[4] = { 0, 0, -1, 1 };
+        for (int q = 0; q < 4; ++q) {
+            int ii = i + di[q], jj = j + dj[q];
+            if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+            long m = (long)jj * nx + ii;
+            if (state[m] == ORC_KNOWN) continue;
+            double a = INFINITY, b = INFINITY;
+            if (ii > 0 && state[m - 1] == ORC_KNOWN) a = fmin(a, T[m - 1]);
+            if (ii < nx - 1 && state[m + 1] == ORC_KNOWN) a = fmin(a, T[m + 1]);
+            if (jj > 0 && state[m - nx] == ORC_KNOWN) b = fmin(b, T[m - nx]);
+            if (jj < ny - 1 && state[m + nx] == ORC_KNOWN) b = fmin(b, T[m + nx]);
+            double t = godunov(a, b, slow[m] * h);
+            if (t < T[m]) {
+                T[m] = t;
+                state[m] = ORC_TRIAL;
+                if (heap_push(&hp, t, (int32_t)m)) { rc = -1; break; }
+            }
+        }
+    }
+    free(hp.a);
+    free(state);
+    if (npop) *npop = pops;
+    return rc;
+}
+
+/* Point-source initial condition: every node within r0 of the source (sx, sy)
+ * is frozen at the straight-ray time |x_k - s| * slow(n*), where n* is the node
+ * nearest the source.  Coordinates are grid-centred (node i at
+ * (i - (nx-1)/2) h).  Returns the number of frozen nodes, or -1 when the
+ * source lies outside the grid's bounding box. */
+int orc_seed(int nx, int ny, double h, const double *slow, double sx, double sy, double r0,
+             unsigned char *frozen, double *T) {
+    double x0 = -0.5 * (nx - 1) * h, y0 = -0.5 * (ny - 1) * h;
+    double gi = (sx - x0) / h, gj = (sy - y0) / h;
+    if (!(gi >= 0.0 && gi <= nx - 1 && gj >= 0.0 && gj <= ny - 1)) return -1;
+    int is = (int)floor(gi + 0.5), js = (int)floor(gj + 0.5);
+    if (is > nx - 1) is = nx - 1;
+    if (js > ny - 1) js = ny - 1;
+    double fs = slow[(long)js * nx + is];
+    int rad = (int)ceil(r0 / h) + 1;
+    int cnt = 0;
+    memset(frozen, 0, (size_t)nx * ny);
+    for (int j = js - rad; j <= js + rad; ++j) {
+        if (j < 0 || j >= ny) continue;
+        for (int i = is - rad; i <= is + rad; ++i) {
+            if (i < 0 || i >= nx) continue;
+            double dx = (x0 + i * h) - sx, dy = (y0 + j * h) - sy;
+            double r = sqrt(dx * dx + dy * dy);
+            if (r <= r0) {
+                long k = (long)j * nx + i;
+                frozen[k] = 1;
+                T[k] = r * fs;
+                ++cnt;
+            }
+        }
+    }
+    return cnt;
+}
+
+/* Delay table: T[s][p] = first-arrival time from sensor s to ROI node pix[p],
+ * one fast-marching solve per sensor, seeded with r0 = 2h.  speed is float32
+ * m/s (row-major [ny][nx]); sxy is [S][2] metres.  Returns 0, -1 on bad input
+ * (non-positive or non-finite speed, sensor outside the grid, pixel index out
+ * of range) or -2 on allocation failure. */
+int orc_tables(int nx, int ny, double h, const float *speed, const double *sxy, int S,
+               const int32_t *pix, long P, double *table, int nthreads) {
+    long n = (long)nx * ny;
+    for (long p = 0; p < P; ++p)
+        if (pix[p] < 0 || pix[p] >= n) return -1;
+    double *slow = (double *)malloc((size_t)n * sizeof(double));
+    if (!slow) return -2;
+    for (long k = 0; k < n; ++k) {
+        double c = (double)speed[k];
+        if (!(c > 0.0) || isinf(c)) { free(slow); return -1; }
+        slow[k] = 1.0 / c;
+    }
+    int rc = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+        double *T = (double *)malloc((size_t)n * sizeof(double));
+        unsigned char *fr = (unsigned char *)malloc((size_t)n);
+        if (!T || !fr) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            rc = -2;
+        }
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int s = 0; s < S; ++s) {
+            if (!T || !fr) continue;
+            int c = orc_seed(nx, ny, h, slow, sxy[2 * s], sxy[2 * s + 1], 2.0 * h, fr, T);
+            if (c < 0) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+                rc = -1;
+                continue;
+            }
+            if (orc_fmm(nx, ny, h, slow, fr, T, 0)) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+                rc = -2;
+                continue;
+            }
+            for (long p = 0; p < P; ++p) table[(long)s * P + p] = T[pix[p]];
+        }
+        free(T);
+        free(fr);
+    }
+    free(slow);
+    return rc;
+}
+
+/* -------------------------------------------------------------- filter */
+
+/* b[r][n] = p[r][n] - t_n * D[r][n], t_n = t0 + n dt, with D the central
+ * difference (p[n+1]-p[n-1])/(2 dt) inside and one-sided differences at n = 0
+ * and n = N-1.  rows independent signals of N >= 2 samples each. */
+void orc_filter(const double *p, long rows, int N, double t0, double dt, double *b) {
+    for (long r = 0; r < rows; ++r) {
+        const double *x = p + r * N;
+        double *y = b + r * N;
+        for (int k = 0; k < N; ++k) {
+            double D;
+            if (k == 0) D = (x[1] - x[0]) / dt;
+            else if (k == N - 1) D = (x[N - 1] - x[N - 2]) / dt;
+            else D = (x[k + 1] - x[k - 1]) / (2.0 * dt);
+            double t = t0 + k * dt;
+            y[k] = x[k] - t * D;
+        }
+    }
+}
+
+/* -------------------------------------------------------------- gather */
+
+/* Linear interpolation of b[0..N-1] at fractional sample position u; zero
+ * outside [0, N-1]. */
+static double lerp_at(const double *b, int N, double u) {
+    if (!(u >= 0.0) || !(u <= (double)(N - 1))) return 0.0;
+    double fl = floor(u);
+    long n = (long)fl;
+    if (n > N - 2) n = N - 2;
+    double a = u - (double)n;
+    return b[n] + a * (b[n + 1] - b[n]);
+}
+
+/* img[f][p] = sum_{s=0}^{S-1} w[s] * b[f][s](T[s][p]) for F frames, summed in
+ * sensor order.  T in seconds (non-finite = no contribution); w may be NULL
+ * (all ones). */
+void orc_gather(const double *T, const double *b, const double *w, int S, long P, int N, int F,
+                double t0, double dt, double *img, int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (long p = 0; p < P; ++p) {
+        for (int f = 0; f < F; ++f) {
+            double acc = 0.0;
+            for (int s = 0; s < S; ++s) {
+                double t = T[(long)s * P + p];
+                if (!isfinite(t)) continue;
+                double u = (t - t0) / dt;
+                double ws = w ? w[s] : 1.0;
+                acc += ws * lerp_at(b + ((long)f * S + s) * N, N, u);
+            }
+            img[(long)f * P + p] = acc;
+        }
+    }
+}
+
+/* 16.16 fixed-point fractional sample index of each delay:
+ * u = (T - t0) / dt in FP64; q = round-half-even(u * 65536) when T is finite
+ * and 0 <= u <= N-1, otherwise the sentinel 0xFFFFFFFF.  Requires N <= 65535. */
+void orc_table_to_q16(const float *T, long n, double t0, double dt, int N, uint32_t *q) {
+    int old = fegetround();
+    fesetround(FE_TONEAREST);
+    for (long k = 0; k < n; ++k) {
+        double t = (double)T[k];
+        double u = (t - t0) / dt;
+        if (!isfinite(t) || !(u >= 0.0) || !(u <= (double)(N - 1))) {
+            q[k] = 0xFFFFFFFFu;
+            continue;
+        }
+        q[k] = (uint32_t)nearbyint(u * 65536.0);
+    }
+    fesetround(old);
+}
+
+/* Gather from a 16.16 table: n = q >> 16, alpha = (q & 0xFFFF) / 65536; the
+ * sentinel contributes zero; n = N-1 (alpha = 0) is read as the end of the
+ * last interval. */
+void orc_gather_q16(const uint32_t *q, const double *b, const double *w, int S, long P, int N, int F,
+                    double *img, int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (long p = 0; p < P; ++p) {
+        for (int f = 0; f < F; ++f) {
+            double acc = 0.0;
+            for (int s = 0; s < S; ++s) {
+                uint32_t v = q[(long)s * P + p];
+                if (v == 0xFFFFFFFFu) continue;
+                double u = (double)(v >> 16) + (double)(v & 0xFFFFu) / 65536.0;
+                double ws = w ? w[s] : 1.0;
+                acc += ws * lerp_at(b + ((long)f * S + s) * N, N, u);
+            }
+            img[(long)f * P + p] = acc;
+        }
+    }
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
