@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Throughput of the back-projection hot path on one MI355X.
+
+A step is one pass of the online path over one frame of synthetic sensor data
+(512 sensors x 2048 samples at 25 MHz) for the paper-scale geometry
+(256x256 grid, h = 0.2 mm, random skull, 21336 region-of-interest pixels):
+the fused UBP filter + delay-and-sum gather, launched through the C ABI with
+the per-sensor delay table already resident in HBM.  The table itself is built
+once beforehand by pat_eikonal_tables (the paper's offline step) and its build
+time is reported separately.
+
+Prints one JSON line (see the keys below).  Usage:
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--variants]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "BP pixel·sensor gathers/s, frames/s, p50/p99 frame latency @512 sensors"
+HBM_PEAK_GBS = 8000.0
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
+
+
+def cpu_baseline(geo, table, frames, budget_s=12.0):
+    """The FP64 oracle (filter + gather) on the host cores, timed on a bounded
+    sample: whole frames of the same workload restricted to a pixel subset."""
+    from oracle import oracle as orc
+    T = np.asarray(table, dtype=np.float64)
+    sub = np.arange(0, geo.P, 8)  # every 8th pixel
+    Ts = np.ascontiguousarray(T[:, sub])
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        p = frames[n % len(frames)]
+        orc.backproject(Ts, p, geo.dt, geo.t0)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 64:
+            break
+    gathers = n * geo.S * sub.size
+    return {"value": gathers / el, "unit": "gathers/s", "cores": orc.max_threads(), "kind": "oracle",
+            "sample": f"{n} frames x {geo.S} sensors x {sub.size} pixels (every 8th ROI pixel), FP64 filter+gather, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--config", default="paper")
+    ap.add_argument("--frames", type=int, default=8, help="distinct resident frames cycled through")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--variants", action="store_true", help="also time the reduced-precision variants")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
+              f"(frame-parallel sharding across GPUs needs no exchange and is described in the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1501_03869_amd import inputs, pat
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    ctx = pat.Context(0)
+    geo = inputs.config(args.config)
+    print(f"[bench] {geo.name}: grid {geo.nx}x{geo.ny} S={geo.S} P={geo.P} N={geo.n_samples}", file=sys.stderr,
+          flush=True)
+
+    speed = torch.from_numpy(geo.speed).to(dev)
+    pix = torch.from_numpy(geo.pix).to(dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    table = ctx.eikonal_tables(speed, geo.h, geo.sensors, pix)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    est = ctx.eikonal_stats()
+    print(f"[bench] tables built in {build_s:.3f} s ({est['rounds']} rounds)", file=sys.stderr, flush=True)
+
+    table_h = table.cpu().numpy()
+    frames_h = [inputs.frame_for(geo, table_h, f) for f in range(args.frames)]
+    frames = torch.from_numpy(np.stack(frames_h)).to(dev)
+    img = torch.empty((args.frames, geo.P), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        r = i % args.frames
+        ctx.backproject(table, frames[r], geo.dt, geo.t0, filtered=False, out=img[r], stream=stream)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        step(i)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = [a.elapsed_time(b) for a, b in ev]
+
+    S, P, N = geo.S, geo.P, geo.n_samples
+    gathers = args.steps * S * P
+    value = gathers / wall
+    bytes_per_frame = 4 * S * P + 4 * S * N + 4 * P
+    avg_kernel_s = float(np.mean(dev_ms)) * 1e-3
+    achieved = bytes_per_frame / avg_kernel_s / 1e9
+
+    # end-to-end latency: host frame -> H2D -> back projection -> D2H image
+    pinned_in = [torch.from_numpy(f).pin_memory() for f in frames_h[:4]]
+    pinned_out = torch.empty((P,), dtype=torch.float32).pin_memory()
+    dframe = torch.empty_like(frames[0])
+    lat = []
+    for i in range(max(50, min(args.steps, 200))):
+        t1 = time.perf_counter()
+        dframe.copy_(pinned_in[i % 4], non_blocking=True)
+        ctx.backproject(table, dframe, geo.dt, geo.t0, filtered=False, out=img[0], stream=stream)
+        pinned_out.copy_(img[0], non_blocking=True)
+        stream.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "gathers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{geo.name}: {geo.nx}x{geo.ny} grid h={geo.h * 1e3:g} mm, {S} sensors, {P} ROI "
+                               f"pixels, {N} samples at {1e-6 / geo.dt:g} MHz, FP32 table + FP32 signals, "
+                               f"fused filter+gather, one frame per step",
+                   "sensors": S, "pixels": P, "samples": N, "frames_per_step": 1, "table_format": "f32"},
+        "frames_per_s": args.steps / wall,
+        "device_ms_per_frame_p50": percentile(dev_ms, 50),
+        "device_ms_per_frame_p99": percentile(dev_ms, 99),
+        "latency_ms_p50": percentile(lat, 50),
+        "latency_ms_p99": percentile(lat, 99),
+        "latency_note": "host frame -> H2D -> fused filter+gather -> D2H image, synchronous, pinned buffers",
+        "table_build_s": build_s,
+        "table_build_rounds": est["rounds"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "pat_backproject (gather + fixed-order partial-sum reduce)",
+                     "algorithmic_bytes_per_launch": bytes_per_frame},
+        "paper_context": "123.79 ms for 512 sensors x 21323 pixels on an NVIDIA Tesla C2075, transfers included",
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(geo, table_h, frames_h)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,180 @@
+/*
+ * pat.h - C ABI of libpat, fast-marching-based back projection for
+ * photoacoustic tomography in heterogeneous media on AMD Instinct MI355X
+ * (gfx950).  Method: Wang & Jing, "A fast marching method based back
+ * projection algorithm for photoacoustic tomography in heterogeneous media".
+ *
+ * Three steps form the hot path:
+ *   pat_eikonal_tables  per-sensor first-arrival times (Section II-B: the
+ *                       eikonal equation solved from each sensor as a point
+ *                       source, by ray reversibility), sampled at the
+ *                       region-of-interest pixels -> delay table t_{i,j};
+ *   pat_filter          b_i(t) = p_i(t) - t dp_i/dt (the bracket of the back
+ *                       projection equation, Section II-C);
+ *   pat_backproject     P(r_j) = sum_i w_i b_i(t_{i,j}), linear interpolation
+ *                       in time (Section II-C, Eq. BP).
+ * The tables are built once per geometry and reused for every frame (the
+ * paper's offline / online split, Section III).
+ *
+ * Conventions for every function:
+ *   - Return 0 (PAT_OK) or a negative pat_status; nothing throws across the
+ *     ABI.  pat_last_error() gives a message for the calling thread's last
+ *     failure.
+ *   - Arguments named d_* are device pointers (HIP device memory of the
+ *     context's device), h_* are host pointers.  The caller owns all of them;
+ *     the library never frees caller memory.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *     is enqueued on it; the caller keeps buffers alive until the stream has
+ *     executed the work (hipMemcpyAsync semantics).  Functions that must read
+ *     a result back to the host (pat_eikonal_tables) synchronise the stream.
+ *   - Inputs are validated before any launch; invalid ones give PAT_EINVAL
+ *     and launch nothing.
+ *   - Grid convention: node (i, j), i along x, flat index k = j*nx + i, at
+ *     x_i = (i - (nx-1)/2) h, y_j = (j - (ny-1)/2) h (grid-centred metres).
+ *   - Time convention: sample n of a signal is taken at t_n = t0 + n dt
+ *     (the laser pulse fires at t = 0).
+ */
+#ifndef PAT_H
+#define PAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pat_status {
+    PAT_OK = 0,
+    PAT_EINVAL = -1,     /* invalid argument (nothing was launched) */
+    PAT_ENOMEM = -2,     /* device or host allocation failed */
+    PAT_EDEVICE = -3,    /* a HIP runtime call failed */
+    PAT_EBUSY = -4,      /* admission refused (serving API) */
+    PAT_ENOTFOUND = -5,  /* unknown map id or ticket (serving API) */
+    PAT_ETIMEOUT = -6,   /* wait timed out (serving API) */
+    PAT_ENOCONV = -7     /* eikonal iteration exceeded its round cap */
+} pat_status;
+
+/* Delay-table formats accepted by pat_backproject. */
+enum {
+    PAT_TABLE_F32 = 0,   /* float32 seconds; non-finite = no contribution */
+    PAT_TABLE_Q16 = 1    /* uint32 16.16 fractional sample index,
+                            0xFFFFFFFF = no contribution */
+};
+
+/* Signal formats accepted by pat_backproject. */
+enum {
+    PAT_SIG_F32 = 0,     /* float32 samples */
+    PAT_SIG_F16 = 1      /* IEEE binary16 samples, value = half * frame_scale[f] */
+};
+
+typedef struct pat_ctx pat_ctx;
+
+/* Message describing the calling thread's most recent failure ("" if none). */
+const char *pat_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int pat_version(void);
+
+/* Create a context bound to HIP device `device` (it becomes current for the
+ * calling thread).  The context owns reusable device scratch (eikonal working
+ * maps, gather partial sums).  One context may be used from one host thread
+ * at a time. */
+int pat_ctx_create(int device, pat_ctx **out);
+int pat_ctx_destroy(pat_ctx *ctx);
+
+/* Grow the context's gather scratch to at least `bytes` now, so that later
+ * pat_backproject calls allocate nothing (e.g. inside HIP graph capture). */
+int pat_ctx_reserve(pat_ctx *ctx, size_t bytes);
+
+/* Bytes of context scratch pat_backproject needs for these sizes. */
+size_t pat_backproject_scratch_bytes(int S, int P, int F);
+
+/*
+ * Delay tables (Section II-B): for every sensor s, the first-arrival time
+ * field of |grad T| = 1/c from s as a point source, discretised by the
+ * first-order upwind (Godunov) scheme on the 4-neighbour grid, the discrete
+ * solution the fast marching method computes; d_table[s][p] = T_s(pix[p]).
+ *
+ *   d_speed   float32 [ny][nx] speed of sound (m/s) at the nodes; every value
+ *             finite and > 0.
+ *   nx, ny    grid size, each >= 2.   h  node spacing (metres), > 0.
+ *   h_sensor_xy  float64 [S][2] sensor positions (metres, grid-centred), each
+ *             inside the grid's bounding box.
+ *   d_pix     int32 [P] region-of-interest node indices k = j*nx + i, each in
+ *             [0, nx*ny).  Any order; the table follows it.
+ *   d_table   float32 [S][P] output, seconds (pixel-major per sensor).
+ *
+ * Source seeding: nodes within 2h of the sensor are fixed at the straight-ray
+ * time |x_k - s| / c(n*), n* the node nearest the sensor; the rest converge
+ * to the upwind fixed point by tile-parallel relaxation in integer fixed
+ * point.  Synchronises `stream`.  PAT_ENOCONV if the relaxation exceeds its
+ * round cap (never expected).
+ */
+int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, int ny, double h,
+                       const double *h_sensor_xy, int S, const int32_t *d_pix, int P,
+                       float *d_table, void *stream);
+
+/* Statistics of the calling context's last pat_eikonal_tables call. */
+typedef struct pat_eikonal_stats {
+    int64_t rounds;          /* relaxation rounds (kernel launches), all chunks */
+    int64_t tile_visits;     /* tiles processed over all rounds */
+    int64_t guard_hits;      /* FP64 fallbacks of the quadratic solve */
+    double lsb_seconds;      /* fixed-point unit of the working times */
+    double seconds;          /* wall time of the call */
+} pat_eikonal_stats;
+int pat_eikonal_last_stats(pat_ctx *ctx, pat_eikonal_stats *out);
+
+/*
+ * Delay table -> 16.16 fixed-point fractional sample index:
+ * u = (T - t0) / dt computed in FP64; d_q = round-half-even(u * 65536) when T
+ * is finite and 0 <= u <= N-1, else 0xFFFFFFFF.  n elements, N <= 65535.
+ */
+int pat_table_to_q16(pat_ctx *ctx, const float *d_table, int64_t n, double t0, double dt, int N,
+                     uint32_t *d_q, void *stream);
+
+/*
+ * Host helper: stable reorder of ROI node indices into tile-major order
+ * (tiles of tile_w x tile_h nodes, tiles row-major, nodes row-major inside a
+ * tile), which gives the gather's pixel blocks compact footprints.
+ * h_pix_out may not alias h_pix.
+ */
+int pat_tile_order(int nx, int ny, const int32_t *h_pix, int P, int tile_w, int tile_h,
+                   int32_t *h_pix_out);
+
+/*
+ * UBP filter (Section II-C): b[r][n] = p[r][n] - t_n * D[r][n] with
+ * t_n = t0 + n dt and D the central difference (p[n+1]-p[n-1])/(2 dt),
+ * one-sided at n = 0 and n = N-1.  rows independent signals of N >= 2 float32
+ * samples, row-major.  d_b may equal d_p only if rows == 0.
+ */
+int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, double dt, float *d_b,
+               void *stream);
+
+/*
+ * Back projection (Section II-C, Eq. BP):
+ *   d_img[f][p] = sum_{s=0}^{S-1} w[s] * lerp(b_f,s, u),  u = (T[s][p] - t0)/dt
+ * with linear interpolation between samples floor(u) and floor(u)+1 (the last
+ * interval at u = N-1); delays with u < 0, u > N-1 or non-finite contribute 0.
+ *
+ *   d_table   [S][P], format table_fmt (PAT_TABLE_F32 seconds or
+ *             PAT_TABLE_Q16 from pat_table_to_q16 with the same t0, dt, N).
+ *   d_sig     [F][S][N] signals, format sig_fmt.  If sig_is_filtered is 0 the
+ *             signals are raw pressures p and the filter above is applied
+ *             inside the kernel; otherwise they are already b.
+ *   d_frame_scale  float32 [F] multipliers of PAT_SIG_F16 frames (NULL = 1).
+ *   d_w       float32 [S] sensor weights (NULL = all 1).
+ *   d_img     float32 [F][P] output.
+ * Accumulation is FP32 in a fixed order, so results are bitwise reproducible
+ * for fixed inputs and sizes.  Uses context scratch of
+ * pat_backproject_scratch_bytes(S, P, F) bytes (allocated on first need).
+ */
+int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
+                    int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
+                    int N, int F, double t0, double dt, float *d_img, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAT_H */

@@ -1,0 +1,175 @@
+// Context, error reporting, validation and the small host-side entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pat_internal.h"
+
+static thread_local char g_err[512] = "";
+
+int pat_fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int pat_hip_fail(hipError_t e, const char *what) {
+    return pat_fail(e == hipErrorOutOfMemory ? PAT_ENOMEM : PAT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char *pat_last_error(void) { return g_err; }
+
+extern "C" int pat_version(void) { return 10000; }
+
+int pat_devbuf::grow(size_t need) {
+    if (need <= bytes) return PAT_OK;
+    release();
+    size_t b = std::max(need, (size_t)256);
+    hipError_t e = hipMalloc(&ptr, b);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return pat_fail(PAT_ENOMEM, "hipMalloc(%zu bytes) failed: %s", b, hipGetErrorString(e));
+    }
+    bytes = b;
+    return PAT_OK;
+}
+
+void pat_devbuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+int pat_make_current(pat_ctx *ctx) {
+    if (!ctx) return pat_fail(PAT_EINVAL, "null context");
+    PAT_HIP(hipSetDevice(ctx->device));
+    return PAT_OK;
+}
+
+extern "C" int pat_ctx_create(int device, pat_ctx **out) {
+    if (!out) return pat_fail(PAT_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    PAT_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return pat_fail(PAT_EINVAL, "device %d out of range [0, %d)", device, n);
+    PAT_HIP(hipSetDevice(device));
+    pat_ctx *c = new (std::nothrow) pat_ctx();
+    if (!c) return pat_fail(PAT_ENOMEM, "host allocation failed");
+    c->device = device;
+    hipError_t e = hipHostMalloc((void **)&c->eik_count_host, 4 * sizeof(uint32_t), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete c;
+        return pat_hip_fail(e, "hipHostMalloc");
+    }
+    *out = c;
+    return PAT_OK;
+}
+
+extern "C" int pat_ctx_destroy(pat_ctx *ctx) {
+    if (!ctx) return PAT_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->gather_scratch.release();
+    ctx->eik_tq.release();
+    ctx->eik_f.release();
+    ctx->eik_flags.release();
+    ctx->eik_lists.release();
+    ctx->eik_seeds.release();
+    ctx->eik_count.release();
+    if (ctx->eik_count_host) (void)hipHostFree(ctx->eik_count_host);
+    delete ctx;
+    return PAT_OK;
+}
+
+extern "C" int pat_ctx_reserve(pat_ctx *ctx, size_t bytes) {
+    int rc = pat_make_current(ctx);
+    if (rc) return rc;
+    return ctx->gather_scratch.grow(bytes);
+}
+
+extern "C" int pat_eikonal_last_stats(pat_ctx *ctx, pat_eikonal_stats *out) {
+    if (!ctx || !out) return pat_fail(PAT_EINVAL, "null argument");
+    *out = ctx->last_eik;
+    return PAT_OK;
+}
+
+extern "C" int pat_tile_order(int nx, int ny, const int32_t *h_pix, int P, int tile_w, int tile_h,
+                              int32_t *h_pix_out) {
+    if (nx < 1 || ny < 1 || P < 0 || tile_w < 1 || tile_h < 1)
+        return pat_fail(PAT_EINVAL, "bad sizes nx=%d ny=%d P=%d tile=%dx%d", nx, ny, P, tile_w, tile_h);
+    if (P > 0 && (!h_pix || !h_pix_out)) return pat_fail(PAT_EINVAL, "null pixel array");
+    if (P > 0 && h_pix == h_pix_out) return pat_fail(PAT_EINVAL, "h_pix_out aliases h_pix");
+    const long n = (long)nx * ny;
+    const int tx = (nx + tile_w - 1) / tile_w;
+    std::vector<std::pair<int64_t, int32_t>> key((size_t)P);
+    for (int p = 0; p < P; ++p) {
+        int32_t k = h_pix[p];
+        if (k < 0 || k >= n) return pat_fail(PAT_EINVAL, "pixel %d index %d out of range", p, k);
+        int i = k % nx, j = k / nx;
+        int64_t tile = (int64_t)(j / tile_h) * tx + (i / tile_w);
+        int64_t in = (int64_t)(j % tile_h) * tile_w + (i % tile_w);
+        key[(size_t)p] = { tile * ((int64_t)tile_w * tile_h) + in, k };
+    }
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<int64_t, int32_t> &a, const std::pair<int64_t, int32_t> &b) {
+                         return a.first < b.first;
+                     });
+    for (int p = 0; p < P; ++p) h_pix_out[p] = key[(size_t)p].second;
+    return PAT_OK;
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+extern "C" int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, double dt, float *d_b,
+                          void *stream) {
+    int rc = pat_make_current(ctx);
+    if (rc) return rc;
+    if (rows < 0 || N < 2) return pat_fail(PAT_EINVAL, "need rows >= 0 and N >= 2 (rows=%d N=%d)", rows, N);
+    if (!finite_pos(dt) || !std::isfinite(t0)) return pat_fail(PAT_EINVAL, "need finite t0 and dt > 0");
+    if (rows == 0) return PAT_OK;
+    if (!d_p || !d_b) return pat_fail(PAT_EINVAL, "null signal pointer");
+    if (d_p == d_b) return pat_fail(PAT_EINVAL, "in-place filtering is not supported");
+    return pat_launch_filter(d_p, rows, N, t0, dt, d_b, (hipStream_t)stream);
+}
+
+extern "C" int pat_table_to_q16(pat_ctx *ctx, const float *d_table, int64_t n, double t0, double dt, int N,
+                                uint32_t *d_q, void *stream) {
+    int rc = pat_make_current(ctx);
+    if (rc) return rc;
+    if (n < 0) return pat_fail(PAT_EINVAL, "negative length");
+    if (N < 2 || N > 65535) return pat_fail(PAT_EINVAL, "16.16 indices need 2 <= N <= 65535 (N=%d)", N);
+    if (!finite_pos(dt) || !std::isfinite(t0)) return pat_fail(PAT_EINVAL, "need finite t0 and dt > 0");
+    if (n == 0) return PAT_OK;
+    if (!d_table || !d_q) return pat_fail(PAT_EINVAL, "null table pointer");
+    return pat_launch_table_to_q16(d_table, n, t0, dt, N, d_q, (hipStream_t)stream);
+}
+
+extern "C" int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
+                               int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
+                               int N, int F, double t0, double dt, float *d_img, void *stream) {
+    int rc = pat_make_current(ctx);
+    if (rc) return rc;
+    if (S < 0 || P < 0 || F < 0) return pat_fail(PAT_EINVAL, "negative size (S=%d P=%d F=%d)", S, P, F);
+    if (N < 2) return pat_fail(PAT_EINVAL, "need N >= 2 samples (N=%d)", N);
+    if (table_fmt != PAT_TABLE_F32 && table_fmt != PAT_TABLE_Q16)
+        return pat_fail(PAT_EINVAL, "unknown table format %d", table_fmt);
+    if (sig_fmt != PAT_SIG_F32 && sig_fmt != PAT_SIG_F16) return pat_fail(PAT_EINVAL, "unknown signal format %d", sig_fmt);
+    if (table_fmt == PAT_TABLE_Q16 && N > 65535) return pat_fail(PAT_EINVAL, "16.16 tables need N <= 65535");
+    if (!finite_pos(dt) || !std::isfinite(t0)) return pat_fail(PAT_EINVAL, "need finite t0 and dt > 0");
+    if ((long long)S * N > INT32_MAX || (long long)S * P > ((long long)1 << 40))
+        return pat_fail(PAT_EINVAL, "sizes too large");
+    if (P == 0 || F == 0) return PAT_OK;
+    if (!d_img) return pat_fail(PAT_EINVAL, "null image pointer");
+    if (S > 0 && (!d_table || !d_sig)) return pat_fail(PAT_EINVAL, "null table or signal pointer");
+    return pat_launch_backproject(ctx, d_table, table_fmt, d_sig, sig_fmt, sig_is_filtered, d_frame_scale, d_w, S, P,
+                                  N, F, t0, dt, d_img, (hipStream_t)stream);
+}

@@ -1,0 +1,373 @@
+// Per-sensor travel-time tables (Section II-B): the first-order upwind
+// (Godunov) discretisation of |grad T| = 1/c from each sensor as a point
+// source, solved by tile-parallel relaxation to the same discrete fixed point
+// that fast marching reaches.
+//
+// Layout and scheme:
+//  * Working times are uint32 fixed point, T = Tq * lsb with lsb a power of two
+//    chosen so that the Dijkstra upper bound (nx + ny + 2) h max(1/c) fits below
+//    2^32 - 1; 0xFFFFFFFF is "not reached".  Integer adds and mins are exact,
+//    so rounding cannot drift systematically along long straight rays, and the
+//    minimum is order independent.
+//  * Each map is cut into 32x32 tiles.  A workgroup loads one tile plus a
+//    one-node halo into LDS and relaxes it in place until no node changes
+//    (workgroup OR-reduction), then writes the changed nodes back and
+//    activates the neighbour tiles whose shared edge changed.  Rounds repeat
+//    until no tile is active.  Values only decrease, so every relaxation
+//    order reaches the same fixed point.
+//  * The local update is computed in FP32 from the exact integer difference
+//    d = |a - b| of the two upwind neighbours:
+//    T = min(a, b) + F when d >= F, else min(a, b) + (d + sqrt(2 F^2 - d^2)) / 2,
+//    F = h / (c lsb).  The discriminant is then at least F^2, so the FP64
+//    fallback (taken below F^2 / 1024) is kept as a guard and counted.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "pat_internal.h"
+
+namespace {
+
+constexpr int TS = 32;                  // tile edge (nodes)
+constexpr int HS = TS + 2;              // tile edge with halo
+constexpr int EK_THREADS = 256;         // 32 columns x 8 strips of 4 rows
+constexpr int ROWS_PER_THREAD = TS * TS / EK_THREADS;
+constexpr uint32_t TQ_INF = 0xFFFFFFFFu;
+constexpr int SEED_BOX = 5;             // frozen nodes lie in a 5x5 box around the nearest node
+constexpr int LOCAL_ITER_CAP = 6 * TS;  // a tile that has not settled re-queues itself
+
+struct EikGrid {
+    int nx, ny, tiles_x, tiles_y, tiles_per_map;
+};
+
+__device__ __forceinline__ uint32_t godunov_q(uint32_t a, uint32_t b, float F, unsigned int *guard) {
+    const uint32_t m = min(a, b);
+    if (m == TQ_INF) return TQ_INF;
+    const uint32_t M = max(a, b);
+    float inc = F;
+    if (M != TQ_INF) {
+        const uint32_t di = M - m;
+        const float d = (float)di;
+        if (d < F) {
+            const float disc = fmaf(-d, d, 2.0f * F * F);
+            if (disc < F * F * (1.0f / 1024.0f)) {
+                const double dd = (double)di, FF = (double)F;
+                inc = (float)(0.5 * (dd + sqrt(2.0 * FF * FF - dd * dd)));
+                atomicAdd(guard, 1u);
+            } else {
+                inc = 0.5f * (d + sqrtf(disc));
+            }
+        }
+    }
+    const uint64_t r = (uint64_t)m + (uint32_t)(inc + 0.5f);
+    return r >= TQ_INF ? TQ_INF - 1 : (uint32_t)r;
+}
+
+__device__ __forceinline__ bool is_frozen(int gx, int gy, const int *seed_ij, const uint32_t *seed_val, int m,
+                                          uint32_t &val) {
+    const int bx = gx - seed_ij[2 * m], by = gy - seed_ij[2 * m + 1];
+    if ((unsigned)bx >= (unsigned)SEED_BOX || (unsigned)by >= (unsigned)SEED_BOX) return false;
+    val = seed_val[m * SEED_BOX * SEED_BOX + by * SEED_BOX + bx];
+    return val != TQ_INF;
+}
+
+// Tq[m][k] = seed value on frozen nodes, "not reached" elsewhere.
+__global__ void __launch_bounds__(256) k_eik_init(uint32_t *__restrict__ Tq, int maps, EikGrid g,
+                                                  const int *__restrict__ seed_ij, const uint32_t *__restrict__ seed_val) {
+    const long n = (long)g.nx * g.ny;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * maps) return;
+    const int m = (int)(i / n);
+    const int k = (int)(i % n);
+    uint32_t v;
+    Tq[i] = is_frozen(k % g.nx, k / g.nx, seed_ij, seed_val, m, v) ? v : TQ_INF;
+}
+
+__device__ __forceinline__ void activate(uint32_t tile, uint32_t *flags_next, uint32_t *list_next, uint32_t *cnt_next) {
+    if (atomicExch(&flags_next[tile], 1u) == 0u) {
+        const uint32_t pos = atomicAdd(cnt_next, 1u);
+        list_next[pos] = tile;
+    }
+}
+
+__global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ Tq, const float *__restrict__ Fmap,
+                                                         EikGrid g, const int *__restrict__ seed_ij,
+                                                         const uint32_t *__restrict__ seed_val,
+                                                         const uint32_t *__restrict__ list_cur,
+                                                         uint32_t *__restrict__ flags_cur,
+                                                         uint32_t *__restrict__ list_next,
+                                                         uint32_t *__restrict__ flags_next,
+                                                         uint32_t *__restrict__ counters) {
+    __shared__ uint32_t T[HS * HS];
+    __shared__ uint32_t side_bits;
+
+    const int tid = threadIdx.x;
+    const uint32_t tile = list_cur[blockIdx.x];
+    const int m = (int)(tile / g.tiles_per_map);
+    const int r = (int)(tile % g.tiles_per_map);
+    const int ty = r / g.tiles_x, tx = r % g.tiles_x;
+    const int gx0 = tx * TS, gy0 = ty * TS;
+    uint32_t *map = Tq + (long)m * g.nx * g.ny;
+    if (tid == 0) {
+        flags_cur[tile] = 0u;
+        side_bits = 0u;
+    }
+
+    // halo: 4 edges of TS nodes each (corners are never read by the 4-point stencil)
+    for (int idx = tid; idx < 4 * TS; idx += EK_THREADS) {
+        const int side = idx / TS, o = idx % TS;
+        int gx, gy, l;
+        if (side == 0) { gx = gx0 + o; gy = gy0 - 1; l = o + 1; }
+        else if (side == 1) { gx = gx0 + o; gy = gy0 + TS; l = (TS + 1) * HS + o + 1; }
+        else if (side == 2) { gx = gx0 - 1; gy = gy0 + o; l = (o + 1) * HS; }
+        else { gx = gx0 + TS; gy = gy0 + o; l = (o + 1) * HS + TS + 1; }
+        const bool in = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny;
+        T[l] = in ? map[(long)gy * g.nx + gx] : TQ_INF;
+    }
+
+    // this thread's nodes: column lx, rows 4*strip .. 4*strip+3
+    const int lx = tid % TS;
+    const int strip = tid / TS;
+    const int gx = gx0 + lx;
+    float F[ROWS_PER_THREAD];
+    uint32_t own[ROWS_PER_THREAD];
+    unsigned live = 0;  // bit q: node q is inside the grid and not frozen
+    for (int q = 0; q < ROWS_PER_THREAD; ++q) {
+        const int ly = strip * ROWS_PER_THREAD + q;
+        const int gy = gy0 + ly;
+        const bool in = gx < g.nx && gy < g.ny;
+        uint32_t v = TQ_INF;
+        F[q] = 0.0f;
+        if (in) {
+            v = map[(long)gy * g.nx + gx];
+            F[q] = Fmap[(long)gy * g.nx + gx];
+            uint32_t sv;
+            if (!is_frozen(gx, gy, seed_ij, seed_val, m, sv)) live |= 1u << q;
+        }
+        own[q] = v;
+        T[(ly + 1) * HS + lx + 1] = v;
+    }
+    __syncthreads();
+
+    unsigned changed = 0;
+    unsigned int *guard = counters + 1;
+    int it = 0;
+    for (; it < LOCAL_ITER_CAP; ++it) {
+        int any = 0;
+        // alternate the strip direction so information crosses a strip in one pass
+        for (int qq = 0; qq < ROWS_PER_THREAD; ++qq) {
+            const int q = (it & 1) ? ROWS_PER_THREAD - 1 - qq : qq;
+            if (!(live & (1u << q))) continue;
+            const int c = (strip * ROWS_PER_THREAD + q + 1) * HS + lx + 1;
+            const uint32_t a = min(T[c - 1], T[c + 1]);
+            const uint32_t b = min(T[c - HS], T[c + HS]);
+            const uint32_t nv = godunov_q(a, b, F[q], guard);
+            if (nv < own[q]) {
+                own[q] = nv;
+                T[c] = nv;
+                changed |= 1u << q;
+                any = 1;
+            }
+        }
+        if (!__syncthreads_or(any)) break;
+    }
+
+    unsigned sides = 0;
+    for (int q = 0; q < ROWS_PER_THREAD; ++q) {
+        if (!(changed & (1u << q))) continue;
+        const int ly = strip * ROWS_PER_THREAD + q;
+        map[(long)(gy0 + ly) * g.nx + gx] = own[q];
+        if (ly == 0) sides |= 1u;
+        if (ly == TS - 1) sides |= 2u;
+        if (lx == 0) sides |= 4u;
+        if (lx == TS - 1) sides |= 8u;
+    }
+    if (it == LOCAL_ITER_CAP) sides |= 16u;
+    if (sides) atomicOr(&side_bits, sides);
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned sb = side_bits;
+        uint32_t *cnt_next = counters;
+        const uint32_t base = (uint32_t)m * g.tiles_per_map;
+        if ((sb & 1u) && ty > 0) activate(base + (ty - 1) * g.tiles_x + tx, flags_next, list_next, cnt_next);
+        if ((sb & 2u) && ty + 1 < g.tiles_y) activate(base + (ty + 1) * g.tiles_x + tx, flags_next, list_next, cnt_next);
+        if ((sb & 4u) && tx > 0) activate(base + ty * g.tiles_x + tx - 1, flags_next, list_next, cnt_next);
+        if ((sb & 8u) && tx + 1 < g.tiles_x) activate(base + ty * g.tiles_x + tx + 1, flags_next, list_next, cnt_next);
+        if (sb & 16u) activate(tile, flags_next, list_next, cnt_next);
+    }
+}
+
+// table[s0 + m][p] = Tq[m][pix[p]] * lsb, rounded once to float32 seconds.
+__global__ void __launch_bounds__(256) k_eik_extract(const uint32_t *__restrict__ Tq, long n_nodes,
+                                                     const int32_t *__restrict__ pix, int P, int maps, double lsb,
+                                                     float *__restrict__ table) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)P * maps) return;
+    const int m = (int)(i / P);
+    const int p = (int)(i % P);
+    const uint32_t v = Tq[(long)m * n_nodes + pix[p]];
+    table[i] = v == TQ_INF ? INFINITY : (float)((double)v * lsb);
+}
+
+}  // namespace
+
+extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, int ny, double h,
+                                  const double *h_sensor_xy, int S, const int32_t *d_pix, int P, float *d_table,
+                                  void *stream) {
+    const auto t_start = std::chrono::steady_clock::now();
+    int rc = pat_make_current(ctx);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (nx < 2 || ny < 2) return pat_fail(PAT_EINVAL, "grid must be at least 2x2 (got %dx%d)", nx, ny);
+    if ((long long)nx * ny > (1LL << 30)) return pat_fail(PAT_EINVAL, "grid too large");
+    if (!(std::isfinite(h) && h > 0.0)) return pat_fail(PAT_EINVAL, "node spacing must be finite and > 0");
+    if (S < 0 || P < 0) return pat_fail(PAT_EINVAL, "negative sensor or pixel count");
+    if (!d_speed) return pat_fail(PAT_EINVAL, "null speed map");
+    if (S > 0 && !h_sensor_xy) return pat_fail(PAT_EINVAL, "null sensor positions");
+    if (P > 0 && (!d_pix || !d_table)) return pat_fail(PAT_EINVAL, "null pixel list or table");
+    ctx->last_eik = pat_eikonal_stats{};
+    const long n = (long)nx * ny;
+
+    // speed map and pixel list to the host for validation and seeding
+    std::vector<float> c((size_t)n);
+    std::vector<int32_t> pix((size_t)P);
+    PAT_HIP(hipMemcpyAsync(c.data(), d_speed, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, st));
+    if (P > 0) PAT_HIP(hipMemcpyAsync(pix.data(), d_pix, (size_t)P * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PAT_HIP(hipStreamSynchronize(st));
+    double cmin = INFINITY;
+    for (long k = 0; k < n; ++k) {
+        const double v = c[(size_t)k];
+        if (!(std::isfinite(v) && v > 0.0)) return pat_fail(PAT_EINVAL, "speed at node %ld is %g (need finite > 0)", k, v);
+        cmin = std::min(cmin, v);
+    }
+    for (int p = 0; p < P; ++p)
+        if (pix[(size_t)p] < 0 || pix[(size_t)p] >= n)
+            return pat_fail(PAT_EINVAL, "pixel %d index %d outside [0, %ld)", p, pix[(size_t)p], n);
+    const double x0 = -0.5 * (nx - 1) * h, y0 = -0.5 * (ny - 1) * h;
+    for (int s = 0; s < S; ++s) {
+        const double gi = (h_sensor_xy[2 * s] - x0) / h, gj = (h_sensor_xy[2 * s + 1] - y0) / h;
+        if (!(gi >= 0.0 && gi <= nx - 1 && gj >= 0.0 && gj <= ny - 1))
+            return pat_fail(PAT_EINVAL, "sensor %d at (%g, %g) m lies outside the grid", s, h_sensor_xy[2 * s],
+                            h_sensor_xy[2 * s + 1]);
+    }
+    if (S == 0 || P == 0) return PAT_OK;
+
+    // fixed-point unit: the Dijkstra bound fits, and F = h/(c lsb) stays below 2^23
+    const double tbound = 1.01 * (double)(nx + ny + 2) * h / cmin;
+    const double lsb_range = tbound / 4294967294.0;
+    const double lsb_prec = h / cmin / 8388608.0;
+    const double lsb = std::exp2(std::ceil(std::log2(std::max(lsb_range, lsb_prec))));
+    ctx->last_eik.lsb_seconds = lsb;
+
+    std::vector<float> Fh((size_t)n);
+    for (long k = 0; k < n; ++k) Fh[(size_t)k] = (float)(h / ((double)c[(size_t)k] * lsb));
+
+    EikGrid g;
+    g.nx = nx;
+    g.ny = ny;
+    g.tiles_x = (nx + TS - 1) / TS;
+    g.tiles_y = (ny + TS - 1) / TS;
+    g.tiles_per_map = g.tiles_x * g.tiles_y;
+
+    // sensors per chunk: working maps limited to 8 GiB
+    const long budget_maps = std::max<long>(1, (8L << 30) / (n * 4));
+    const int chunk = (int)std::min<long>(S, budget_maps);
+    const long max_tiles = (long)chunk * g.tiles_per_map;
+    if (max_tiles > 0x7FFFFFFFL) return pat_fail(PAT_EINVAL, "too many tiles");
+
+    if ((rc = ctx->eik_tq.grow((size_t)chunk * n * sizeof(uint32_t)))) return rc;
+    if ((rc = ctx->eik_f.grow((size_t)n * sizeof(float)))) return rc;
+    if ((rc = ctx->eik_flags.grow((size_t)2 * max_tiles * sizeof(uint32_t)))) return rc;
+    if ((rc = ctx->eik_lists.grow((size_t)2 * max_tiles * sizeof(uint32_t)))) return rc;
+    if ((rc = ctx->eik_seeds.grow((size_t)chunk * (2 * sizeof(int) + SEED_BOX * SEED_BOX * sizeof(uint32_t))))) return rc;
+    if ((rc = ctx->eik_count.grow(4 * sizeof(uint32_t)))) return rc;
+
+    uint32_t *Tq = static_cast<uint32_t *>(ctx->eik_tq.ptr);
+    float *Fd = static_cast<float *>(ctx->eik_f.ptr);
+    uint32_t *flags[2] = { static_cast<uint32_t *>(ctx->eik_flags.ptr),
+                           static_cast<uint32_t *>(ctx->eik_flags.ptr) + max_tiles };
+    uint32_t *lists[2] = { static_cast<uint32_t *>(ctx->eik_lists.ptr),
+                           static_cast<uint32_t *>(ctx->eik_lists.ptr) + max_tiles };
+    int *seed_ij = static_cast<int *>(ctx->eik_seeds.ptr);
+    uint32_t *seed_val = reinterpret_cast<uint32_t *>(seed_ij + 2 * chunk);
+    uint32_t *counters = static_cast<uint32_t *>(ctx->eik_count.ptr);  // [0] next count, [1] guard hits
+
+    PAT_HIP(hipMemcpyAsync(Fd, Fh.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice, st));
+    PAT_HIP(hipMemsetAsync(ctx->eik_flags.ptr, 0, (size_t)2 * max_tiles * sizeof(uint32_t), st));
+    PAT_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(uint32_t), st));
+
+    const long round_cap = 100L * (g.tiles_x + g.tiles_y) + 1000;
+    std::vector<int> hij((size_t)2 * chunk);
+    std::vector<uint32_t> hval((size_t)chunk * SEED_BOX * SEED_BOX);
+    std::vector<uint32_t> init_list;
+    int64_t rounds = 0, visits = 0;
+
+    for (int s0 = 0; s0 < S; s0 += chunk) {
+        const int maps = std::min(chunk, S - s0);
+        init_list.clear();
+        for (int m = 0; m < maps; ++m) {
+            const double sx = h_sensor_xy[2 * (s0 + m)], sy = h_sensor_xy[2 * (s0 + m) + 1];
+            int is = (int)std::floor((sx - x0) / h + 0.5), js = (int)std::floor((sy - y0) / h + 0.5);
+            is = std::min(is, nx - 1);
+            js = std::min(js, ny - 1);
+            const double cs = (double)c[(size_t)js * nx + is];
+            hij[2 * m] = is - 2;
+            hij[2 * m + 1] = js - 2;
+            for (int b = 0; b < SEED_BOX; ++b)
+                for (int a = 0; a < SEED_BOX; ++a) {
+                    const int i = is - 2 + a, j = js - 2 + b;
+                    uint32_t v = TQ_INF;
+                    if (i >= 0 && i < nx && j >= 0 && j < ny) {
+                        const double dx = (x0 + i * h) - sx, dy = (y0 + j * h) - sy;
+                        const double rr = std::sqrt(dx * dx + dy * dy);
+                        if (rr <= 2.0 * h) v = (uint32_t)std::nearbyint(rr / cs / lsb);
+                    }
+                    hval[(size_t)m * SEED_BOX * SEED_BOX + b * SEED_BOX + a] = v;
+                }
+            // initial tiles: those touching the seed box grown by one node
+            const int ta = std::max(0, is - 3) / TS, tb = std::min(nx - 1, is + 3) / TS;
+            const int tc = std::max(0, js - 3) / TS, td = std::min(ny - 1, js + 3) / TS;
+            for (int ty = tc; ty <= td; ++ty)
+                for (int tx = ta; tx <= tb; ++tx) init_list.push_back((uint32_t)(m * g.tiles_per_map + ty * g.tiles_x + tx));
+        }
+        PAT_HIP(hipMemcpyAsync(seed_ij, hij.data(), (size_t)2 * maps * sizeof(int), hipMemcpyHostToDevice, st));
+        PAT_HIP(hipMemcpyAsync(seed_val, hval.data(), (size_t)maps * SEED_BOX * SEED_BOX * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, st));
+        PAT_HIP(hipMemcpyAsync(lists[0], init_list.data(), init_list.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        const long tot = (long)maps * n;
+        k_eik_init<<<dim3((unsigned)((tot + 255) / 256)), 256, 0, st>>>(Tq, maps, g, seed_ij, seed_val);
+        PAT_HIP(hipGetLastError());
+
+        uint32_t cnt = (uint32_t)init_list.size();
+        int cur = 0;
+        long chunk_rounds = 0;
+        while (cnt > 0) {
+            if (++chunk_rounds > round_cap)
+                return pat_fail(PAT_ENOCONV, "eikonal relaxation did not settle within %ld rounds", round_cap);
+            PAT_HIP(hipMemsetAsync(counters, 0, sizeof(uint32_t), st));
+            k_eik_tile<<<dim3(cnt), EK_THREADS, 0, st>>>(Tq, Fd, g, seed_ij, seed_val, lists[cur], flags[cur],
+                                                         lists[cur ^ 1], flags[cur ^ 1], counters);
+            PAT_HIP(hipGetLastError());
+            PAT_HIP(hipMemcpyAsync(ctx->eik_count_host, counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            PAT_HIP(hipStreamSynchronize(st));
+            visits += cnt;
+            cnt = ctx->eik_count_host[0];
+            cur ^= 1;
+        }
+        rounds += chunk_rounds;
+        const long tp = (long)P * maps;
+        k_eik_extract<<<dim3((unsigned)((tp + 255) / 256)), 256, 0, st>>>(Tq, n, d_pix, P, maps, lsb,
+                                                                         d_table + (long)s0 * P);
+        PAT_HIP(hipGetLastError());
+    }
+    PAT_HIP(hipStreamSynchronize(st));
+    ctx->last_eik.rounds = rounds;
+    ctx->last_eik.tile_visits = visits;
+    ctx->last_eik.guard_hits = ctx->eik_count_host[1];
+    ctx->last_eik.seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    return PAT_OK;
+}

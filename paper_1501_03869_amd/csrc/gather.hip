@@ -1,0 +1,335 @@
+// Delay-and-sum back projection (Section II-C, Eq. BP):
+//   img[f][p] = sum_s w_s * lerp(b_{f,s}, u_{s,p}),  u = (T[s][p] - t0) / dt,
+// with b = p - t dp/dt either supplied or computed in the kernel.
+//
+// Work decomposition (one launch per call):
+//  * A workgroup of 256 threads owns a chunk of 1024 consecutive table columns
+//    (4 per thread, read as one 16-byte load per sensor: the pixel-major table
+//    streams from HBM fully coalesced) and a contiguous group of sensors.
+//    Callers order the ROI tile-major (pat_tile_order) so a chunk covers a
+//    compact 2-D patch and its delays to one sensor span a short time window.
+//  * Sensors are processed 8 at a time.  For each, the workgroup stages a
+//    512-sample window of the signal, centred on the delay of the chunk's first
+//    pixel, in LDS; when the signal is raw it is filtered there
+//    (b = p - t dp/dt, central differences, one-sided ends).  Every gather then
+//    reads its two neighbouring samples from LDS.  A delay outside the window
+//    (non-compact pixel sets) is served from global memory instead, so any
+//    pixel order is correct.
+//  * Partial sums of the sensor groups are added by the last workgroup of each
+//    chunk to finish, in group order, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <algorithm>
+
+#include "pat_internal.h"
+
+namespace {
+
+constexpr int BP_THREADS = 256;
+constexpr int BP_PPT = 4;                          // pixels per thread
+constexpr int BP_CHUNK = BP_THREADS * BP_PPT;      // pixels per workgroup
+constexpr int BP_SC = 8;                           // sensors staged together
+constexpr int BP_W = 512;                          // window samples per sensor
+constexpr int BP_RAW = BP_W + 2;                   // raw samples incl. both neighbours
+constexpr int BP_TARGET_BLOCKS = 1024;             // workgroups wanted per launch
+
+struct BpShape {
+    int chunks;  // workgroups along pixels
+    int groups;  // sensor groups
+    int spg;     // sensors per group (a multiple of BP_SC unless one group)
+};
+
+BpShape bp_shape(int S, int P, int F) {
+    BpShape s;
+    s.chunks = (P + BP_CHUNK - 1) / BP_CHUNK;
+    const long per_group = (long)s.chunks * std::max(F, 1);
+    const int S1 = std::max(S, 1);
+    int G = (int)std::min<long>((BP_TARGET_BLOCKS + per_group - 1) / per_group, (S1 + BP_SC - 1) / BP_SC);
+    G = std::max(G, 1);
+    int spg = (S1 + G - 1) / G;
+    spg = ((spg + BP_SC - 1) / BP_SC) * BP_SC;
+    s.spg = spg;
+    s.groups = (S1 + spg - 1) / spg;
+    return s;
+}
+
+struct DelayF32 {
+    float inv_hi, inv_lo, off;  // u = T * (inv_hi + inv_lo) + off
+    float umax;                 // N - 1
+    __device__ __forceinline__ bool decode(float T, int N, int &n, float &a) const {
+        const float u = fmaf(T, inv_hi, fmaf(T, inv_lo, off));
+        if (!(u >= 0.0f && u <= umax)) return false;  // also rejects NaN and inf
+        n = min((int)u, N - 2);
+        a = u - (float)n;
+        return true;
+    }
+    __device__ __forceinline__ bool decode(uint32_t bits, int N, int &n, float &a) const {
+        return decode(__uint_as_float(bits), N, n, a);
+    }
+};
+
+struct DelayQ16 {
+    __device__ __forceinline__ bool decode(uint32_t q, int N, int &n, float &a) const {
+        if (q == 0xFFFFFFFFu) return false;
+        n = (int)(q >> 16);
+        a = (float)(q & 0xFFFFu) * (1.0f / 65536.0f);
+        if (n > N - 2) {  // only u = N-1 exactly: end of the last interval
+            n = N - 2;
+            a = 1.0f;
+        }
+        return true;
+    }
+};
+
+template <int SFMT>
+__device__ __forceinline__ float load_sig(const void *sig, long i, float scale) {
+    if constexpr (SFMT == PAT_SIG_F32) {
+        return static_cast<const float *>(sig)[i];
+    } else {
+        return __half2float(static_cast<const __half *>(sig)[i]) * scale;
+    }
+}
+
+// b[n] = p[n] - (n + t0/dt) * 0.5 * (p[n+1] - p[n-1]); one-sided at both ends.
+__device__ __forceinline__ float ubp(float pm, float p0, float pp, int n, int N, float t0dt) {
+    float d = pp - pm;
+    if (n == 0) d = 2.0f * (pp - p0);
+    if (n == N - 1) d = 2.0f * (p0 - pm);
+    return p0 - ((float)n + t0dt) * (0.5f * d);
+}
+
+template <int SFMT, bool FILTERED>
+__device__ __forceinline__ float sample_b(const void *sig, long row, int n, int N, float sc, float t0dt) {
+    if constexpr (FILTERED) {
+        return load_sig<SFMT>(sig, row + n, sc);
+    } else {
+        const float pm = load_sig<SFMT>(sig, row + max(n - 1, 0), sc);
+        const float p0 = load_sig<SFMT>(sig, row + n, sc);
+        const float pp = load_sig<SFMT>(sig, row + min(n + 1, N - 1), sc);
+        return ubp(pm, p0, pp, n, N, t0dt);
+    }
+}
+
+template <bool VEC4>
+__device__ __forceinline__ void load_delays(const uint32_t *__restrict__ tab, long rowoff, int p0, int P,
+                                            uint32_t (&v)[BP_PPT]) {
+    if constexpr (VEC4) {
+        if (p0 < P) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(tab + rowoff + p0);
+            v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+        } else {
+            v[0] = v[1] = v[2] = v[3] = 0xFFFFFFFFu;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < BP_PPT; ++k) v[k] = (p0 + k < P) ? tab[rowoff + p0 + k] : 0xFFFFFFFFu;
+    }
+}
+
+template <class Delay, int SFMT, bool FILTERED, bool VEC4>
+__global__ void __launch_bounds__(BP_THREADS) k_bp(const uint32_t *__restrict__ tab, const void *__restrict__ sig,
+                                                   const float *__restrict__ scale, const float *__restrict__ w,
+                                                   int S, int P, int N, int spg, int G, Delay dec, float t0dt,
+                                                   float *__restrict__ part, float *__restrict__ img,
+                                                   unsigned int *__restrict__ done) {
+    __shared__ float bwin[BP_SC][BP_W];
+    __shared__ float raw[FILTERED ? 1 : BP_SC][FILTERED ? 1 : BP_RAW];
+    __shared__ int anchor[BP_SC];
+    __shared__ unsigned int is_last;
+
+    const int tid = threadIdx.x;
+    const int c = blockIdx.x, g = blockIdx.y, f = blockIdx.z;
+    const int pbase = c * BP_CHUNK;
+    const int p0 = pbase + tid * BP_PPT;  // this thread's first pixel
+    const int s_begin = g * spg;
+    const int s_end = min(S, s_begin + spg);
+    const float sc = (SFMT == PAT_SIG_F16 && scale) ? scale[f] : 1.0f;
+    const long frame_row = (long)f * S;
+
+    float acc[BP_PPT] = { 0.0f, 0.0f, 0.0f, 0.0f };
+    uint32_t cur[BP_SC][BP_PPT], nxt[BP_SC][BP_PPT];
+
+#pragma unroll
+    for (int j = 0; j < BP_SC; ++j) {
+        if (s_begin + j < s_end) load_delays<VEC4>(tab, (long)(s_begin + j) * P, p0, P, cur[j]);
+        else { cur[j][0] = cur[j][1] = cur[j][2] = cur[j][3] = 0xFFFFFFFFu; }
+    }
+
+    for (int s0 = s_begin; s0 < s_end; s0 += BP_SC) {
+        const int ns = min(BP_SC, s_end - s0);
+        // prefetch the next chunk of delays while this one is staged and gathered
+#pragma unroll
+        for (int j = 0; j < BP_SC; ++j) {
+            const int s = s0 + BP_SC + j;
+            if (s < s_end) load_delays<VEC4>(tab, (long)s * P, p0, P, nxt[j]);
+            else { nxt[j][0] = nxt[j][1] = nxt[j][2] = nxt[j][3] = 0xFFFFFFFFu; }
+        }
+        // window anchors from the chunk's first pixel
+        if (tid < ns) {
+            int n;
+            float a;
+            int an = 0;
+            if (dec.decode(tab[(long)(s0 + tid) * P + pbase], N, n, a)) an = n - BP_W / 2;
+            anchor[tid] = an;
+        }
+        __syncthreads();
+        if constexpr (FILTERED) {
+            for (int idx = tid; idx < ns * BP_W; idx += BP_THREADS) {
+                const int si = idx / BP_W, j = idx % BP_W;
+                const int gi = min(max(anchor[si] + j, 0), N - 1);
+                bwin[si][j] = load_sig<SFMT>(sig, (frame_row + s0 + si) * N + gi, sc);
+            }
+        } else {
+            for (int idx = tid; idx < ns * BP_RAW; idx += BP_THREADS) {
+                const int si = idx / BP_RAW, j = idx % BP_RAW;
+                const int gi = min(max(anchor[si] - 1 + j, 0), N - 1);
+                raw[si][j] = load_sig<SFMT>(sig, (frame_row + s0 + si) * N + gi, sc);
+            }
+            __syncthreads();
+            for (int idx = tid; idx < ns * BP_W; idx += BP_THREADS) {
+                const int si = idx / BP_W, j = idx % BP_W;
+                const int i = anchor[si] + j;
+                bwin[si][j] = ubp(raw[si][j], raw[si][j + 1], raw[si][j + 2], i, N, t0dt);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < BP_SC; ++j) {
+            if (j < ns) {
+                const int s = s0 + j;
+                const float ws = w ? w[s] : 1.0f;
+                const int an = anchor[j];
+                const long row = (frame_row + s) * N;
+#pragma unroll
+                for (int k = 0; k < BP_PPT; ++k) {
+                    int n;
+                    float a;
+                    if (dec.decode(cur[j][k], N, n, a)) {
+                        const int idx = n - an;
+                        float b0, b1;
+                        if ((unsigned)idx < (unsigned)(BP_W - 1)) {
+                            b0 = bwin[j][idx];
+                            b1 = bwin[j][idx + 1];
+                        } else {
+                            b0 = sample_b<SFMT, FILTERED>(sig, row, n, N, sc, t0dt);
+                            b1 = sample_b<SFMT, FILTERED>(sig, row, n + 1, N, sc, t0dt);
+                        }
+                        acc[k] = fmaf(ws, fmaf(a, b1 - b0, b0), acc[k]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < BP_SC; ++j) {
+#pragma unroll
+            for (int k = 0; k < BP_PPT; ++k) cur[j][k] = nxt[j][k];
+        }
+        __syncthreads();  // windows and anchors are rewritten by the next chunk
+    }
+
+    const long fP = (long)f * P;
+    if (G == 1) {
+#pragma unroll
+        for (int k = 0; k < BP_PPT; ++k)
+            if (p0 + k < P) img[fP + p0 + k] = acc[k];
+        return;
+    }
+    float *mine = part + ((long)f * G + g) * P;
+#pragma unroll
+    for (int k = 0; k < BP_PPT; ++k)
+        if (p0 + k < P) mine[p0 + k] = acc[k];
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned int prev = atomicAdd(&done[(long)f * gridDim.x + c], 1u);
+        is_last = (prev == (unsigned)(G - 1)) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    const float *base = part + (long)f * G * P;
+#pragma unroll
+    for (int k = 0; k < BP_PPT; ++k) {
+        const int p = p0 + k;
+        if (p >= P) continue;
+        float s = 0.0f;
+        for (int gg = 0; gg < G; ++gg) s += __builtin_nontemporal_load(base + (long)gg * P + p);
+        img[fP + p] = s;
+    }
+    if (tid == 0) done[(long)f * gridDim.x + c] = 0u;  // ready for the next launch
+}
+
+template <class Delay, int SFMT>
+int launch(bool filtered, bool vec4, dim3 grid, const uint32_t *tab, const void *sig, const float *scale,
+           const float *w, int S, int P, int N, int spg, int G, Delay dec, float t0dt, float *part, float *img,
+           unsigned int *done, hipStream_t st) {
+#define PAT_BP_LAUNCH(FI, V4) \
+    k_bp<Delay, SFMT, FI, V4><<<grid, BP_THREADS, 0, st>>>(tab, sig, scale, w, S, P, N, spg, G, dec, t0dt, part, img, done)
+    if (filtered) {
+        if (vec4) PAT_BP_LAUNCH(true, true); else PAT_BP_LAUNCH(true, false);
+    } else {
+        if (vec4) PAT_BP_LAUNCH(false, true); else PAT_BP_LAUNCH(false, false);
+    }
+#undef PAT_BP_LAUNCH
+    PAT_HIP(hipGetLastError());
+    return PAT_OK;
+}
+
+}  // namespace
+
+// Scratch: partial sums [F][G][P] followed by one completion counter per
+// (frame, chunk), 256-byte aligned.
+static size_t part_bytes(const BpShape &sh, int P, int F) {
+    return sh.groups > 1 ? (((size_t)sh.groups * P * F * sizeof(float) + 255) / 256) * 256 : 0;
+}
+
+extern "C" size_t pat_backproject_scratch_bytes(int S, int P, int F) {
+    if (S <= 0 || P <= 0 || F <= 0) return 0;
+    BpShape sh = bp_shape(S, P, F);
+    if (sh.groups == 1) return 0;
+    return part_bytes(sh, P, F) + (size_t)sh.chunks * F * sizeof(unsigned int);
+}
+
+int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const void *sig, int sig_fmt,
+                           int sig_is_filtered, const float *frame_scale, const float *w, int S, int P, int N,
+                           int F, double t0, double dt, float *img, hipStream_t st) {
+    if (S == 0) {
+        PAT_HIP(hipMemsetAsync(img, 0, (size_t)P * F * sizeof(float), st));
+        return PAT_OK;
+    }
+    const BpShape sh = bp_shape(S, P, F);
+    float *part = nullptr;
+    unsigned int *done = nullptr;
+    if (sh.groups > 1) {
+        const size_t need = pat_backproject_scratch_bytes(S, P, F);
+        if (need > ctx->gather_scratch.bytes) {
+            int rc = ctx->gather_scratch.grow(need);
+            if (rc) return rc;
+            // completion counters start at zero and are reset by their last user
+            PAT_HIP(hipMemset(ctx->gather_scratch.ptr, 0, ctx->gather_scratch.bytes));
+        }
+        part = static_cast<float *>(ctx->gather_scratch.ptr);
+        done = reinterpret_cast<unsigned int *>(static_cast<char *>(ctx->gather_scratch.ptr) + part_bytes(sh, P, F));
+    }
+    const dim3 grid(sh.chunks, sh.groups, F);
+    const float t0dt = (float)(t0 / dt);
+    const bool filt = sig_is_filtered != 0;
+    const uint32_t *tab = static_cast<const uint32_t *>(table);
+    const bool vec4 = (P % 4 == 0) && ((uintptr_t)table % 16 == 0);
+    if (table_fmt == PAT_TABLE_F32) {
+        DelayF32 d;
+        const double inv = 1.0 / dt;
+        d.inv_hi = (float)inv;
+        d.inv_lo = (float)(inv - (double)d.inv_hi);
+        d.off = (float)(-t0 / dt);
+        d.umax = (float)(N - 1);
+        return sig_fmt == PAT_SIG_F32
+                   ? launch<DelayF32, PAT_SIG_F32>(filt, vec4, grid, tab, sig, frame_scale, w, S, P, N, sh.spg, sh.groups, d, t0dt, part, img, done, st)
+                   : launch<DelayF32, PAT_SIG_F16>(filt, vec4, grid, tab, sig, frame_scale, w, S, P, N, sh.spg, sh.groups, d, t0dt, part, img, done, st);
+    }
+    DelayQ16 d;
+    return sig_fmt == PAT_SIG_F32
+               ? launch<DelayQ16, PAT_SIG_F32>(filt, vec4, grid, tab, sig, frame_scale, w, S, P, N, sh.spg, sh.groups, d, t0dt, part, img, done, st)
+               : launch<DelayQ16, PAT_SIG_F16>(filt, vec4, grid, tab, sig, frame_scale, w, S, P, N, sh.spg, sh.groups, d, t0dt, part, img, done, st);
+}

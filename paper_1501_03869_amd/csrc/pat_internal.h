@@ -1,0 +1,48 @@
+// Internal declarations shared by the libpat translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "pat.h"
+
+// Thread-local error message + status helpers.
+int pat_fail(int code, const char *fmt, ...);
+int pat_hip_fail(hipError_t e, const char *what);
+
+#define PAT_HIP(call)                                   \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return pat_hip_fail(e_, #call); \
+    } while (0)
+
+// Growable device buffer owned by a context.
+struct pat_devbuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int grow(size_t need);  // PAT_OK or PAT_ENOMEM; contents are not preserved
+    void release();
+};
+
+struct pat_ctx {
+    int device = 0;
+    // gather partial sums
+    pat_devbuf gather_scratch;
+    // eikonal working memory
+    pat_devbuf eik_tq, eik_f, eik_flags, eik_lists, eik_seeds, eik_count;
+    uint32_t *eik_count_host = nullptr;  // pinned, 2 counters
+    pat_eikonal_stats last_eik{};
+};
+
+int pat_make_current(pat_ctx *ctx);
+
+// Launchers (stream-ordered; arguments validated by the callers).
+int pat_launch_filter(const float *p, long rows, int N, double t0, double dt, float *b, hipStream_t st);
+int pat_launch_table_to_q16(const float *T, int64_t n, double t0, double dt, int N, uint32_t *q,
+                            hipStream_t st);
+int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const void *sig, int sig_fmt,
+                           int sig_is_filtered, const float *frame_scale, const float *w, int S, int P,
+                           int N, int F, double t0, double dt, float *img, hipStream_t st);

@@ -1,0 +1,198 @@
+"""Thin Python binding of libpat (C ABI in include/pat.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+Tensors must be CUDA (HIP) tensors on the context's device, contiguous, of the
+documented dtype; the current torch stream is passed to the library unless a
+stream is given.  Importing this module does not need a GPU, but creating a
+context does, and a missing libpat.so raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpat.so")
+
+PAT_OK, PAT_EINVAL, PAT_ENOMEM, PAT_EDEVICE, PAT_EBUSY, PAT_ENOTFOUND, PAT_ETIMEOUT, PAT_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
+TABLE_F32, TABLE_Q16 = 0, 1
+SIG_F32, SIG_F16 = 0, 1
+
+EXPORTED = [
+    "pat_last_error", "pat_version", "pat_ctx_create", "pat_ctx_destroy", "pat_ctx_reserve",
+    "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_last_stats", "pat_table_to_q16",
+    "pat_tile_order", "pat_filter", "pat_backproject",
+]
+
+
+class PatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libpat error {code}: {msg}")
+        self.code = code
+
+
+class EikonalStats(C.Structure):
+    _fields_ = [("rounds", C.c_int64), ("tile_visits", C.c_int64), ("guard_hits", C.c_int64),
+                ("lsb_seconds", C.c_double), ("seconds", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libpat.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1501_03869_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dbl, sz = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_size_t
+        L.pat_last_error.restype = C.c_char_p
+        L.pat_last_error.argtypes = []
+        L.pat_version.restype = i32
+        L.pat_ctx_create.argtypes = [i32, C.POINTER(vp)]
+        L.pat_ctx_destroy.argtypes = [vp]
+        L.pat_ctx_reserve.argtypes = [vp, sz]
+        L.pat_backproject_scratch_bytes.argtypes = [i32, i32, i32]
+        L.pat_backproject_scratch_bytes.restype = sz
+        L.pat_eikonal_tables.argtypes = [vp, vp, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
+        L.pat_eikonal_last_stats.argtypes = [vp, C.POINTER(EikonalStats)]
+        L.pat_table_to_q16.argtypes = [vp, vp, i64, dbl, dbl, i32, vp, vp]
+        L.pat_tile_order.argtypes = [i32, i32, vp, i32, i32, i32, vp]
+        L.pat_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp]
+        L.pat_backproject.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp, i32, i32, i32, i32, dbl, dbl, vp, vp]
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != PAT_OK:
+        raise PatError(rc, lib().pat_last_error().decode(errors="replace"))
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _need(t, dtype, name):
+    import torch
+    if t is None:
+        return
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Context:
+    """Owns a pat_ctx on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        check(lib().pat_ctx_create(int(device), C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pat_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, nbytes: int):
+        check(lib().pat_ctx_reserve(self.h, int(nbytes)))
+
+    # ------------------------------------------------------------------ tables
+    def eikonal_tables(self, speed, h: float, sensors: np.ndarray, pix, table=None, stream=None):
+        """speed: float32 [ny][nx] device; sensors: host float64 [S][2]; pix: int32 [P] device."""
+        import torch
+        _need(speed, torch.float32, "speed")
+        _need(pix, torch.int32, "pix")
+        ny, nx = speed.shape
+        sxy = np.ascontiguousarray(sensors, dtype=np.float64)
+        S, P = sxy.shape[0], pix.shape[0]
+        if table is None:
+            table = torch.empty((S, P), dtype=torch.float32, device=speed.device)
+        _need(table, torch.float32, "table")
+        check(lib().pat_eikonal_tables(self.h, _ptr(speed), nx, ny, float(h), sxy.ctypes.data, S, _ptr(pix), P,
+                                       _ptr(table), _stream(stream)))
+        return table
+
+    def eikonal_stats(self) -> dict:
+        st = EikonalStats()
+        check(lib().pat_eikonal_last_stats(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in EikonalStats._fields_}
+
+    def table_to_q16(self, table, dt: float, N: int, t0: float = 0.0, out=None, stream=None):
+        import torch
+        _need(table, torch.float32, "table")
+        if out is None:
+            out = torch.empty(table.shape, dtype=torch.int32, device=table.device)
+        _need(out, torch.int32, "out")
+        check(lib().pat_table_to_q16(self.h, _ptr(table), table.numel(), float(t0), float(dt), int(N), _ptr(out),
+                                     _stream(stream)))
+        return out
+
+    # ------------------------------------------------------------------ frames
+    def filter(self, p, dt: float, t0: float = 0.0, out=None, stream=None):
+        import torch
+        _need(p, torch.float32, "p")
+        N = p.shape[-1]
+        rows = p.numel() // N if N else 0
+        if out is None:
+            out = torch.empty_like(p)
+        _need(out, torch.float32, "out")
+        check(lib().pat_filter(self.h, _ptr(p), rows, N, float(t0), float(dt), _ptr(out), _stream(stream)))
+        return out
+
+    def backproject(self, table, sig, dt: float, t0: float = 0.0, *, filtered: bool = True, w=None,
+                    frame_scale=None, out=None, stream=None):
+        """table: [S][P] float32 seconds or int32 (16.16 bits); sig: [S][N] or [F][S][N] float32/float16."""
+        import torch
+        S, P = table.shape
+        tfmt = TABLE_Q16 if table.dtype == torch.int32 else TABLE_F32
+        _need(table, torch.int32 if tfmt == TABLE_Q16 else torch.float32, "table")
+        single = sig.dim() == 2
+        F = 1 if single else sig.shape[0]
+        N = sig.shape[-1]
+        if sig.shape[-2] != S:
+            raise ValueError("signal and table sensor counts differ")
+        sfmt = SIG_F16 if sig.dtype == torch.float16 else SIG_F32
+        _need(sig, torch.float16 if sfmt == SIG_F16 else torch.float32, "sig")
+        _need(w, torch.float32, "w")
+        _need(frame_scale, torch.float32, "frame_scale")
+        if out is None:
+            out = torch.empty((P,) if single else (F, P), dtype=torch.float32, device=table.device)
+        _need(out, torch.float32, "out")
+        check(lib().pat_backproject(self.h, _ptr(table), tfmt, _ptr(sig), sfmt, 1 if filtered else 0,
+                                    _ptr(frame_scale), _ptr(w), S, P, N, F, float(t0), float(dt), _ptr(out),
+                                    _stream(stream)))
+        return out
+
+
+def tile_order(nx: int, ny: int, pix: np.ndarray, tile_w: int = 16, tile_h: int = 16) -> np.ndarray:
+    """Host helper: ROI node indices in tile-major order."""
+    src = np.ascontiguousarray(pix, dtype=np.int32)
+    out = np.empty_like(src)
+    check(lib().pat_tile_order(nx, ny, src.ctypes.data, src.shape[0], tile_w, tile_h, out.ctypes.data))
+    return out
+
+
+def backproject_scratch_bytes(S: int, P: int, F: int = 1) -> int:
+    return int(lib().pat_backproject_scratch_bytes(S, P, F))
