@@ -56,6 +56,61 @@ def cpu_baseline(geo, table, frames, budget_s=12.0):
                       f"{el:.1f} s"}
 
 
+def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
+    """Reduced-precision and batched variants on the same geometry and frames."""
+    import torch
+    S, P, N = geo.S, geo.P, geo.n_samples
+    dev = table.device
+    q16 = ctx.table_to_q16(table, geo.dt, N, geo.t0)
+    R = len(frames_h)
+    p = np.stack(frames_h).astype(np.float32)
+    scale = (np.abs(p).reshape(R, -1).max(1) / 2.0 ** 14).astype(np.float32)
+    half = torch.from_numpy((p / scale[:, None, None]).astype(np.float16)).to(dev)
+    scale_d = torch.from_numpy(scale).to(dev)
+    img = torch.empty((R, P), dtype=torch.float32, device=dev)
+    res = {}
+
+    def single(name, tab, sig, sc):
+        def fn(i):
+            r = i % R
+            ctx.backproject(tab, sig[r], geo.dt, geo.t0, filtered=False, frame_scale=None if sc is None else sc[r:r + 1],
+                            out=img[r], stream=stream)
+        wall, ms = timed(fn, args.steps, args.warmup)
+        res[name] = {"frames_per_launch": 1, "gathers_per_s": args.steps * S * P / wall,
+                     "frames_per_s": args.steps / wall, "device_ms_p50": percentile(ms, 50),
+                     "device_ms_p99": percentile(ms, 99)}
+
+    single("v0_f32_table_f32_signal", table, frames, None)
+    single("v1_q16_table_f32_signal", q16, frames, None)
+    single("v2_f32_table_f16_signal", table, half, scale_d)
+    single("v3_q16_table_f16_signal", q16, half, scale_d)
+
+    # batched: F frames per launch, table read once; replayed from a HIP graph
+    F = 64
+    idx = np.arange(F) % R
+    sigs = {"f32": frames[torch.from_numpy(idx).to(dev)].contiguous(), "f16": half[torch.from_numpy(idx).to(dev)].contiguous()}
+    scl = scale_d[torch.from_numpy(idx).to(dev)].contiguous()
+    outF = torch.empty((F, P), dtype=torch.float32, device=dev)
+    for name, tab, sk in (("batch64_v0_f32", table, "f32"), ("batch64_v3_q16_f16", q16, "f16")):
+        sig = sigs[sk]
+        sc = scl if sk == "f16" else None
+        ctx.reserve(S, P, F)
+        g = torch.cuda.CUDAGraph()
+        s2 = torch.cuda.Stream()
+        s2.wait_stream(stream)
+        with torch.cuda.stream(s2):
+            ctx.backproject(tab, sig, geo.dt, geo.t0, filtered=False, frame_scale=sc, out=outF, stream=s2)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            ctx.backproject(tab, sig, geo.dt, geo.t0, filtered=False, frame_scale=sc, out=outF)
+        steps = max(20, args.steps // 8)
+        wall, ms = timed(lambda i: g.replay(), steps, 5)
+        res[name] = {"frames_per_launch": F, "gathers_per_s": steps * F * S * P / wall,
+                     "frames_per_s": steps * F / wall, "device_ms_p50": percentile(ms, 50),
+                     "device_ms_p99": percentile(ms, 99), "hip_graph": True}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +140,8 @@ def main():
     print(f"[bench] {geo.name}: grid {geo.nx}x{geo.ny} S={geo.S} P={geo.P} N={geo.n_samples}", file=sys.stderr,
           flush=True)
 
+    # ROI in 32x32-tile, Z-order-inside order: compact pixel blocks for the gather
+    geo.pix = pat.tile_order(geo.nx, geo.ny, geo.pix, 32, 32)
     speed = torch.from_numpy(geo.speed).to(dev)
     pix = torch.from_numpy(geo.pix).to(dev)
     torch.cuda.synchronize()
@@ -101,31 +158,27 @@ def main():
     img = torch.empty((args.frames, geo.P), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
 
+    def timed(fn, steps, warmup):
+        """Run fn(i) warmup + steps times on the current stream; per-call device
+        times from HIP events on that stream, wall time of the timed steps."""
+        for i in range(warmup):
+            fn(i)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ev[i][0].record(stream)
+            fn(i)
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, [a.elapsed_time(b) for a, b in ev]
+
     def step(i):
         r = i % args.frames
         ctx.backproject(table, frames[r], geo.dt, geo.t0, filtered=False, out=img[r], stream=stream)
 
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ev[i][0].record(stream)
-        step(i)
-        ev[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    dev_ms = [a.elapsed_time(b) for a, b in ev]
-
-    S, P, N = geo.S, geo.P, geo.n_samples
-    gathers = args.steps * S * P
-    value = gathers / wall
-    bytes_per_frame = 4 * S * P + 4 * S * N + 4 * P
-    avg_kernel_s = float(np.mean(dev_ms)) * 1e-3
-    achieved = bytes_per_frame / avg_kernel_s / 1e9
-
+    wall, dev_ms = timed(step, args.steps, args.warmup)
     # end-to-end latency: host frame -> H2D -> back projection -> D2H image
     pinned_in = [torch.from_numpy(f).pin_memory() for f in frames_h[:4]]
     pinned_out = torch.empty((P,), dtype=torch.float32).pin_memory()
@@ -170,6 +223,8 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_per_frame},
         "paper_context": "123.79 ms for 512 sensors x 21323 pixels on an NVIDIA Tesla C2075, transfers included",
     }
+    if args.variants:
+        out["variants"] = run_variants(ctx, geo, table, frames, frames_h, stream, timed, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(geo, table_h, frames_h)
     print(json.dumps(out), flush=True)

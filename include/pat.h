@@ -83,11 +83,14 @@ int pat_version(void);
 int pat_ctx_create(int device, pat_ctx **out);
 int pat_ctx_destroy(pat_ctx *ctx);
 
-/* Grow the context's gather scratch to at least `bytes` now, so that later
- * pat_backproject calls allocate nothing (e.g. inside HIP graph capture). */
-int pat_ctx_reserve(pat_ctx *ctx, size_t bytes);
+/* Allocate the context's gather scratch for pat_backproject calls of S
+ * sensors, P pixels and F frames now, so that later calls of these sizes
+ * allocate nothing (for example inside HIP graph capture).  Synchronous. */
+int pat_ctx_reserve(pat_ctx *ctx, int S, int P, int F);
 
-/* Bytes of context scratch pat_backproject needs for these sizes. */
+/* Bytes of partial-sum scratch pat_backproject needs for these sizes (0 when
+ * one workgroup per pixel block covers all sensors); a small zeroed buffer of
+ * completion counters comes on top.  Host-only, no GPU needed. */
 size_t pat_backproject_scratch_bytes(int S, int P, int F);
 
 /*
@@ -134,10 +137,11 @@ int pat_table_to_q16(pat_ctx *ctx, const float *d_table, int64_t n, double t0, d
                      uint32_t *d_q, void *stream);
 
 /*
- * Host helper: stable reorder of ROI node indices into tile-major order
- * (tiles of tile_w x tile_h nodes, tiles row-major, nodes row-major inside a
- * tile), which gives the gather's pixel blocks compact footprints.
- * h_pix_out may not alias h_pix.
+ * Host helper: reorder ROI node indices tile-major (tiles of tile_w x tile_h
+ * nodes, tiles row-major, Z-order (Morton) inside a tile), so that every
+ * aligned run of 64, 256 or 1024 pixels of a 32x32-tiled ROI is a compact
+ * square or 2:1 patch: the gather's pixel blocks then need short time
+ * windows.  Stable for equal keys; h_pix_out may not alias h_pix.  Host only.
  */
 int pat_tile_order(int nx, int ny, const int32_t *h_pix, int P, int tile_w, int tile_h,
                    int32_t *h_pix_out);
@@ -167,7 +171,10 @@ int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, doubl
  *   d_img     float32 [F][P] output.
  * Accumulation is FP32 in a fixed order, so results are bitwise reproducible
  * for fixed inputs and sizes.  Uses context scratch of
- * pat_backproject_scratch_bytes(S, P, F) bytes (allocated on first need).
+ * pat_backproject_scratch_bytes(S, P, F) bytes (allocated on first need, or
+ * up front by pat_ctx_reserve).  When F >= 2, N is a multiple of 8 (FP16) or
+ * 4 (FP32) and d_sig is 16-byte aligned, one launch reads the table once for
+ * all frames; otherwise each frame is gathered as a single frame.
  */
 int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,

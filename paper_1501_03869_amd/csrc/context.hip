@@ -79,6 +79,7 @@ extern "C" int pat_ctx_destroy(pat_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     ctx->gather_scratch.release();
+    ctx->gather_done.release();
     ctx->eik_tq.release();
     ctx->eik_f.release();
     ctx->eik_flags.release();
@@ -90,10 +91,14 @@ extern "C" int pat_ctx_destroy(pat_ctx *ctx) {
     return PAT_OK;
 }
 
-extern "C" int pat_ctx_reserve(pat_ctx *ctx, size_t bytes) {
+extern "C" int pat_ctx_reserve(pat_ctx *ctx, int S, int P, int F) {
     int rc = pat_make_current(ctx);
     if (rc) return rc;
-    return ctx->gather_scratch.grow(bytes);
+    if (S < 0 || P < 0 || F < 0) return pat_fail(PAT_EINVAL, "negative size");
+    if (S == 0 || P == 0 || F == 0) return PAT_OK;
+    float *part;
+    unsigned int *done;
+    return pat_gather_scratch(ctx, P, F, pat_backproject_scratch_bytes(S, P, F), &part, &done);
 }
 
 extern "C" int pat_eikonal_last_stats(pat_ctx *ctx, pat_eikonal_stats *out) {
@@ -102,25 +107,34 @@ extern "C" int pat_eikonal_last_stats(pat_ctx *ctx, pat_eikonal_stats *out) {
     return PAT_OK;
 }
 
+// Morton (Z-order) index of local tile coordinates: interleaved bits of i and j.
+static uint64_t morton2(uint32_t i, uint32_t j) {
+    uint64_t r = 0;
+    for (int b = 0; b < 16; ++b) {
+        r |= (uint64_t)((i >> b) & 1u) << (2 * b);
+        r |= (uint64_t)((j >> b) & 1u) << (2 * b + 1);
+    }
+    return r;
+}
+
 extern "C" int pat_tile_order(int nx, int ny, const int32_t *h_pix, int P, int tile_w, int tile_h,
                               int32_t *h_pix_out) {
-    if (nx < 1 || ny < 1 || P < 0 || tile_w < 1 || tile_h < 1)
+    if (nx < 1 || ny < 1 || P < 0 || tile_w < 1 || tile_h < 1 || tile_w > 65536 || tile_h > 65536)
         return pat_fail(PAT_EINVAL, "bad sizes nx=%d ny=%d P=%d tile=%dx%d", nx, ny, P, tile_w, tile_h);
     if (P > 0 && (!h_pix || !h_pix_out)) return pat_fail(PAT_EINVAL, "null pixel array");
     if (P > 0 && h_pix == h_pix_out) return pat_fail(PAT_EINVAL, "h_pix_out aliases h_pix");
     const long n = (long)nx * ny;
     const int tx = (nx + tile_w - 1) / tile_w;
-    std::vector<std::pair<int64_t, int32_t>> key((size_t)P);
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)P);
     for (int p = 0; p < P; ++p) {
         int32_t k = h_pix[p];
         if (k < 0 || k >= n) return pat_fail(PAT_EINVAL, "pixel %d index %d out of range", p, k);
         int i = k % nx, j = k / nx;
-        int64_t tile = (int64_t)(j / tile_h) * tx + (i / tile_w);
-        int64_t in = (int64_t)(j % tile_h) * tile_w + (i % tile_w);
-        key[(size_t)p] = { tile * ((int64_t)tile_w * tile_h) + in, k };
+        uint64_t tile = (uint64_t)(j / tile_h) * tx + (i / tile_w);
+        key[(size_t)p] = { (tile << 32) | morton2((uint32_t)(i % tile_w), (uint32_t)(j % tile_h)), k };
     }
     std::stable_sort(key.begin(), key.end(),
-                     [](const std::pair<int64_t, int32_t> &a, const std::pair<int64_t, int32_t> &b) {
+                     [](const std::pair<uint64_t, int32_t> &a, const std::pair<uint64_t, int32_t> &b) {
                          return a.first < b.first;
                      });
     for (int p = 0; p < P; ++p) h_pix_out[p] = key[(size_t)p].second;

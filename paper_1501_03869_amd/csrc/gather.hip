@@ -22,9 +22,12 @@
 
 #include <algorithm>
 
+#include "gather_common.h"
 #include "pat_internal.h"
 
 namespace {
+
+using namespace pat_gather;
 
 constexpr int BP_THREADS = 256;
 constexpr int BP_PPT = 4;                          // pixels per thread
@@ -52,63 +55,6 @@ BpShape bp_shape(int S, int P, int F) {
     s.spg = spg;
     s.groups = (S1 + spg - 1) / spg;
     return s;
-}
-
-struct DelayF32 {
-    float inv_hi, inv_lo, off;  // u = T * (inv_hi + inv_lo) + off
-    float umax;                 // N - 1
-    __device__ __forceinline__ bool decode(float T, int N, int &n, float &a) const {
-        const float u = fmaf(T, inv_hi, fmaf(T, inv_lo, off));
-        if (!(u >= 0.0f && u <= umax)) return false;  // also rejects NaN and inf
-        n = min((int)u, N - 2);
-        a = u - (float)n;
-        return true;
-    }
-    __device__ __forceinline__ bool decode(uint32_t bits, int N, int &n, float &a) const {
-        return decode(__uint_as_float(bits), N, n, a);
-    }
-};
-
-struct DelayQ16 {
-    __device__ __forceinline__ bool decode(uint32_t q, int N, int &n, float &a) const {
-        if (q == 0xFFFFFFFFu) return false;
-        n = (int)(q >> 16);
-        a = (float)(q & 0xFFFFu) * (1.0f / 65536.0f);
-        if (n > N - 2) {  // only u = N-1 exactly: end of the last interval
-            n = N - 2;
-            a = 1.0f;
-        }
-        return true;
-    }
-};
-
-template <int SFMT>
-__device__ __forceinline__ float load_sig(const void *sig, long i, float scale) {
-    if constexpr (SFMT == PAT_SIG_F32) {
-        return static_cast<const float *>(sig)[i];
-    } else {
-        return __half2float(static_cast<const __half *>(sig)[i]) * scale;
-    }
-}
-
-// b[n] = p[n] - (n + t0/dt) * 0.5 * (p[n+1] - p[n-1]); one-sided at both ends.
-__device__ __forceinline__ float ubp(float pm, float p0, float pp, int n, int N, float t0dt) {
-    float d = pp - pm;
-    if (n == 0) d = 2.0f * (pp - p0);
-    if (n == N - 1) d = 2.0f * (p0 - pm);
-    return p0 - ((float)n + t0dt) * (0.5f * d);
-}
-
-template <int SFMT, bool FILTERED>
-__device__ __forceinline__ float sample_b(const void *sig, long row, int n, int N, float sc, float t0dt) {
-    if constexpr (FILTERED) {
-        return load_sig<SFMT>(sig, row + n, sc);
-    } else {
-        const float pm = load_sig<SFMT>(sig, row + max(n - 1, 0), sc);
-        const float p0 = load_sig<SFMT>(sig, row + n, sc);
-        const float pp = load_sig<SFMT>(sig, row + min(n + 1, N - 1), sc);
-        return ubp(pm, p0, pp, n, N, t0dt);
-    }
 }
 
 template <bool VEC4>
@@ -278,17 +224,37 @@ int launch(bool filtered, bool vec4, dim3 grid, const uint32_t *tab, const void 
 
 }  // namespace
 
-// Scratch: partial sums [F][G][P] followed by one completion counter per
-// (frame, chunk), 256-byte aligned.
-static size_t part_bytes(const BpShape &sh, int P, int F) {
-    return sh.groups > 1 ? (((size_t)sh.groups * P * F * sizeof(float) + 255) / 256) * 256 : 0;
+// Gather scratch: the partial sums live in the context's gather buffer; the
+// completion counters (at most ceil(P/256) * F for either kernel) live in a
+// buffer of their own that is zeroed when it is (re)allocated and that every
+// launch leaves at zero, so no call can see another call's partial sums as
+// counters whatever the sizes of successive calls.
+size_t pat_gather_counter_bytes(int P, int F) {
+    return ((((size_t)(P + 255) / 256) * (size_t)F * sizeof(unsigned int) + 255) / 256) * 256;
+}
+
+int pat_gather_scratch(pat_ctx *ctx, int P, int F, size_t part_bytes, float **part, unsigned int **done) {
+    const size_t cb = pat_gather_counter_bytes(P, F);
+    if (cb > ctx->gather_done.bytes) {
+        int rc = ctx->gather_done.grow(cb);
+        if (rc) return rc;
+        PAT_HIP(hipMemset(ctx->gather_done.ptr, 0, ctx->gather_done.bytes));
+    }
+    int rc = ctx->gather_scratch.grow(part_bytes);
+    if (rc) return rc;
+    *done = static_cast<unsigned int *>(ctx->gather_done.ptr);
+    *part = static_cast<float *>(ctx->gather_scratch.ptr);
+    return PAT_OK;
+}
+
+static size_t single_part_bytes(int S, int P, int F) {
+    const BpShape sh = bp_shape(S, P, F);
+    return sh.groups > 1 ? (size_t)sh.groups * P * F * sizeof(float) : 0;
 }
 
 extern "C" size_t pat_backproject_scratch_bytes(int S, int P, int F) {
     if (S <= 0 || P <= 0 || F <= 0) return 0;
-    BpShape sh = bp_shape(S, P, F);
-    if (sh.groups == 1) return 0;
-    return part_bytes(sh, P, F) + (size_t)sh.chunks * F * sizeof(unsigned int);
+    return std::max(single_part_bytes(S, P, F), pat_batch_part_bytes(S, P, F));
 }
 
 int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const void *sig, int sig_fmt,
@@ -298,19 +264,15 @@ int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const
         PAT_HIP(hipMemsetAsync(img, 0, (size_t)P * F * sizeof(float), st));
         return PAT_OK;
     }
+    if (pat_batch_eligible(sig_fmt, N, F, sig))
+        return pat_launch_backproject_batch(ctx, table, table_fmt, sig, sig_fmt, sig_is_filtered, frame_scale, w, S, P,
+                                            N, F, t0, dt, img, st);
     const BpShape sh = bp_shape(S, P, F);
     float *part = nullptr;
     unsigned int *done = nullptr;
     if (sh.groups > 1) {
-        const size_t need = pat_backproject_scratch_bytes(S, P, F);
-        if (need > ctx->gather_scratch.bytes) {
-            int rc = ctx->gather_scratch.grow(need);
-            if (rc) return rc;
-            // completion counters start at zero and are reset by their last user
-            PAT_HIP(hipMemset(ctx->gather_scratch.ptr, 0, ctx->gather_scratch.bytes));
-        }
-        part = static_cast<float *>(ctx->gather_scratch.ptr);
-        done = reinterpret_cast<unsigned int *>(static_cast<char *>(ctx->gather_scratch.ptr) + part_bytes(sh, P, F));
+        int rc = pat_gather_scratch(ctx, P, F, single_part_bytes(S, P, F), &part, &done);
+        if (rc) return rc;
     }
     const dim3 grid(sh.chunks, sh.groups, F);
     const float t0dt = (float)(t0 / dt);

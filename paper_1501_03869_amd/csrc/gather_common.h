@@ -1,0 +1,71 @@
+// Device helpers shared by the back-projection kernels: delay decoding for
+// both table formats, signal loads for both sample formats, and the UBP
+// filter on three neighbouring samples.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include "pat.h"
+
+namespace pat_gather {
+
+struct DelayF32 {
+    float inv_hi, inv_lo, off;  // u = T * (inv_hi + inv_lo) + off
+    float umax;                 // N - 1
+    __device__ __forceinline__ bool decode(float T, int N, int &n, float &a) const {
+        const float u = fmaf(T, inv_hi, fmaf(T, inv_lo, off));
+        if (!(u >= 0.0f && u <= umax)) return false;  // also rejects NaN and inf
+        n = min((int)u, N - 2);
+        a = u - (float)n;
+        return true;
+    }
+    __device__ __forceinline__ bool decode(uint32_t bits, int N, int &n, float &a) const {
+        return decode(__uint_as_float(bits), N, n, a);
+    }
+};
+
+struct DelayQ16 {
+    __device__ __forceinline__ bool decode(uint32_t q, int N, int &n, float &a) const {
+        if (q == 0xFFFFFFFFu) return false;
+        n = (int)(q >> 16);
+        a = (float)(q & 0xFFFFu) * (1.0f / 65536.0f);
+        if (n > N - 2) {  // only u = N-1 exactly: end of the last interval
+            n = N - 2;
+            a = 1.0f;
+        }
+        return true;
+    }
+};
+
+template <int SFMT>
+__device__ __forceinline__ float load_sig(const void *sig, long i, float scale) {
+    if constexpr (SFMT == PAT_SIG_F32) {
+        return static_cast<const float *>(sig)[i];
+    } else {
+        return __half2float(static_cast<const __half *>(sig)[i]) * scale;
+    }
+}
+
+// b[n] = p[n] - (n + t0/dt) * 0.5 * (p[n+1] - p[n-1]); one-sided at both ends.
+__device__ __forceinline__ float ubp(float pm, float p0, float pp, int n, int N, float t0dt) {
+    float d = pp - pm;
+    if (n == 0) d = 2.0f * (pp - p0);
+    if (n == N - 1) d = 2.0f * (p0 - pm);
+    return p0 - ((float)n + t0dt) * (0.5f * d);
+}
+
+template <int SFMT, bool FILTERED>
+__device__ __forceinline__ float sample_b(const void *sig, long row, int n, int N, float sc, float t0dt) {
+    if constexpr (FILTERED) {
+        return load_sig<SFMT>(sig, row + n, sc);
+    } else {
+        const float pm = load_sig<SFMT>(sig, row + max(n - 1, 0), sc);
+        const float p0 = load_sig<SFMT>(sig, row + n, sc);
+        const float pp = load_sig<SFMT>(sig, row + min(n + 1, N - 1), sc);
+        return ubp(pm, p0, pp, n, N, t0dt);
+    }
+}
+
+
+}  // namespace pat_gather

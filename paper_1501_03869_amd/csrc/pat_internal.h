@@ -31,6 +31,8 @@ struct pat_ctx {
     int device = 0;
     // gather partial sums
     pat_devbuf gather_scratch;
+    // gather completion counters (kept at zero between launches)
+    pat_devbuf gather_done;
     // eikonal working memory
     pat_devbuf eik_tq, eik_f, eik_flags, eik_lists, eik_seeds, eik_count;
     uint32_t *eik_count_host = nullptr;  // pinned, 2 counters
@@ -43,6 +45,14 @@ int pat_make_current(pat_ctx *ctx);
 int pat_launch_filter(const float *p, long rows, int N, double t0, double dt, float *b, hipStream_t st);
 int pat_launch_table_to_q16(const float *T, int64_t n, double t0, double dt, int N, uint32_t *q,
                             hipStream_t st);
+// Gather scratch shared by the single-frame and batched kernels.
+size_t pat_gather_counter_bytes(int P, int F);
+int pat_gather_scratch(pat_ctx *ctx, int P, int F, size_t part_bytes, float **part, unsigned int **done);
+size_t pat_batch_part_bytes(int S, int P, int F);
+bool pat_batch_eligible(int sig_fmt, int N, int F, const void *sig);
+int pat_launch_backproject_batch(pat_ctx *ctx, const void *table, int table_fmt, const void *sig, int sig_fmt,
+                                 int sig_is_filtered, const float *frame_scale, const float *w, int S, int P, int N,
+                                 int F, double t0, double dt, float *img, hipStream_t st);
 int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const void *sig, int sig_fmt,
                            int sig_is_filtered, const float *frame_scale, const float *w, int S, int P,
                            int N, int F, double t0, double dt, float *img, hipStream_t st);

@@ -54,7 +54,7 @@ def lib() -> C.CDLL:
         L.pat_version.restype = i32
         L.pat_ctx_create.argtypes = [i32, C.POINTER(vp)]
         L.pat_ctx_destroy.argtypes = [vp]
-        L.pat_ctx_reserve.argtypes = [vp, sz]
+        L.pat_ctx_reserve.argtypes = [vp, i32, i32, i32]
         L.pat_backproject_scratch_bytes.argtypes = [i32, i32, i32]
         L.pat_backproject_scratch_bytes.restype = sz
         L.pat_eikonal_tables.argtypes = [vp, vp, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
@@ -115,8 +115,9 @@ class Context:
         except Exception:
             pass
 
-    def reserve(self, nbytes: int):
-        check(lib().pat_ctx_reserve(self.h, int(nbytes)))
+    def reserve(self, S: int, P: int, F: int = 1):
+        """Pre-allocate gather scratch for calls of these sizes (graph capture)."""
+        check(lib().pat_ctx_reserve(self.h, int(S), int(P), int(F)))
 
     # ------------------------------------------------------------------ tables
     def eikonal_tables(self, speed, h: float, sensors: np.ndarray, pix, table=None, stream=None):

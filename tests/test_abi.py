@@ -43,6 +43,13 @@ def test_null_context_is_rejected_without_gpu():
     assert L.pat_ctx_create(0, None) == pat.PAT_EINVAL
 
 
+def _morton(i, j):
+    r = 0
+    for b in range(16):
+        r |= ((i >> b) & 1) << (2 * b) | ((j >> b) & 1) << (2 * b + 1)
+    return r
+
+
 def test_tile_order_host_helper():
     nx, ny = 37, 29
     rng = np.random.default_rng(0)
@@ -50,8 +57,15 @@ def test_tile_order_host_helper():
     out = pat.tile_order(nx, ny, pix, 8, 4)
     assert sorted(out.tolist()) == sorted(pix.tolist())
     i, j = out % nx, out // nx
-    key = ((j // 4) * ((nx + 7) // 8) + i // 8) * 32 + (j % 4) * 8 + (i % 8)
-    assert np.all(np.diff(key) > 0)
+    key = [(((jj // 4) * ((nx + 7) // 8) + ii // 8) << 32) | _morton(ii % 8, jj % 4)
+           for ii, jj in zip(i.tolist(), j.tolist())]
+    assert all(a < b for a, b in zip(key, key[1:]))
+    # a full 32x32 tile: every aligned run of 256 pixels is a 16x16 square
+    full = np.arange(64 * 64, dtype=np.int32)
+    o = pat.tile_order(64, 64, full, 32, 32)
+    for r in range(0, 1024, 256):
+        blk = o[r:r + 256]
+        assert np.ptp(blk % 64) == 15 and np.ptp(blk // 64) == 15
     with pytest.raises(pat.PatError):
         pat.tile_order(nx, ny, np.array([nx * ny], np.int32), 8, 4)
 

@@ -246,3 +246,113 @@ def test_small_end_to_end(ctx, orc):
     err = rel_l2(got, ref)
     print(f"[e2e] small rel L2 {err:.3e}", flush=True)
     assert err <= 2e-3
+
+
+# ----------------------------------------------------------------------------- batched frames
+
+def _fp16_frames(p):
+    """Per-frame scale max|p|/2^14 and the binary16 codes, plus their exact values."""
+    F = p.shape[0]
+    scale = (np.abs(p).reshape(F, -1).max(1) / 2.0 ** 14).astype(np.float32)
+    scale[scale == 0] = 1.0
+    h = (p / scale[:, None, None]).astype(np.float16)
+    return scale, h, h.astype(np.float64) * scale.astype(np.float64)[:, None, None]
+
+
+@pytest.mark.parametrize("F,sig,filtered,q16", [(20, "f32", False, False), (3, "f16", True, False),
+                                                (17, "f32", True, True), (33, "f16", False, True)])
+def test_backproject_batched_matches_oracle(ctx, orc, F, sig, filtered, q16):
+    # one launch for all frames; real (compact) delays from the small geometry
+    # exercise the LDS windows, a random table exercises the global fallback
+    geo = inputs.config("small")
+    Tg = oracle_table(orc, geo).astype(np.float32)
+    for T in (Tg[:, :5000], inputs.random_table(12, geo.S, 3001, geo.n_samples, geo.dt, frac_out=0.05)):
+        S, P = T.shape
+        p = inputs.random_signals(13, S, geo.n_samples, F)
+        w = np.random.default_rng(14).uniform(0.5, 1.5, S).astype(np.float32)
+        tab = ctx.table_to_q16(dev(T), geo.dt, geo.n_samples) if q16 else dev(T)
+        if sig == "f16":
+            scale, h, vals = _fp16_frames(p)
+            got = ctx.backproject(tab, dev(h), geo.dt, filtered=filtered, w=dev(w), frame_scale=dev(scale))
+        else:
+            vals = p.astype(np.float64)
+            got = ctx.backproject(tab, dev(p), geo.dt, filtered=filtered, w=dev(w))
+        got = got.cpu().numpy()
+        b = vals if filtered else orc.filt(vals, geo.dt)
+        if q16:
+            ref = orc.gather_q16(tab.cpu().numpy().view(np.uint32), b, w.astype(np.float64))
+        else:
+            ref = orc.gather(T.astype(np.float64), b, geo.dt, 0.0, w.astype(np.float64))
+        err = rel_l2(got, ref)
+        print(f"[batch] F={F} {sig} filtered={filtered} q16={q16} P={P} rel L2 {err:.3e}", flush=True)
+        assert err <= IMG_TOL
+
+
+def _v3_error_bound(q, T64, p, scale, dt, w):
+    """A-priori per-pixel bound of |img_V3 - img_FP64| for one frame: 16.16
+    delays, binary16 samples with a per-frame scale, FP32 arithmetic.
+    q: uint32 [S][P]; T64: the FP64 delays; p: FP64 raw samples [S][N]."""
+    S, N = p.shape
+    u = T64 / dt
+    valid = np.isfinite(u) & (u >= 0) & (u <= N - 1)
+    uq = np.where(valid, u, 0.0)
+    n = np.minimum(np.floor(uq).astype(np.int64), N - 2)
+    b = np.empty_like(p)
+    b[:, 1:-1] = p[:, 1:-1] - np.arange(1, N - 1) * 0.5 * (p[:, 2:] - p[:, :-2])
+    b[:, 0] = p[:, 0]
+    b[:, -1] = p[:, -1] - (N - 1) * (p[:, -1] - p[:, -2])
+    rows = np.arange(S)[:, None]
+    # binary16 rounding of p (relative 2^-11, absolute 2^-25 * scale below the normal range)
+    dp = 2.0 ** -11 * np.abs(p) + 2.0 ** -25 * scale
+    tn = np.arange(N, dtype=np.float64)
+    db = dp + 0.5 * tn * (np.roll(dp, -1, 1) + np.roll(dp, 1, 1))
+    db[:, 0] = dp[:, 0] + 0.0 * (dp[:, 1] + dp[:, 0])
+    db[:, -1] = dp[:, -1] + (N - 1) * (dp[:, -1] + dp[:, -2])
+    slope = np.abs(b[:, 1:] - b[:, :-1])
+    slope = np.maximum(slope, np.concatenate([slope[:, 1:], slope[:, -1:]], 1))
+    term = 2.0 ** -17 * slope[rows, n] + np.maximum(db[rows, n], db[rows, n + 1])
+    # magnitude of the FP32 terms: coefficients ~ n/2 on four raw taps
+    taps = np.abs(p[rows, np.maximum(n - 1, 0)]) + np.abs(p[rows, n]) + np.abs(p[rows, n + 1]) + \
+        np.abs(p[rows, np.minimum(n + 2, N - 1)])
+    mag = (1.0 + 0.5 * (n + 1)) * taps
+    wv = np.abs(w)[:, None] * valid
+    arith = 2.0 ** -24 * (S + 8) * (wv * mag).sum(0)
+    return (wv * term).sum(0) + arith
+
+
+def test_batched_v3_within_bound(ctx, orc):
+    # the batched-frames workload: paper-scale geometry, one resident table,
+    # frames with their own phantom and 20 dB noise, FP16 signals and a 16.16
+    # table, one fused launch; every pixel of every checked frame must lie
+    # within the a-priori bound of the FP64 oracle on the unquantised inputs.
+    geo = inputs.config("paper")
+    T64 = oracle_table(orc, geo)
+    T32 = T64.astype(np.float32)
+    F = 16
+    p = np.stack([inputs.frame_for(geo, T64, f, noise_snr_db=20.0) for f in range(F)])
+    scale, h, _ = _fp16_frames(p)
+    q = ctx.table_to_q16(dev(T32), geo.dt, geo.n_samples)
+    got = ctx.backproject(q, dev(h), geo.dt, filtered=False, frame_scale=dev(scale)).cpu().numpy()
+    w = np.ones(geo.S)
+    for f in (0, 7, 15):
+        ref = orc.backproject(T32.astype(np.float64), p[f], geo.dt)
+        bound = _v3_error_bound(q.cpu().numpy().view(np.uint32), T32.astype(np.float64), p[f].astype(np.float64),
+                                float(scale[f]), geo.dt, w)
+        err = np.abs(got[f] - ref)
+        print(f"[v3] frame {f}: rel L2 {rel_l2(got[f], ref):.3e}, bound rel L2 "
+              f"{np.linalg.norm(bound) / np.linalg.norm(ref):.3e}, max err/bound {(err / bound).max():.3f}", flush=True)
+        assert np.all(err <= bound)
+    # plain FP32 batched on the same frames stays within the FP32 target
+    got0 = ctx.backproject(dev(T32), dev(p.astype(np.float32)), geo.dt, filtered=False).cpu().numpy()
+    for f in (0, 15):
+        ref = orc.backproject(T32.astype(np.float64), p[f], geo.dt)
+        assert rel_l2(got0[f], ref) <= IMG_TOL
+
+
+def test_scratch_reuse_across_shapes(ctx, orc):
+    # successive calls whose scratch layouts differ (more or fewer sensor
+    # groups, frames, pixel blocks) must each be right
+    cases = [(130, 777, 2048, 1), (64, 4099, 1024, 2), (512, 5000, 256, 1), (9, 300, 64, 40), (130, 777, 2048, 1)]
+    for k, (S, P, N, F) in enumerate(cases):
+        got, ref = _gather_case(ctx, orc, S, P, N, F, 0.05, seed=40 + k)
+        assert rel_l2(got, ref) <= IMG_TOL, (S, P, N, F)
