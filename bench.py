@@ -111,6 +111,131 @@ def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
     return res
 
 
+def run_serving(ctx, seconds, variant, rate_hz=200.0, new_map_every_s=2.0):
+    """Serving mix: Poisson frame stream over three resident speed maps (128^2
+    with 128 sensors, 256^2 with 512, 512^2 with 512) plus a new paper-scale
+    speed map every few seconds that triggers a table build; then a saturation
+    burst with all slots busy.  Returns the server's statistics."""
+    import threading
+    import torch
+    from paper_1501_03869_amd import inputs, pat
+    dev = torch.device("cuda:0")
+    geos = [inputs.config("serve_a"), inputs.config("paper"), inputs.config("serve_c")]
+    for g in geos:
+        g.pix = pat.tile_order(g.nx, g.ny, g.pix, 32, 32)
+    frames = []
+    for g in geos:
+        T = ctx.eikonal_tables(torch.from_numpy(g.speed).to(dev), g.h, g.sensors,
+                               torch.from_numpy(g.pix).to(dev)).cpu().numpy()
+        fr = [inputs.frame_for(g, T, 100 + k, noise_snr_db=20.0) for k in range(2)]
+        frames.append(fr)
+    q16 = variant == "v3"
+    srv = pat.Server(ctx, table_fmt=pat.TABLE_Q16 if q16 else pat.TABLE_F32,
+                     sig_fmt=pat.SIG_F16 if q16 else pat.SIG_F32, max_batch=64, max_inflight=3, max_slots=512)
+
+    def enc(p):
+        if not q16:
+            return p, 1.0
+        sc = float(np.abs(p).max() / 2.0 ** 14)
+        return (p / sc).astype(np.float16), sc
+
+    encoded = [[enc(p) for p in fr] for fr in frames]
+    ids = [srv.add_map(g.speed, g.h, g.sensors, g.pix, g.n_samples, g.dt, g.t0) for g in geos]
+    t_wait = time.perf_counter()
+    while any(srv.map_state(i) != pat.MAP_READY for i in ids):
+        if time.perf_counter() - t_wait > 120:
+            raise RuntimeError("maps not ready")
+        time.sleep(0.01)
+    build_s = time.perf_counter() - t_wait
+    kinds = {i: k for k, i in enumerate(ids)}  # map id -> frame set
+    P_of = {i: geos[k].P for k, i in enumerate(ids)}
+    rng = np.random.default_rng(inputs.SEED_ARRIVALS)
+    arrivals = inputs.poisson_arrivals(rate_hz, seconds)
+    q = []
+    lock = threading.Lock()
+    done = threading.Event()
+    errors = []
+
+    def collector():
+        while True:
+            with lock:
+                item = q.pop(0) if q else None
+            if item is None:
+                if done.is_set():
+                    return
+                time.sleep(0.0002)
+                continue
+            try:
+                srv.wait(item[0], P=item[1], timeout_ms=60000)
+            except Exception as e:  # noqa: BLE001
+                errors.append(repr(e))
+
+    th = threading.Thread(target=collector)
+    th.start()
+    srv.reset_stats()
+    t0 = time.perf_counter()
+    next_map_t = new_map_every_s
+    seed = 5000
+    new_ids = []
+    for a in arrivals:
+        while True:
+            now = time.perf_counter() - t0
+            if now >= next_map_t:
+                g = geos[1]
+                sp = inputs.paper_like_speed(seed, g.nx, g.ny, g.h)
+                seed += 1
+                try:
+                    mid = srv.add_map(sp, g.h, g.sensors, g.pix, g.n_samples, g.dt, g.t0)
+                    kinds[mid] = 1
+                    P_of[mid] = g.P
+                    new_ids.append(mid)
+                except pat.PatError:
+                    pass
+                next_map_t += new_map_every_s
+            if now >= a:
+                break
+            time.sleep(min(a - now, 0.0005))
+        ready = [i for i in kinds if srv.map_state(i) == pat.MAP_READY]
+        mid = ready[int(rng.integers(0, len(ready)))]
+        p, sc = encoded[kinds[mid]][int(rng.integers(0, 2))]
+        t = srv.submit(mid, p, sc)
+        with lock:
+            q.append((t, P_of[mid]))
+    while True:
+        with lock:
+            if not q:
+                break
+        time.sleep(0.001)
+    paced = srv.stats()
+    paced_wall = time.perf_counter() - t0
+    # saturation: keep the server full for a short burst
+    srv.reset_stats()
+    t1 = time.perf_counter()
+    n_sat = 0
+    while time.perf_counter() - t1 < min(3.0, seconds):
+        for k in range(3):
+            mid = ids[k]
+            p, sc = encoded[k][n_sat % 2]
+            t = srv.submit(mid, p, sc)
+            with lock:
+                q.append((t, P_of[mid]))
+            n_sat += 1
+    while True:
+        with lock:
+            if not q:
+                break
+        time.sleep(0.001)
+    sat = srv.stats()
+    done.set()
+    th.join()
+    srv.close()
+    keys = ("frames_done", "frames_per_s", "gathers_per_s", "latency_p50_us", "latency_p99_us", "latency_max_us",
+            "mean_batch_frames", "batches", "builds", "evictions", "frames_refused")
+    return {"variant": variant, "rate_hz": rate_hz, "seconds": seconds, "initial_build_s": build_s,
+            "paced": {k: paced[k] for k in keys}, "paced_wall_s": paced_wall, "new_maps": len(new_ids),
+            "saturated": {k: sat[k] for k in keys}, "errors": errors[:3]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +245,7 @@ def main():
     ap.add_argument("--frames", type=int, default=8, help="distinct resident frames cycled through")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--variants", action="store_true", help="also time the reduced-precision variants")
+    ap.add_argument("--serve", type=float, default=0.0, help="seconds of the serving mix per variant (0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -225,6 +351,8 @@ def main():
     }
     if args.variants:
         out["variants"] = run_variants(ctx, geo, table, frames, frames_h, stream, timed, args)
+    if args.serve > 0:
+        out["serving"] = [run_serving(ctx, args.serve, v) for v in ("v0", "v3")]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(geo, table_h, frames_h)
     print(json.dumps(out), flush=True)

@@ -180,6 +180,74 @@ int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void
                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
                     int N, int F, double t0, double dt, float *d_img, void *stream);
 
+/* ------------------------------------------------------------------ serving
+ *
+ * A frame server keeps each speed map's delay table resident in HBM (the
+ * paper's table is computed once per geometry offline and reused for every
+ * frame, Section III) and gathers incoming frames of any of its maps in
+ * mixed-geometry batches: frames that arrive while others are on the GPU join
+ * the next batch as slots and memory free up.  Each frame is split across
+ * workgroups exactly as a single-frame pat_backproject call of the same sizes
+ * would split it, so its image does not depend on its batch-mates.
+ */
+typedef struct pat_server pat_server;
+
+typedef struct pat_server_config {
+    size_t hbm_budget_bytes;  /* device bytes for tables, frames and build working
+                                 memory; 0 = 80% of the free memory at creation */
+    int table_fmt;            /* PAT_TABLE_F32 or PAT_TABLE_Q16, all maps */
+    int sig_fmt;              /* PAT_SIG_F32 or PAT_SIG_F16, all frames (raw p) */
+    int max_batch;            /* frames per launch (0 = 64) */
+    int max_inflight;         /* batches on the device at once (0 = 2, <= 8) */
+    int max_slots;            /* frames submitted and not yet collected by
+                                 pat_server_wait (0 = 1024) */
+} pat_server_config;
+
+enum { PAT_MAP_BUILDING = 0, PAT_MAP_READY = 1, PAT_MAP_FAILED = 2, PAT_MAP_EVICTED = 3 };
+
+typedef struct pat_server_stats {
+    int64_t frames_submitted, frames_done, frames_refused, batches, builds, evictions;
+    double mean_batch_frames;
+    double frames_per_s, gathers_per_s;       /* completed frames over the window
+                                                 since creation or the last reset */
+    double latency_p50_us, latency_p99_us, latency_max_us;  /* submit -> image on host */
+    uint64_t bytes_budget, bytes_used, bytes_tables;
+    int maps_ready, maps_building, queue_depth, inflight_batches;
+} pat_server_stats;
+
+/* Create a server on ctx's device (ctx is not used afterwards; the server owns
+ * its streams, threads and a context for table builds).  cfg may be NULL. */
+int pat_server_create(pat_ctx *ctx, const pat_server_config *cfg, pat_server **out);
+/* Waits for batches on the device, then frees everything. */
+int pat_server_destroy(pat_server *s);
+
+/* Register a speed map (host arrays are copied; same conventions as
+ * pat_eikonal_tables) with its frames' sampling (t0, dt, N).  Its table is
+ * built asynchronously on the server's build stream; frames may be submitted
+ * at once and wait until it is ready.  PAT_EBUSY if its table and build
+ * memory cannot fit in the budget even after evicting idle maps. */
+int pat_server_add_map(pat_server *s, const float *h_speed, int nx, int ny, double h,
+                       const double *h_sensor_xy, int S, const int32_t *h_pix, int P,
+                       double t0, double dt, int N, int *map_id);
+int pat_server_map_state(pat_server *s, int map_id, int *state);
+/* Unregister an idle map (PAT_EBUSY while it has frames or a build). */
+int pat_server_remove_map(pat_server *s, int map_id);
+
+/* Submit one raw frame p[S][N] (float32 or binary16 per the config; value =
+ * sample * scale for binary16, scale ignored for float32) for map_id.  The
+ * frame is copied to pinned memory before returning.  When all slots are in
+ * use: PAT_EBUSY if nonblocking, else wait for a slot.  *ticket identifies
+ * the frame.  An evicted map is rebuilt on demand. */
+int pat_server_submit(pat_server *s, int map_id, const void *h_frame, float scale, int nonblocking,
+                      uint64_t *ticket);
+/* Wait for a frame and copy its image [P] to h_img (may be NULL); releases the
+ * ticket.  timeout_ms < 0 waits forever; PAT_ETIMEOUT keeps the ticket. */
+int pat_server_wait(pat_server *s, uint64_t ticket, float *h_img, int timeout_ms);
+
+int pat_server_get_stats(pat_server *s, pat_server_stats *out);
+/* Restart the throughput window and the latency record. */
+int pat_server_reset_stats(pat_server *s);
+
 #ifdef __cplusplus
 }
 #endif

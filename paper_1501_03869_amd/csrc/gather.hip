@@ -73,25 +73,37 @@ __device__ __forceinline__ void load_delays(const uint32_t *__restrict__ tab, lo
     }
 }
 
+struct BpJob {
+    const uint32_t *tab;   // [S][P]
+    const void *sig;       // this frame's [S][N]
+    const float *w;        // [S] or null
+    float *part;           // this frame's [G][P] partial sums (G > 1)
+    float *img;            // this frame's [P]
+    unsigned int *done;    // this frame's per-chunk completion counters (G > 1)
+    int S, P, N, spg, G;
+    float t0dt, scale;
+};
+
+// One workgroup's share of one frame: pixel chunk c, sensor group g.
 template <class Delay, int SFMT, bool FILTERED, bool VEC4>
-__global__ void __launch_bounds__(BP_THREADS) k_bp(const uint32_t *__restrict__ tab, const void *__restrict__ sig,
-                                                   const float *__restrict__ scale, const float *__restrict__ w,
-                                                   int S, int P, int N, int spg, int G, Delay dec, float t0dt,
-                                                   float *__restrict__ part, float *__restrict__ img,
-                                                   unsigned int *__restrict__ done) {
+__device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c, int g) {
+    const uint32_t *__restrict__ tab = J.tab;
+    const void *__restrict__ sig = J.sig;
+    const float *__restrict__ w = J.w;
+    const int S = J.S, P = J.P, N = J.N, spg = J.spg, G = J.G;
+    const float t0dt = J.t0dt;
     __shared__ float bwin[BP_SC][BP_W];
     __shared__ float raw[FILTERED ? 1 : BP_SC][FILTERED ? 1 : BP_RAW];
     __shared__ int anchor[BP_SC];
     __shared__ unsigned int is_last;
 
     const int tid = threadIdx.x;
-    const int c = blockIdx.x, g = blockIdx.y, f = blockIdx.z;
     const int pbase = c * BP_CHUNK;
     const int p0 = pbase + tid * BP_PPT;  // this thread's first pixel
     const int s_begin = g * spg;
     const int s_end = min(S, s_begin + spg);
-    const float sc = (SFMT == PAT_SIG_F16 && scale) ? scale[f] : 1.0f;
-    const long frame_row = (long)f * S;
+    const float sc = J.scale;
+    const long frame_row = 0;
 
     float acc[BP_PPT] = { 0.0f, 0.0f, 0.0f, 0.0f };
     uint32_t cur[BP_SC][BP_PPT], nxt[BP_SC][BP_PPT];
@@ -174,36 +186,87 @@ __global__ void __launch_bounds__(BP_THREADS) k_bp(const uint32_t *__restrict__ 
         __syncthreads();  // windows and anchors are rewritten by the next chunk
     }
 
-    const long fP = (long)f * P;
+    float *__restrict__ img = J.img;
     if (G == 1) {
 #pragma unroll
         for (int k = 0; k < BP_PPT; ++k)
-            if (p0 + k < P) img[fP + p0 + k] = acc[k];
+            if (p0 + k < P) img[p0 + k] = acc[k];
         return;
     }
-    float *mine = part + ((long)f * G + g) * P;
+    float *mine = J.part + (long)g * P;
 #pragma unroll
     for (int k = 0; k < BP_PPT; ++k)
         if (p0 + k < P) mine[p0 + k] = acc[k];
     __threadfence();
     __syncthreads();
     if (tid == 0) {
-        const unsigned int prev = atomicAdd(&done[(long)f * gridDim.x + c], 1u);
+        const unsigned int prev = atomicAdd(&J.done[c], 1u);
         is_last = (prev == (unsigned)(G - 1)) ? 1u : 0u;
     }
     __syncthreads();
     if (!is_last) return;
     __threadfence();
-    const float *base = part + (long)f * G * P;
+    const float *base = J.part;
 #pragma unroll
     for (int k = 0; k < BP_PPT; ++k) {
         const int p = p0 + k;
         if (p >= P) continue;
         float s = 0.0f;
         for (int gg = 0; gg < G; ++gg) s += __builtin_nontemporal_load(base + (long)gg * P + p);
-        img[fP + p] = s;
+        img[p] = s;
     }
-    if (tid == 0) done[(long)f * gridDim.x + c] = 0u;  // ready for the next launch
+    if (tid == 0) J.done[c] = 0u;  // ready for the next launch
+}
+
+template <class Delay, int SFMT, bool FILTERED, bool VEC4>
+__global__ void __launch_bounds__(BP_THREADS) k_bp(const uint32_t *__restrict__ tab, const void *__restrict__ sig,
+                                                   const float *__restrict__ scale, const float *__restrict__ w,
+                                                   int S, int P, int N, int spg, int G, Delay dec, float t0dt,
+                                                   float *__restrict__ part, float *__restrict__ img,
+                                                   unsigned int *__restrict__ done) {
+    const int f = blockIdx.z;
+    const size_t esz = SFMT == PAT_SIG_F16 ? 2 : 4;
+    BpJob J;
+    J.tab = tab;
+    J.sig = static_cast<const char *>(sig) + (size_t)f * S * N * esz;
+    J.w = w;
+    J.part = part ? part + (long)f * G * P : nullptr;
+    J.img = img + (long)f * P;
+    J.done = done ? done + (long)f * gridDim.x : nullptr;
+    J.S = S; J.P = P; J.N = N; J.spg = spg; J.G = G;
+    J.t0dt = t0dt;
+    J.scale = (SFMT == PAT_SIG_F16 && scale) ? scale[f] : 1.0f;
+    bp_block<Delay, SFMT, FILTERED, VEC4>(J, dec, blockIdx.x, blockIdx.y);
+}
+
+// Frames of different geometries in one launch: workgroup b belongs to the
+// last descriptor whose block_begin <= b and covers (chunk, group) of that
+// frame exactly as a single-frame launch would, so a frame's image does not
+// depend on its batch-mates.
+template <int TFMT, int SFMT, bool VEC4>
+__global__ void __launch_bounds__(BP_THREADS) k_bp_multi(const pat_bp_desc *__restrict__ descs, int nd) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+    }
+    const pat_bp_desc &D = descs[lo];
+    const int local = b - D.block_begin;
+    BpJob J;
+    J.tab = D.tab; J.sig = D.sig; J.w = D.w; J.part = D.part; J.img = D.img; J.done = D.done;
+    J.S = D.S; J.P = D.P; J.N = D.N; J.spg = D.spg; J.G = D.G;
+    J.t0dt = D.t0dt;
+    J.scale = D.scale;
+    const int c = local % D.chunks, g = local / D.chunks;
+    if constexpr (TFMT == PAT_TABLE_F32) {
+        DelayF32 dec;
+        dec.inv_hi = D.inv_hi; dec.inv_lo = D.inv_lo; dec.off = D.off; dec.umax = D.umax;
+        bp_block<DelayF32, SFMT, false, VEC4>(J, dec, c, g);
+    } else {
+        DelayQ16 dec;
+        bp_block<DelayQ16, SFMT, false, VEC4>(J, dec, c, g);
+    }
 }
 
 template <class Delay, int SFMT>
@@ -294,4 +357,40 @@ int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const
     return sig_fmt == PAT_SIG_F32
                ? launch<DelayQ16, PAT_SIG_F32>(filt, vec4, grid, tab, sig, frame_scale, w, S, P, N, sh.spg, sh.groups, d, t0dt, part, img, done, st)
                : launch<DelayQ16, PAT_SIG_F16>(filt, vec4, grid, tab, sig, frame_scale, w, S, P, N, sh.spg, sh.groups, d, t0dt, part, img, done, st);
+}
+
+int pat_bp_frame_shape(pat_bp_desc *d, int S, int P, int N, double t0, double dt, size_t *part_floats) {
+    const BpShape sh = bp_shape(S, P, 1);
+    d->S = S;
+    d->P = P;
+    d->N = N;
+    d->spg = sh.spg;
+    d->G = sh.groups;
+    d->chunks = sh.chunks;
+    d->t0dt = (float)(t0 / dt);
+    const double inv = 1.0 / dt;
+    d->inv_hi = (float)inv;
+    d->inv_lo = (float)(inv - (double)d->inv_hi);
+    d->off = (float)(-t0 / dt);
+    d->umax = (float)(N - 1);
+    d->scale = 1.0f;
+    *part_floats = sh.groups > 1 ? (size_t)sh.groups * P : 0;
+    return sh.chunks * sh.groups;
+}
+
+int pat_launch_bp_multi(const pat_bp_desc *d_descs, int nd, int total_blocks, int table_fmt, int sig_fmt, bool vec4,
+                        hipStream_t st) {
+    if (nd <= 0 || total_blocks <= 0) return PAT_OK;
+    const dim3 grid(total_blocks);
+#define PAT_BPM(TF, SF, V4) k_bp_multi<TF, SF, V4><<<grid, BP_THREADS, 0, st>>>(d_descs, nd)
+    if (table_fmt == PAT_TABLE_F32) {
+        if (sig_fmt == PAT_SIG_F32) { if (vec4) PAT_BPM(PAT_TABLE_F32, PAT_SIG_F32, true); else PAT_BPM(PAT_TABLE_F32, PAT_SIG_F32, false); }
+        else { if (vec4) PAT_BPM(PAT_TABLE_F32, PAT_SIG_F16, true); else PAT_BPM(PAT_TABLE_F32, PAT_SIG_F16, false); }
+    } else {
+        if (sig_fmt == PAT_SIG_F32) { if (vec4) PAT_BPM(PAT_TABLE_Q16, PAT_SIG_F32, true); else PAT_BPM(PAT_TABLE_Q16, PAT_SIG_F32, false); }
+        else { if (vec4) PAT_BPM(PAT_TABLE_Q16, PAT_SIG_F16, true); else PAT_BPM(PAT_TABLE_Q16, PAT_SIG_F16, false); }
+    }
+#undef PAT_BPM
+    PAT_HIP(hipGetLastError());
+    return PAT_OK;
 }

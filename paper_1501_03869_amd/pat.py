@@ -24,13 +24,32 @@ EXPORTED = [
     "pat_last_error", "pat_version", "pat_ctx_create", "pat_ctx_destroy", "pat_ctx_reserve",
     "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_last_stats", "pat_table_to_q16",
     "pat_tile_order", "pat_filter", "pat_backproject",
+    "pat_server_create", "pat_server_destroy", "pat_server_add_map", "pat_server_map_state",
+    "pat_server_remove_map", "pat_server_submit", "pat_server_wait", "pat_server_get_stats",
+    "pat_server_reset_stats",
 ]
+MAP_BUILDING, MAP_READY, MAP_FAILED, MAP_EVICTED = 0, 1, 2, 3
 
 
 class PatError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"libpat error {code}: {msg}")
         self.code = code
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("table_fmt", C.c_int), ("sig_fmt", C.c_int),
+                ("max_batch", C.c_int), ("max_inflight", C.c_int), ("max_slots", C.c_int)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("frames_submitted", C.c_int64), ("frames_done", C.c_int64), ("frames_refused", C.c_int64),
+                ("batches", C.c_int64), ("builds", C.c_int64), ("evictions", C.c_int64),
+                ("mean_batch_frames", C.c_double), ("frames_per_s", C.c_double), ("gathers_per_s", C.c_double),
+                ("latency_p50_us", C.c_double), ("latency_p99_us", C.c_double), ("latency_max_us", C.c_double),
+                ("bytes_budget", C.c_uint64), ("bytes_used", C.c_uint64), ("bytes_tables", C.c_uint64),
+                ("maps_ready", C.c_int), ("maps_building", C.c_int), ("queue_depth", C.c_int),
+                ("inflight_batches", C.c_int)]
 
 
 class EikonalStats(C.Structure):
@@ -63,6 +82,15 @@ def lib() -> C.CDLL:
         L.pat_tile_order.argtypes = [i32, i32, vp, i32, i32, i32, vp]
         L.pat_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp]
         L.pat_backproject.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp, i32, i32, i32, i32, dbl, dbl, vp, vp]
+        L.pat_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
+        L.pat_server_destroy.argtypes = [vp]
+        L.pat_server_add_map.argtypes = [vp, vp, i32, i32, dbl, vp, i32, vp, i32, dbl, dbl, i32, C.POINTER(i32)]
+        L.pat_server_map_state.argtypes = [vp, i32, C.POINTER(i32)]
+        L.pat_server_remove_map.argtypes = [vp, i32]
+        L.pat_server_submit.argtypes = [vp, i32, vp, C.c_float, i32, C.POINTER(C.c_uint64)]
+        L.pat_server_wait.argtypes = [vp, C.c_uint64, vp, i32]
+        L.pat_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.pat_server_reset_stats.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -197,3 +225,75 @@ def tile_order(nx: int, ny: int, pix: np.ndarray, tile_w: int = 16, tile_h: int 
 
 def backproject_scratch_bytes(S: int, P: int, F: int = 1) -> int:
     return int(lib().pat_backproject_scratch_bytes(S, P, F))
+
+
+class Server:
+    """Frame server (resident tables, continuous mixed-geometry batching)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, table_fmt: int = TABLE_F32, sig_fmt: int = SIG_F32,
+                 max_batch: int = 0, max_inflight: int = 0, max_slots: int = 0):
+        cfg = ServerConfig(int(hbm_budget_bytes), int(table_fmt), int(sig_fmt), int(max_batch), int(max_inflight),
+                           int(max_slots))
+        h = C.c_void_p()
+        check(lib().pat_server_create(ctx.h, C.byref(cfg), C.byref(h)))
+        self.h = h
+        self.sig_fmt = sig_fmt
+        self._geo = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(lib().pat_server_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_map(self, speed: np.ndarray, h: float, sensors: np.ndarray, pix: np.ndarray, n_samples: int, dt: float,
+                t0: float = 0.0) -> int:
+        c = np.ascontiguousarray(speed, dtype=np.float32)
+        ny, nx = c.shape
+        sxy = np.ascontiguousarray(sensors, dtype=np.float64)
+        px = np.ascontiguousarray(pix, dtype=np.int32)
+        mid = C.c_int()
+        check(lib().pat_server_add_map(self.h, c.ctypes.data, nx, ny, float(h), sxy.ctypes.data, sxy.shape[0],
+                                       px.ctypes.data, px.shape[0], float(t0), float(dt), int(n_samples),
+                                       C.byref(mid)))
+        self._geo[mid.value] = (sxy.shape[0], px.shape[0], int(n_samples))
+        return mid.value
+
+    def map_state(self, map_id: int) -> int:
+        st = C.c_int()
+        check(lib().pat_server_map_state(self.h, int(map_id), C.byref(st)))
+        return st.value
+
+    def remove_map(self, map_id: int):
+        check(lib().pat_server_remove_map(self.h, int(map_id)))
+
+    def submit(self, map_id: int, frame: np.ndarray, scale: float = 1.0, nonblocking: bool = False) -> int:
+        want = np.float16 if self.sig_fmt == SIG_F16 else np.float32
+        f = np.ascontiguousarray(frame, dtype=want)
+        S, P, N = self._geo[map_id]
+        if f.shape != (S, N):
+            raise ValueError(f"frame must be {(S, N)}, got {f.shape}")
+        t = C.c_uint64()
+        check(lib().pat_server_submit(self.h, int(map_id), f.ctypes.data, C.c_float(scale), 1 if nonblocking else 0,
+                                      C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, map_id: int | None = None, P: int | None = None, timeout_ms: int = -1):
+        if P is None:
+            P = self._geo[map_id][1]
+        out = np.empty(P, dtype=np.float32)
+        check(lib().pat_server_wait(self.h, C.c_uint64(ticket), out.ctypes.data, int(timeout_ms)))
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check(lib().pat_server_get_stats(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        check(lib().pat_server_reset_stats(self.h))
