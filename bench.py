@@ -9,8 +9,12 @@ the per-sensor delay table already resident in HBM.  The table itself is built
 once beforehand by pat_eikonal_tables (the paper's offline step) and its build
 time is reported separately.
 
-Prints one JSON line (see the keys below).  Usage:
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--variants]
+Also timed (extra keys of the same JSON line): the 16.16-table and FP16
+variants, 64-frame batched launches replayed from a HIP graph, and a short
+serving mix (Poisson frames over three resident maps plus table builds).
+
+Prints one JSON line.  Usage:
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-variants] [--serve SECONDS]
 """
 from __future__ import annotations
 
@@ -244,8 +248,10 @@ def main():
     ap.add_argument("--config", default="paper")
     ap.add_argument("--frames", type=int, default=8, help="distinct resident frames cycled through")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--variants", action="store_true", help="also time the reduced-precision variants")
-    ap.add_argument("--serve", type=float, default=0.0, help="seconds of the serving mix per variant (0 = skip)")
+    ap.add_argument("--no-variants", action="store_true", help="skip the reduced-precision and batched variants")
+    ap.add_argument("--serve", type=float, default=5.0, help="seconds of the serving mix per variant (0 = skip)")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
+                    help="only run a plain device copy of MB megabytes 10 times (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -260,6 +266,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration > 0:
+        # a plain copy of known size: the scale of the HBM byte counters
+        n = int(args.copy_calibration * 1e6) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 10}), flush=True)
+        return
     dev = torch.device("cuda:0")
     ctx = pat.Context(0)
     geo = inputs.config(args.config)
@@ -305,6 +321,13 @@ def main():
         ctx.backproject(table, frames[r], geo.dt, geo.t0, filtered=False, out=img[r], stream=stream)
 
     wall, dev_ms = timed(step, args.steps, args.warmup)
+    S, P, N = geo.S, geo.P, geo.n_samples
+    gathers = args.steps * S * P
+    value = gathers / wall
+    bytes_per_frame = 4 * S * P + 4 * S * N + 4 * P
+    avg_kernel_s = float(np.mean(dev_ms)) * 1e-3
+    achieved = bytes_per_frame / avg_kernel_s / 1e9
+
     # end-to-end latency: host frame -> H2D -> back projection -> D2H image
     pinned_in = [torch.from_numpy(f).pin_memory() for f in frames_h[:4]]
     pinned_out = torch.empty((P,), dtype=torch.float32).pin_memory()
@@ -345,11 +368,11 @@ def main():
         "table_build_rounds": est["rounds"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "pat_backproject (gather + fixed-order partial-sum reduce)",
+                     "kernel": "k_bp: fused UBP filter + delay-and-sum gather, one launch per frame",
                      "algorithmic_bytes_per_launch": bytes_per_frame},
         "paper_context": "123.79 ms for 512 sensors x 21323 pixels on an NVIDIA Tesla C2075, transfers included",
     }
-    if args.variants:
+    if not args.no_variants:
         out["variants"] = run_variants(ctx, geo, table, frames, frames_h, stream, timed, args)
     if args.serve > 0:
         out["serving"] = [run_serving(ctx, args.serve, v) for v in ("v0", "v3")]

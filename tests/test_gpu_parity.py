@@ -356,3 +356,38 @@ def test_scratch_reuse_across_shapes(ctx, orc):
     for k, (S, P, N, F) in enumerate(cases):
         got, ref = _gather_case(ctx, orc, S, P, N, F, 0.05, seed=40 + k)
         assert rel_l2(got, ref) <= IMG_TOL, (S, P, N, F)
+
+
+def test_eikonal_random_tiny_media(ctx, orc):
+    # property sweep: random small grids (including 2xN strips and sizes that
+    # straddle tile edges), random contrast, random in-box sensors
+    rng = np.random.default_rng(2024)
+    for case in range(12):
+        nx, ny = int(rng.integers(2, 41)), int(rng.integers(2, 41))
+        if case == 0:
+            nx, ny = 2, 37
+        if case == 1:
+            nx, ny = 33, 2
+        h = float(rng.uniform(0.05e-3, 0.5e-3))
+        c = rng.uniform(1000, 4000, size=(ny, nx)).astype(np.float32)
+        x, y = inputs.node_coords(nx, ny, h)
+        S = int(rng.integers(1, 6))
+        sens = np.stack([rng.uniform(x[0], x[-1], S), rng.uniform(y[0], y[-1], S)], 1)
+        pix = rng.permutation(nx * ny)[: int(rng.integers(1, nx * ny + 1))].astype(np.int32)
+        geo = inputs.Geometry("rand", nx, ny, h, c, sens, pix, 64, 1e-7)
+        ref = orc.tables(c, h, sens, pix)
+        got = gpu_table(ctx, geo).cpu().numpy()
+        assert max_rel(got, ref) <= T_TOL, (case, nx, ny)
+
+
+def test_q16_at_the_sample_limit(ctx, orc):
+    # the largest record a 16.16 index can address
+    N, dt = 65535, 2.0 ** -20
+    T = np.array([[0.0, (N - 1) * dt, (N - 1.5) * dt, (N - 1) * dt * (1 + 1e-6), 123.25 * dt]], np.float32)
+    got = ctx.table_to_q16(dev(T), dt, N).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, orc.table_to_q16(T, dt, N))
+    assert got[0, 1] == (N - 1) << 16 and got[0, 3] == 0xFFFFFFFF
+    b = np.random.default_rng(3).normal(size=(1, N)).astype(np.float32)
+    img = ctx.backproject(dev(got.view(np.int32)), dev(b), dt).cpu().numpy()
+    ref = orc.gather_q16(got, b)
+    np.testing.assert_allclose(img, ref, rtol=1e-6, atol=1e-6)
