@@ -132,47 +132,72 @@ __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c
             anchor[tid] = an;
         }
         __syncthreads();
+        // stage: per sensor a window of b = p - t dp/dt, filtered here from raw samples
         if constexpr (FILTERED) {
-            for (int idx = tid; idx < ns * BP_W; idx += BP_THREADS) {
-                const int si = idx / BP_W, j = idx % BP_W;
-                const int gi = min(max(anchor[si] + j, 0), N - 1);
-                bwin[si][j] = load_sig<SFMT>(sig, (frame_row + s0 + si) * N + gi, sc);
+            for (int si = 0; si < ns; ++si) {
+                const int an = anchor[si];
+                const long row = (frame_row + s0 + si) * N;
+                for (int j = tid; j < BP_W; j += BP_THREADS)
+                    bwin[si][j] = load_sig<SFMT>(sig, row + min(max(an + j, 0), N - 1), sc);
             }
         } else {
-            for (int idx = tid; idx < ns * BP_RAW; idx += BP_THREADS) {
-                const int si = idx / BP_RAW, j = idx % BP_RAW;
-                const int gi = min(max(anchor[si] - 1 + j, 0), N - 1);
-                raw[si][j] = load_sig<SFMT>(sig, (frame_row + s0 + si) * N + gi, sc);
+            for (int si = 0; si < ns; ++si) {
+                const int an = anchor[si];
+                const long row = (frame_row + s0 + si) * N;
+                for (int j = tid; j < BP_RAW; j += BP_THREADS)
+                    raw[si][j] = load_sig<SFMT>(sig, row + min(max(an - 1 + j, 0), N - 1), sc);
             }
             __syncthreads();
-            for (int idx = tid; idx < ns * BP_W; idx += BP_THREADS) {
-                const int si = idx / BP_W, j = idx % BP_W;
-                const int i = anchor[si] + j;
-                bwin[si][j] = ubp(raw[si][j], raw[si][j + 1], raw[si][j + 2], i, N, t0dt);
+            for (int si = 0; si < ns; ++si) {
+                const int an = anchor[si];
+                for (int j = tid; j < BP_W; j += BP_THREADS)
+                    bwin[si][j] = ubp(raw[si][j], raw[si][j + 1], raw[si][j + 2], an + j, N, t0dt);
             }
         }
         __syncthreads();
+        // gather: branch-free from the windows; a delay outside its window is
+        // only noted here and served from global memory below
+        bool anyfall = false;
 #pragma unroll
         for (int j = 0; j < BP_SC; ++j) {
             if (j < ns) {
-                const int s = s0 + j;
-                const float ws = w ? w[s] : 1.0f;
-                const int an = anchor[j];
-                const long row = (frame_row + s) * N;
+                const float ws = w ? w[s0 + j] : 1.0f;
+                const auto win = dec.window(anchor[j]);
+                float b0[BP_PPT], b1[BP_PPT], al[BP_PPT], wk[BP_PPT];
 #pragma unroll
                 for (int k = 0; k < BP_PPT; ++k) {
+                    int idx;
+                    const bool ok = dec.decode_win(cur[j][k], win, idx, al[k]);
+                    const bool inw = (unsigned)idx < (unsigned)(BP_W - 1);
+                    wk[k] = (ok && inw) ? ws : 0.0f;
+                    anyfall |= !inw;  // a delay that does not contribute decodes to idx 0
+                    const int id = inw ? idx : 0;
+                    b0[k] = bwin[j][id];
+                    b1[k] = bwin[j][id + 1];
+                }
+#pragma unroll
+                for (int k = 0; k < BP_PPT; ++k) acc[k] = fmaf(wk[k], fmaf(al[k], b1[k] - b0[k], b0[k]), acc[k]);
+            }
+        }
+        if (__any(anyfall)) {
+            // rare: recompute which delays missed their window and read the
+            // two samples from global memory
+#pragma unroll
+            for (int j = 0; j < BP_SC; ++j) {
+                if (j >= ns) continue;
+                const auto win = dec.window(anchor[j]);
+                const float ws = w ? w[s0 + j] : 1.0f;
+                const long row = (frame_row + s0 + j) * N;
+#pragma unroll
+                for (int k = 0; k < BP_PPT; ++k) {
+                    int idx;
+                    float al;
+                    const bool ok = dec.decode_win(cur[j][k], win, idx, al);
                     int n;
                     float a;
-                    if (dec.decode(cur[j][k], N, n, a)) {
-                        const int idx = n - an;
-                        float b0, b1;
-                        if ((unsigned)idx < (unsigned)(BP_W - 1)) {
-                            b0 = bwin[j][idx];
-                            b1 = bwin[j][idx + 1];
-                        } else {
-                            b0 = sample_b<SFMT, FILTERED>(sig, row, n, N, sc, t0dt);
-                            b1 = sample_b<SFMT, FILTERED>(sig, row, n + 1, N, sc, t0dt);
-                        }
+                    if (ok && (unsigned)idx >= (unsigned)(BP_W - 1) && dec.decode(cur[j][k], N, n, a)) {
+                        const float b0 = sample_b<SFMT, FILTERED>(sig, row, n, N, sc, t0dt);
+                        const float b1 = sample_b<SFMT, FILTERED>(sig, row, n + 1, N, sc, t0dt);
                         acc[k] = fmaf(ws, fmaf(a, b1 - b0, b0), acc[k]);
                     }
                 }

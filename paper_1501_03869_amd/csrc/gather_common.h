@@ -23,6 +23,27 @@ struct DelayF32 {
     __device__ __forceinline__ bool decode(uint32_t bits, int N, int &n, float &a) const {
         return decode(__uint_as_float(bits), N, n, a);
     }
+    // Window-relative, branch-free decoding for an LDS window that starts at
+    // sample an: idx = floor(u) - an and a = frac(u) with u' = u - an computed
+    // directly (the anchor folds into the offset, so u' keeps more fraction
+    // bits than u).  ok: the delay contributes; idx and a are 0 when not ok.
+    struct Win { float off, lo, hi; };
+    __device__ __forceinline__ Win window(int an) const {
+        Win w;
+        w.off = off - (float)an;
+        w.lo = -(float)an;
+        w.hi = umax - (float)an;
+        return w;
+    }
+    __device__ __forceinline__ bool decode_win(uint32_t bits, const Win &w, int &idx, float &a) const {
+        const float T = __uint_as_float(bits);
+        float u = fmaf(T, inv_hi, fmaf(T, inv_lo, w.off));
+        const bool ok = u >= w.lo && u <= w.hi;
+        u = ok ? u : 0.0f;
+        idx = (int)floorf(u);
+        a = u - floorf(u);
+        return ok;
+    }
 };
 
 struct DelayQ16 {
@@ -35,6 +56,14 @@ struct DelayQ16 {
             a = 1.0f;
         }
         return true;
+    }
+    struct Win { int an; };
+    __device__ __forceinline__ Win window(int an) const { return Win{ an }; }
+    __device__ __forceinline__ bool decode_win(uint32_t q, const Win &w, int &idx, float &a) const {
+        const bool ok = q != 0xFFFFFFFFu;
+        idx = ok ? (int)(q >> 16) - w.an : 0;
+        a = ok ? (float)(q & 0xFFFFu) * (1.0f / 65536.0f) : 0.0f;
+        return ok;
     }
 };
 
