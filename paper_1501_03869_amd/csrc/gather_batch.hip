@@ -197,24 +197,45 @@ __global__ void __launch_bounds__(BB_THREADS) k_bp_batch(const uint32_t *__restr
             coeffs<FILTERED>(n, a, w ? w[s] : 1.0f, N, t0dt, cf);
             const int j = n - 1 - A;
             if ((unsigned)j <= (unsigned)(BB_WS - 4)) {
+                // all taps of the 16 frames first, so the LDS reads overlap
+                uint32_t d0[BB_FB], d1[BB_FB], d2[BB_FB], d3[BB_FB];
 #pragma unroll
                 for (int f = 0; f < BB_FB; ++f) {
                     const uint32_t *wf = &win[buf][f][j];
                     if constexpr (SFMT == PAT_SIG_F16) {
                         if constexpr (FILTERED) {
-                            const uint32_t d = wf[1];
-                            acc[f] = fmaf(cf[1], lo_h(d), fmaf(cf[2], hi_h(d), acc[f]));
+                            d0[f] = wf[1];
                         } else {
-                            const uint32_t d0 = wf[0], d1 = wf[2];
-                            acc[f] = fmaf(cf[0], lo_h(d0), fmaf(cf[1], hi_h(d0),
-                                     fmaf(cf[2], lo_h(d1), fmaf(cf[3], hi_h(d1), acc[f]))));
+                            d0[f] = wf[0];
+                            d1[f] = wf[2];
                         }
                     } else {
-                        const float *xf = reinterpret_cast<const float *>(wf);
                         if constexpr (FILTERED) {
-                            acc[f] = fmaf(cf[1], xf[1], fmaf(cf[2], xf[2], acc[f]));
+                            d1[f] = wf[1];
+                            d2[f] = wf[2];
                         } else {
-                            acc[f] = fmaf(cf[0], xf[0], fmaf(cf[1], xf[1], fmaf(cf[2], xf[2], fmaf(cf[3], xf[3], acc[f]))));
+                            d0[f] = wf[0];
+                            d1[f] = wf[1];
+                            d2[f] = wf[2];
+                            d3[f] = wf[3];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < BB_FB; ++f) {
+                    if constexpr (SFMT == PAT_SIG_F16) {
+                        if constexpr (FILTERED) {
+                            acc[f] = fmaf(cf[1], lo_h(d0[f]), fmaf(cf[2], hi_h(d0[f]), acc[f]));
+                        } else {
+                            acc[f] = fmaf(cf[0], lo_h(d0[f]), fmaf(cf[1], hi_h(d0[f]),
+                                     fmaf(cf[2], lo_h(d1[f]), fmaf(cf[3], hi_h(d1[f]), acc[f]))));
+                        }
+                    } else {
+                        if constexpr (FILTERED) {
+                            acc[f] = fmaf(cf[1], __uint_as_float(d1[f]), fmaf(cf[2], __uint_as_float(d2[f]), acc[f]));
+                        } else {
+                            acc[f] = fmaf(cf[0], __uint_as_float(d0[f]), fmaf(cf[1], __uint_as_float(d1[f]),
+                                     fmaf(cf[2], __uint_as_float(d2[f]), fmaf(cf[3], __uint_as_float(d3[f]), acc[f]))));
                         }
                     }
                 }
