@@ -295,7 +295,10 @@ def main():
     print(f"[bench] tables built in {build_s:.3f} s ({est['rounds']} rounds)", file=sys.stderr, flush=True)
 
     table_h = table.cpu().numpy()
-    frames_h = [inputs.frame_for(geo, table_h, f) for f in range(args.frames)]
+    # the large grid's vascular phantom has tens of thousands of nodes: point
+    # absorbers keep its frame synthesis short (the content does not change the work)
+    phantom = "points" if geo.nx * geo.ny > 512 * 512 else "segments"
+    frames_h = [inputs.frame_for(geo, table_h, f, phantom=phantom) for f in range(args.frames)]
     frames = torch.from_numpy(np.stack(frames_h)).to(dev)
     img = torch.empty((args.frames, geo.P), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()

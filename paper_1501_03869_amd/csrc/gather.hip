@@ -85,6 +85,16 @@ struct BpJob {
 };
 
 // One workgroup's share of one frame: pixel chunk c, sensor group g.
+//
+// Software pipeline over chunks of BP_SC sensors (i = current chunk):
+//   top     - decode the window anchors of chunk i+1 (probe delays loaded one
+//             iteration earlier), issue its window loads into registers, its
+//             delay loads, and the probe loads of chunk i+2;
+//   middle  - gather chunk i from its LDS windows while those loads fly;
+//   bottom  - store chunk i+1's raw window, filter it into the other window
+//             buffer, barrier.
+// So a chunk costs one memory latency overlapped with a chunk of gathers,
+// instead of a chain of dependent loads.
 template <class Delay, int SFMT, bool FILTERED, bool VEC4>
 __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c, int g) {
     const uint32_t *__restrict__ tab = J.tab;
@@ -92,9 +102,10 @@ __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c
     const float *__restrict__ w = J.w;
     const int S = J.S, P = J.P, N = J.N, spg = J.spg, G = J.G;
     const float t0dt = J.t0dt;
-    __shared__ float bwin[BP_SC][BP_W];
+    constexpr int WLEN = FILTERED ? BP_W : BP_RAW;                 // staged samples per sensor
+    constexpr int NR = (WLEN + BP_THREADS - 1) / BP_THREADS;       // staged samples per thread
+    __shared__ float bwin[2][BP_SC][BP_W];
     __shared__ float raw[FILTERED ? 1 : BP_SC][FILTERED ? 1 : BP_RAW];
-    __shared__ int anchor[BP_SC];
     __shared__ unsigned int is_last;
 
     const int tid = threadIdx.x;
@@ -102,59 +113,108 @@ __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c
     const int p0 = pbase + tid * BP_PPT;  // this thread's first pixel
     const int s_begin = g * spg;
     const int s_end = min(S, s_begin + spg);
+    const int nchunk = s_end > s_begin ? (s_end - s_begin + BP_SC - 1) / BP_SC : 0;
     const float sc = J.scale;
-    const long frame_row = 0;
 
     float acc[BP_PPT] = { 0.0f, 0.0f, 0.0f, 0.0f };
     uint32_t cur[BP_SC][BP_PPT], nxt[BP_SC][BP_PPT];
+    uint32_t pr_next[BP_SC], pr_next2[BP_SC];
+    int an_cur[BP_SC], an_next[BP_SC];
+    float rv[BP_SC][NR];
 
-#pragma unroll
-    for (int j = 0; j < BP_SC; ++j) {
-        if (s_begin + j < s_end) load_delays<VEC4>(tab, (long)(s_begin + j) * P, p0, P, cur[j]);
-        else { cur[j][0] = cur[j][1] = cur[j][2] = cur[j][3] = 0xFFFFFFFFu; }
-    }
-
-    for (int s0 = s_begin; s0 < s_end; s0 += BP_SC) {
-        const int ns = min(BP_SC, s_end - s0);
-        // prefetch the next chunk of delays while this one is staged and gathered
+    // delay of the chunk's first pixel to each sensor of chunk i (window probes)
+    auto probe = [&](int i, uint32_t (&pr)[BP_SC]) {
 #pragma unroll
         for (int j = 0; j < BP_SC; ++j) {
-            const int s = s0 + BP_SC + j;
-            if (s < s_end) load_delays<VEC4>(tab, (long)s * P, p0, P, nxt[j]);
-            else { nxt[j][0] = nxt[j][1] = nxt[j][2] = nxt[j][3] = 0xFFFFFFFFu; }
+            const int s = s_begin + i * BP_SC + j;
+            pr[j] = (i < nchunk && s < s_end) ? tab[(long)s * P + pbase] : 0xFFFFFFFFu;
         }
-        // window anchors from the chunk's first pixel
-        if (tid < ns) {
+    };
+    auto anchors = [&](const uint32_t (&pr)[BP_SC], int (&an)[BP_SC]) {
+#pragma unroll
+        for (int j = 0; j < BP_SC; ++j) {
             int n;
             float a;
-            int an = 0;
-            if (dec.decode(tab[(long)(s0 + tid) * P + pbase], N, n, a)) an = n - BP_W / 2;
-            anchor[tid] = an;
+            an[j] = dec.decode(pr[j], N, n, a) ? n - BP_W / 2 : 0;
         }
-        __syncthreads();
-        // stage: per sensor a window of b = p - t dp/dt, filtered here from raw samples
+    };
+    auto delays = [&](int i, uint32_t (&v)[BP_SC][BP_PPT]) {
+#pragma unroll
+        for (int j = 0; j < BP_SC; ++j) {
+            const int s = s_begin + i * BP_SC + j;
+            if (s < s_end) load_delays<VEC4>(tab, (long)s * P, p0, P, v[j]);
+            else { v[j][0] = v[j][1] = v[j][2] = v[j][3] = 0xFFFFFFFFu; }
+        }
+    };
+    // window samples of chunk i into registers (all loads issued together)
+    auto stage_load = [&](int i, const int (&an)[BP_SC]) {
+#pragma unroll
+        for (int si = 0; si < BP_SC; ++si) {
+            const int s = s_begin + i * BP_SC + si;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int j = tid + r * BP_THREADS;
+                rv[si][r] = 0.0f;
+                if (s < s_end && j < WLEN) {
+                    const int gi = min(max((FILTERED ? an[si] : an[si] - 1) + j, 0), N - 1);
+                    rv[si][r] = load_sig<SFMT>(sig, (long)s * N + gi, sc);
+                }
+            }
+        }
+    };
+    // registers -> LDS window buffer buf (raw samples are filtered on the way)
+    auto stage_store = [&](int i, const int (&an)[BP_SC], int buf) {
+        const int ns = min(BP_SC, s_end - (s_begin + i * BP_SC));
         if constexpr (FILTERED) {
-            for (int si = 0; si < ns; ++si) {
-                const int an = anchor[si];
-                const long row = (frame_row + s0 + si) * N;
-                for (int j = tid; j < BP_W; j += BP_THREADS)
-                    bwin[si][j] = load_sig<SFMT>(sig, row + min(max(an + j, 0), N - 1), sc);
-            }
+#pragma unroll
+            for (int si = 0; si < BP_SC; ++si)
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const int j = tid + r * BP_THREADS;
+                    if (si < ns && j < BP_W) bwin[buf][si][j] = rv[si][r];
+                }
         } else {
-            for (int si = 0; si < ns; ++si) {
-                const int an = anchor[si];
-                const long row = (frame_row + s0 + si) * N;
-                for (int j = tid; j < BP_RAW; j += BP_THREADS)
-                    raw[si][j] = load_sig<SFMT>(sig, row + min(max(an - 1 + j, 0), N - 1), sc);
-            }
+#pragma unroll
+            for (int si = 0; si < BP_SC; ++si)
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const int j = tid + r * BP_THREADS;
+                    if (si < ns && j < BP_RAW) raw[si][j] = rv[si][r];
+                }
             __syncthreads();
-            for (int si = 0; si < ns; ++si) {
-                const int an = anchor[si];
-                for (int j = tid; j < BP_W; j += BP_THREADS)
-                    bwin[si][j] = ubp(raw[si][j], raw[si][j + 1], raw[si][j + 2], an + j, N, t0dt);
+#pragma unroll
+            for (int si = 0; si < BP_SC; ++si) {
+                if (si >= ns) continue;
+#pragma unroll
+                for (int r = 0; r < (BP_W + BP_THREADS - 1) / BP_THREADS; ++r) {
+                    const int j = tid + r * BP_THREADS;
+                    if (j < BP_W) bwin[buf][si][j] = ubp(raw[si][j], raw[si][j + 1], raw[si][j + 2], an[si] + j, N, t0dt);
+                }
             }
         }
+    };
+
+    if (nchunk > 0) {
+        probe(0, pr_next);
+        anchors(pr_next, an_cur);
+        delays(0, cur);
+        stage_load(0, an_cur);
+        probe(1, pr_next);
+        stage_store(0, an_cur, 0);
         __syncthreads();
+    }
+
+    for (int i = 0; i < nchunk; ++i) {
+        const int buf = i & 1;
+        const bool more = i + 1 < nchunk;
+        const int s0 = s_begin + i * BP_SC;
+        const int ns = min(BP_SC, s_end - s0);
+        if (more) {
+            anchors(pr_next, an_next);
+            stage_load(i + 1, an_next);
+            delays(i + 1, nxt);
+            probe(i + 2, pr_next2);
+        }
         // gather: branch-free from the windows; a delay outside its window is
         // only noted here and served from global memory below
         bool anyfall = false;
@@ -162,7 +222,7 @@ __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c
         for (int j = 0; j < BP_SC; ++j) {
             if (j < ns) {
                 const float ws = w ? w[s0 + j] : 1.0f;
-                const auto win = dec.window(anchor[j]);
+                const auto win = dec.window(an_cur[j]);
                 float b0[BP_PPT], b1[BP_PPT], al[BP_PPT], wk[BP_PPT];
 #pragma unroll
                 for (int k = 0; k < BP_PPT; ++k) {
@@ -172,22 +232,21 @@ __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c
                     wk[k] = (ok && inw) ? ws : 0.0f;
                     anyfall |= !inw;  // a delay that does not contribute decodes to idx 0
                     const int id = inw ? idx : 0;
-                    b0[k] = bwin[j][id];
-                    b1[k] = bwin[j][id + 1];
+                    b0[k] = bwin[buf][j][id];
+                    b1[k] = bwin[buf][j][id + 1];
                 }
 #pragma unroll
                 for (int k = 0; k < BP_PPT; ++k) acc[k] = fmaf(wk[k], fmaf(al[k], b1[k] - b0[k], b0[k]), acc[k]);
             }
         }
         if (__any(anyfall)) {
-            // rare: recompute which delays missed their window and read the
-            // two samples from global memory
+            // rare: the delays that missed their window read global memory
 #pragma unroll
             for (int j = 0; j < BP_SC; ++j) {
                 if (j >= ns) continue;
-                const auto win = dec.window(anchor[j]);
+                const auto win = dec.window(an_cur[j]);
                 const float ws = w ? w[s0 + j] : 1.0f;
-                const long row = (frame_row + s0 + j) * N;
+                const long row = (long)(s0 + j) * N;
 #pragma unroll
                 for (int k = 0; k < BP_PPT; ++k) {
                     int idx;
@@ -203,12 +262,15 @@ __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c
                 }
             }
         }
+        if (more) stage_store(i + 1, an_next, buf ^ 1);
+        __syncthreads();
 #pragma unroll
         for (int j = 0; j < BP_SC; ++j) {
+            an_cur[j] = an_next[j];
+            pr_next[j] = pr_next2[j];
 #pragma unroll
             for (int k = 0; k < BP_PPT; ++k) cur[j][k] = nxt[j][k];
         }
-        __syncthreads();  // windows and anchors are rewritten by the next chunk
     }
 
     float *__restrict__ img = J.img;

@@ -64,53 +64,66 @@ __device__ __forceinline__ float raw_at(const void *sig, long row, int i, int N)
     else return __half2float(static_cast<const __half *>(sig)[row + i]);
 }
 
-// Stage the window [A, A + BB_WS) of one (sensor, frame) row, 8 samples per call.
+// Eight window samples s[i0 .. i0+7] of one (sensor, frame) row (plus s[i0+8]
+// for FP16, whose pairs overlap), loaded into registers; indices outside the
+// record are clamped to it.
+struct Raw8 {
+    uint4 q;      // FP16: 8 halves; FP32: samples 0..3
+    uint4 q2;     // FP32: samples 4..7
+    uint32_t h8;  // FP16: sample 8
+};
+
 template <int SFMT>
-__device__ __forceinline__ void stage8(const void *sig, long row, int i0, int N, uint32_t *dst) {
+__device__ __forceinline__ void load8(const void *sig, long row, int i0, int N, Raw8 &r) {
     if constexpr (SFMT == PAT_SIG_F16) {
         const unsigned short *h = static_cast<const unsigned short *>(sig) + row;
-        uint4 q;
-        uint32_t h8;
         if (i0 >= 0 && i0 + 8 < N) {
-            q = *reinterpret_cast<const uint4 *>(h + i0);
-            h8 = h[i0 + 8];
+            r.q = *reinterpret_cast<const uint4 *>(h + i0);
+            r.h8 = h[i0 + 8];
         } else {
             uint32_t v[9];
 #pragma unroll
             for (int m = 0; m < 9; ++m) v[m] = h[min(max(i0 + m, 0), N - 1)];
-            q.x = v[0] | (v[1] << 16);
-            q.y = v[2] | (v[3] << 16);
-            q.z = v[4] | (v[5] << 16);
-            q.w = v[6] | (v[7] << 16);
-            h8 = v[8];
+            r.q.x = v[0] | (v[1] << 16);
+            r.q.y = v[2] | (v[3] << 16);
+            r.q.z = v[4] | (v[5] << 16);
+            r.q.w = v[6] | (v[7] << 16);
+            r.h8 = v[8];
         }
-        // overlapping pairs (s[j], s[j+1]) for j = i0 .. i0+7
+    } else {
+        const float *x = static_cast<const float *>(sig) + row;
+        if (i0 >= 0 && i0 + 8 <= N) {
+            r.q = *reinterpret_cast<const uint4 *>(x + i0);
+            r.q2 = *reinterpret_cast<const uint4 *>(x + i0 + 4);
+        } else {
+            uint32_t v[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) v[m] = __float_as_uint(x[min(max(i0 + m, 0), N - 1)]);
+            r.q = make_uint4(v[0], v[1], v[2], v[3]);
+            r.q2 = make_uint4(v[4], v[5], v[6], v[7]);
+        }
+    }
+}
+
+// Store eight loaded samples at dst: FP32 as is; FP16 as the overlapping pairs
+// (s[j], s[j+1]) for j = i0 .. i0+7.
+template <int SFMT>
+__device__ __forceinline__ void store8(const Raw8 &r, uint32_t *dst) {
+    if constexpr (SFMT == PAT_SIG_F16) {
         uint4 e, o;
-        e.x = q.x;
-        e.y = __builtin_amdgcn_alignbyte(q.y, q.x, 2);
-        e.z = q.y;
-        e.w = __builtin_amdgcn_alignbyte(q.z, q.y, 2);
-        o.x = q.z;
-        o.y = __builtin_amdgcn_alignbyte(q.w, q.z, 2);
-        o.z = q.w;
-        o.w = (q.w >> 16) | (h8 << 16);
+        e.x = r.q.x;
+        e.y = __builtin_amdgcn_alignbyte(r.q.y, r.q.x, 2);
+        e.z = r.q.y;
+        e.w = __builtin_amdgcn_alignbyte(r.q.z, r.q.y, 2);
+        o.x = r.q.z;
+        o.y = __builtin_amdgcn_alignbyte(r.q.w, r.q.z, 2);
+        o.z = r.q.w;
+        o.w = (r.q.w >> 16) | (r.h8 << 16);
         reinterpret_cast<uint4 *>(dst)[0] = e;
         reinterpret_cast<uint4 *>(dst)[1] = o;
     } else {
-        const float *x = static_cast<const float *>(sig) + row;
-        float4 a, b;
-        if (i0 >= 0 && i0 + 8 <= N) {
-            a = *reinterpret_cast<const float4 *>(x + i0);
-            b = *reinterpret_cast<const float4 *>(x + i0 + 4);
-        } else {
-            float v[8];
-#pragma unroll
-            for (int m = 0; m < 8; ++m) v[m] = x[min(max(i0 + m, 0), N - 1)];
-            a = make_float4(v[0], v[1], v[2], v[3]);
-            b = make_float4(v[4], v[5], v[6], v[7]);
-        }
-        reinterpret_cast<float4 *>(dst)[0] = a;
-        reinterpret_cast<float4 *>(dst)[1] = b;
+        reinterpret_cast<uint4 *>(dst)[0] = r.q;
+        reinterpret_cast<uint4 *>(dst)[1] = r.q2;
     }
 }
 
@@ -158,37 +171,62 @@ __global__ void __launch_bounds__(BB_THREADS) k_bp_batch(const uint32_t *__restr
 #pragma unroll
     for (int f = 0; f < BB_FB; ++f) acc[f] = 0.0f;
 
-    // window start for sensor s: 8-aligned, reaching BB_HALF samples below the probe delay
-    auto anchor_of = [&](int s) -> int {
+    // window start for sensor s: 8-aligned, reaching BB_HALF samples below
+    // the delay of the workgroup's first pixel (the probe)
+    auto probe = [&](int s) -> uint32_t { return s < s_end ? tab[(long)s * P + pbase] : 0xFFFFFFFFu; };
+    auto anchor_of = [&](uint32_t pr) -> int {
         int n;
         float a;
-        if (dec.decode(tab[(long)s * P + pbase], N, n, a)) return floor8(n - BB_HALF - 1);
-        return 0;
+        return dec.decode(pr, N, n, a) ? floor8(n - BB_HALF - 1) : 0;
     };
-    auto stage = [&](int s, int A, int buf) {
-        for (int idx = tid; idx < nf * BB_CHUNKS; idx += BB_THREADS) {
-            const int f = idx / BB_CHUNKS, k = idx % BB_CHUNKS;
-            const long row = ((long)(f0 + f) * S + s) * N;
-            stage8<SFMT>(sig, row, A + 8 * k, N, &win[buf][f][8 * k]);
+    constexpr int NSLOT = (BB_FB * BB_CHUNKS + BB_THREADS - 1) / BB_THREADS;
+    Raw8 rr[NSLOT];
+    // window loads of sensor s into registers, all issued together
+    auto stage_load = [&](int s, int A) {
+#pragma unroll
+        for (int r = 0; r < NSLOT; ++r) {
+            const int idx = tid + r * BB_THREADS;
+            if (idx < nf * BB_CHUNKS) {
+                const int f = idx / BB_CHUNKS, k = idx % BB_CHUNKS;
+                load8<SFMT>(sig, ((long)(f0 + f) * S + s) * N, A + 8 * k, N, rr[r]);
+            }
+        }
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < NSLOT; ++r) {
+            const int idx = tid + r * BB_THREADS;
+            if (idx < nf * BB_CHUNKS) {
+                const int f = idx / BB_CHUNKS, k = idx % BB_CHUNKS;
+                store8<SFMT>(rr[r], &win[buf][f][8 * k]);
+            }
         }
     };
 
+    // pipeline: while sensor s is gathered from LDS, the window loads of s+1,
+    // its delays and the probe of s+2 are in flight
     int A = 0;
+    uint32_t pr1 = 0xFFFFFFFFu;
+    uint32_t tcur = 0xFFFFFFFFu;
     if (s_begin < s_end) {
-        A = anchor_of(s_begin);
-        stage(s_begin, A, 0);
+        A = anchor_of(probe(s_begin));
+        stage_load(s_begin, A);
+        tcur = pix_ok ? tab[(long)s_begin * P + p] : 0xFFFFFFFFu;
+        pr1 = probe(s_begin + 1);
+        stage_store(0);
     }
-    uint32_t tcur = (pix_ok && s_begin < s_end) ? tab[(long)s_begin * P + p] : 0xFFFFFFFFu;
     __syncthreads();
 
     for (int s = s_begin; s < s_end; ++s) {
         const int buf = (s - s_begin) & 1;
         const bool more = s + 1 < s_end;
-        const uint32_t tnext = (more && pix_ok) ? tab[(long)(s + 1) * P + p] : 0xFFFFFFFFu;
+        uint32_t tnext = 0xFFFFFFFFu, pr2 = 0xFFFFFFFFu;
         int Anext = A;
         if (more) {
-            Anext = anchor_of(s + 1);
-            stage(s + 1, Anext, buf ^ 1);
+            Anext = anchor_of(pr1);
+            stage_load(s + 1, Anext);
+            tnext = pix_ok ? tab[(long)(s + 1) * P + p] : 0xFFFFFFFFu;
+            pr2 = probe(s + 2);
         }
         int n;
         float a;
@@ -249,8 +287,10 @@ __global__ void __launch_bounds__(BB_THREADS) k_bp_batch(const uint32_t *__restr
                 }
             }
         }
+        if (more) stage_store(buf ^ 1);
         tcur = tnext;
         A = Anext;
+        pr1 = pr2;
         __syncthreads();
     }
 

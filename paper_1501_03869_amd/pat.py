@@ -275,9 +275,10 @@ class Server:
     def submit(self, map_id: int, frame: np.ndarray, scale: float = 1.0, nonblocking: bool = False) -> int:
         want = np.float16 if self.sig_fmt == SIG_F16 else np.float32
         f = np.ascontiguousarray(frame, dtype=want)
-        S, P, N = self._geo[map_id]
-        if f.shape != (S, N):
-            raise ValueError(f"frame must be {(S, N)}, got {f.shape}")
+        if map_id in self._geo:  # unknown ids are reported by the library
+            S, P, N = self._geo[map_id]
+            if f.shape != (S, N):
+                raise ValueError(f"frame must be {(S, N)}, got {f.shape}")
         t = C.c_uint64()
         check(lib().pat_server_submit(self.h, int(map_id), f.ctypes.data, C.c_float(scale), 1 if nonblocking else 0,
                                       C.byref(t)))
