@@ -273,6 +273,26 @@ int orc_tables(int nx, int ny, double h, const float *speed, const double *sxy, 
     return rc;
 }
 
+/* Conventional back projection's delays (Section III: the constant-speed
+ * comparison): T[s][p] = |x_pix[p] - s| / c, straight rays in a homogeneous
+ * medium of speed c.  Returns 0, or -1 on a bad pixel index or c <= 0. */
+int orc_tables_const(int nx, int ny, double h, double c, const double *sxy, int S, const int32_t *pix, long P,
+                     double *table) {
+    long n = (long)nx * ny;
+    if (!(c > 0.0)) return -1;
+    for (long p = 0; p < P; ++p)
+        if (pix[p] < 0 || pix[p] >= n) return -1;
+    double x0 = -0.5 * (nx - 1) * h, y0 = -0.5 * (ny - 1) * h;
+    for (int s = 0; s < S; ++s) {
+        for (long p = 0; p < P; ++p) {
+            int i = pix[p] % nx, j = pix[p] / nx;
+            double dx = (x0 + i * h) - sxy[2 * s], dy = (y0 + j * h) - sxy[2 * s + 1];
+            table[(long)s * P + p] = sqrt(dx * dx + dy * dy) / c;
+        }
+    }
+    return 0;
+}
+
 /* -------------------------------------------------------------- filter */
 
 /* b[r][n] = p[r][n] - t_n * D[r][n], t_n = t0 + n dt, with D the central

@@ -50,6 +50,8 @@ def lib():
         L.orc_seed.restype = C.c_int
         L.orc_tables.argtypes = [C.c_int, C.c_int, C.c_double, _fp, _dp, C.c_int, _i32, C.c_long, _dp, C.c_int]
         L.orc_tables.restype = C.c_int
+        L.orc_tables_const.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, C.c_int, _i32, C.c_long, _dp]
+        L.orc_tables_const.restype = C.c_int
         L.orc_filter.argtypes = [_dp, C.c_long, C.c_int, C.c_double, C.c_double, _dp]
         L.orc_filter.restype = None
         L.orc_gather.argtypes = [_dp, _dp, C.c_void_p, C.c_int, C.c_long, C.c_int, C.c_int, C.c_double,
@@ -116,6 +118,16 @@ def tables(speed: np.ndarray, h: float, sensors: np.ndarray, pix: np.ndarray, nt
         raise ValueError("orc_tables: invalid input")
     if rc:
         raise MemoryError("orc_tables")
+    return out
+
+
+def tables_const(nx: int, ny: int, h: float, c: float, sensors: np.ndarray, pix: np.ndarray) -> np.ndarray:
+    """Straight-ray delays |x - s| / c of the conventional back projection."""
+    sxy = np.ascontiguousarray(sensors, dtype=np.float64)
+    pix = np.ascontiguousarray(pix, dtype=np.int32)
+    out = np.empty((sxy.shape[0], pix.shape[0]), dtype=np.float64)
+    if lib().orc_tables_const(int(nx), int(ny), float(h), float(c), sxy, sxy.shape[0], pix, pix.shape[0], out):
+        raise ValueError("orc_tables_const: invalid input")
     return out
 
 

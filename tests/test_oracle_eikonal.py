@@ -286,3 +286,23 @@ def test_tables_reject_bad_input(orc):
         orc.tables(geo.speed, geo.h, geo.sensors * 100, geo.pix)
     with pytest.raises(ValueError):
         orc.tables(geo.speed, geo.h, geo.sensors, np.array([geo.nx * geo.ny], np.int32))
+
+
+def test_const_speed_tables(orc):
+    # conventional back projection's straight-ray delays: the fast-marching
+    # table of a homogeneous medium converges to them (first order), and they
+    # are the exact Euclidean distances over c
+    n, h, c = 81, 0.2e-3, 1560.0
+    x, y = inputs.node_coords(n, n, h)
+    sens = np.array([[x[3], y[70]], [0.4 * h, -0.3 * h]])
+    pix = np.arange(n * n, dtype=np.int32)[::7]
+    T = orc.tables_const(n, n, h, c, sens, pix)
+    X, Y = x[pix % n], y[pix // n]
+    for s in range(2):
+        np.testing.assert_allclose(T[s], np.hypot(X - sens[s, 0], Y - sens[s, 1]) / c, rtol=1e-12)
+    F = orc.tables(np.full((n, n), c, np.float32), h, sens, pix)
+    far = T > 10 * h / c
+    assert np.all(F >= T * (1 - 1e-12))
+    assert ((F - T)[far] / T[far]).max() < 0.08  # first-order error of the discrete eikonal
+    with pytest.raises(ValueError):
+        orc.tables_const(n, n, h, -1.0, sens, pix)
