@@ -180,6 +180,21 @@ int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void
                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
                     int N, int F, double t0, double dt, float *d_img, void *stream);
 
+/*
+ * Conventional back projection (Section III's comparison reconstruction): the
+ * same filtered delay-and-sum as pat_backproject, with the straight-ray delay
+ * t = |x_pix[p] - s| / c of a homogeneous medium of speed c computed per
+ * gather instead of read from a table.  d_pix are node indices on the grid
+ * convention above (used only as coordinates); h_sensor_xy is host float64
+ * [S][2] metres (copied stream-ordered into context memory).  Delays are
+ * computed in FP32.  Other arguments as pat_backproject; scratch as
+ * pat_backproject with the same S, P, F.
+ */
+int pat_backproject_const(pat_ctx *ctx, int nx, int ny, double h, double c, const double *h_sensor_xy, int S,
+                          const int32_t *d_pix, int P, const void *d_sig, int sig_fmt, int sig_is_filtered,
+                          const float *d_frame_scale, const float *d_w, int N, int F, double t0, double dt,
+                          float *d_img, void *stream);
+
 /* ------------------------------------------------------------------ serving
  *
  * A frame server keeps each speed map's delay table resident in HBM (the

@@ -80,6 +80,7 @@ extern "C" int pat_ctx_destroy(pat_ctx *ctx) {
     (void)hipDeviceSynchronize();
     ctx->gather_scratch.release();
     ctx->gather_done.release();
+    ctx->sensors.release();
     ctx->eik_tq.release();
     ctx->eik_f.release();
     ctx->eik_flags.release();
@@ -186,4 +187,33 @@ extern "C" int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt,
     if (S > 0 && (!d_table || !d_sig)) return pat_fail(PAT_EINVAL, "null table or signal pointer");
     return pat_launch_backproject(ctx, d_table, table_fmt, d_sig, sig_fmt, sig_is_filtered, d_frame_scale, d_w, S, P,
                                   N, F, t0, dt, d_img, (hipStream_t)stream);
+}
+
+extern "C" int pat_backproject_const(pat_ctx *ctx, int nx, int ny, double h, double c, const double *h_sensor_xy,
+                                     int S, const int32_t *d_pix, int P, const void *d_sig, int sig_fmt,
+                                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int N, int F,
+                                     double t0, double dt, float *d_img, void *stream) {
+    int rc = pat_make_current(ctx);
+    if (rc) return rc;
+    if (nx < 1 || ny < 1 || !finite_pos(h) || !finite_pos(c)) return pat_fail(PAT_EINVAL, "need a grid, h > 0 and c > 0");
+    if (S < 0 || P < 0 || F < 0) return pat_fail(PAT_EINVAL, "negative size");
+    if (N < 2 || !finite_pos(dt) || !std::isfinite(t0)) return pat_fail(PAT_EINVAL, "need N >= 2, finite t0, dt > 0");
+    if (sig_fmt != PAT_SIG_F32 && sig_fmt != PAT_SIG_F16) return pat_fail(PAT_EINVAL, "unknown signal format %d", sig_fmt);
+    if ((long long)S * N > INT32_MAX) return pat_fail(PAT_EINVAL, "sizes too large");
+    if (P == 0 || F == 0) return PAT_OK;
+    if (!d_img || !d_pix || (S > 0 && (!d_sig || !h_sensor_xy))) return pat_fail(PAT_EINVAL, "null pointer");
+    // stream-ordered copy of the sensor positions (as float32) into context memory
+    std::vector<float> sxy((size_t)2 * S);
+    for (int i = 0; i < 2 * S; ++i) {
+        if (!std::isfinite(h_sensor_xy[i])) return pat_fail(PAT_EINVAL, "non-finite sensor position");
+        sxy[(size_t)i] = (float)h_sensor_xy[i];
+    }
+    if (S > 0) {
+        if ((rc = ctx->sensors.grow(sxy.size() * sizeof(float)))) return rc;
+        PAT_HIP(hipMemcpyAsync(ctx->sensors.ptr, sxy.data(), sxy.size() * sizeof(float), hipMemcpyHostToDevice,
+                               (hipStream_t)stream));
+    }
+    return pat_launch_backproject_const(ctx, nx, ny, h, c, static_cast<const float *>(ctx->sensors.ptr), S, d_pix, P,
+                                        d_sig, sig_fmt, sig_is_filtered, d_frame_scale, d_w, N, F, t0, dt, d_img,
+                                        (hipStream_t)stream);
 }

@@ -82,6 +82,11 @@ struct BpJob {
     unsigned int *done;    // this frame's per-chunk completion counters (G > 1)
     int S, P, N, spg, G;
     float t0dt, scale;
+    // straight-ray delays instead of a table (conventional back projection)
+    const int32_t *pix;    // [P] node indices
+    const float *sxy;      // [S][2] sensor positions, metres
+    int nx;
+    float h, x0, y0, inv_c;
 };
 
 // One workgroup's share of one frame: pixel chunk c, sensor group g.
@@ -95,7 +100,7 @@ struct BpJob {
 //             buffer, barrier.
 // So a chunk costs one memory latency overlapped with a chunk of gathers,
 // instead of a chain of dependent loads.
-template <class Delay, int SFMT, bool FILTERED, bool VEC4>
+template <class Delay, int SFMT, bool FILTERED, bool VEC4, bool CONSTC = false>
 __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c, int g) {
     const uint32_t *__restrict__ tab = J.tab;
     const void *__restrict__ sig = J.sig;
@@ -123,11 +128,30 @@ __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c
     float rv[BP_SC][NR];
 
     // delay of the chunk's first pixel to each sensor of chunk i (window probes)
+    // straight-ray delay (seconds, as float bits) of node k to sensor s
+    auto ray = [&](int s, float px, float py) -> uint32_t {
+        const float dx = px - J.sxy[2 * s], dy = py - J.sxy[2 * s + 1];
+        return __float_as_uint(__builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy)) * J.inv_c);
+    };
+    float px[BP_PPT], py[BP_PPT], qx = 0.0f, qy = 0.0f;  // pixel coordinates (conventional BP)
+    if constexpr (CONSTC) {
+#pragma unroll
+        for (int k = 0; k < BP_PPT; ++k) {
+            const int kk = J.pix[min(p0 + k, P - 1)];
+            px[k] = J.x0 + (float)(kk % J.nx) * J.h;
+            py[k] = J.y0 + (float)(kk / J.nx) * J.h;
+        }
+        const int kq = J.pix[pbase];
+        qx = J.x0 + (float)(kq % J.nx) * J.h;
+        qy = J.y0 + (float)(kq / J.nx) * J.h;
+    }
+    // delay of the chunk's first pixel to each sensor of chunk i (window probes)
     auto probe = [&](int i, uint32_t (&pr)[BP_SC]) {
 #pragma unroll
         for (int j = 0; j < BP_SC; ++j) {
             const int s = s_begin + i * BP_SC + j;
-            pr[j] = (i < nchunk && s < s_end) ? tab[(long)s * P + pbase] : 0xFFFFFFFFu;
+            if constexpr (CONSTC) pr[j] = (i < nchunk && s < s_end) ? ray(s, qx, qy) : 0xFFFFFFFFu;
+            else pr[j] = (i < nchunk && s < s_end) ? tab[(long)s * P + pbase] : 0xFFFFFFFFu;
         }
     };
     auto anchors = [&](const uint32_t (&pr)[BP_SC], int (&an)[BP_SC]) {
@@ -142,8 +166,16 @@ __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c
 #pragma unroll
         for (int j = 0; j < BP_SC; ++j) {
             const int s = s_begin + i * BP_SC + j;
-            if (s < s_end) load_delays<VEC4>(tab, (long)s * P, p0, P, v[j]);
-            else { v[j][0] = v[j][1] = v[j][2] = v[j][3] = 0xFFFFFFFFu; }
+            if (s < s_end) {
+                if constexpr (CONSTC) {
+#pragma unroll
+                    for (int k = 0; k < BP_PPT; ++k) v[j][k] = p0 + k < P ? ray(s, px[k], py[k]) : 0xFFFFFFFFu;
+                } else {
+                    load_delays<VEC4>(tab, (long)s * P, p0, P, v[j]);
+                }
+            } else {
+                v[j][0] = v[j][1] = v[j][2] = v[j][3] = 0xFFFFFFFFu;
+            }
         }
     };
     // window samples of chunk i into registers (all loads issued together)
@@ -326,6 +358,31 @@ __global__ void __launch_bounds__(BP_THREADS) k_bp(const uint32_t *__restrict__ 
     bp_block<Delay, SFMT, FILTERED, VEC4>(J, dec, blockIdx.x, blockIdx.y);
 }
 
+// Conventional back projection: straight-ray delays |x - s| / c computed per
+// gather instead of read from a table (no table traffic; ALU bound).
+template <int SFMT, bool FILTERED>
+__global__ void __launch_bounds__(BP_THREADS) k_bp_const(const void *__restrict__ sig, const float *__restrict__ scale,
+                                                         const float *__restrict__ w, int S, int P, int N, int spg,
+                                                         int G, DelayF32 dec, float t0dt, float *__restrict__ part,
+                                                         float *__restrict__ img, unsigned int *__restrict__ done,
+                                                         const int32_t *__restrict__ pix, const float *__restrict__ sxy,
+                                                         int nx, float h, float x0, float y0, float inv_c) {
+    const int f = blockIdx.z;
+    const size_t esz = SFMT == PAT_SIG_F16 ? 2 : 4;
+    BpJob J;
+    J.tab = nullptr;
+    J.sig = static_cast<const char *>(sig) + (size_t)f * S * N * esz;
+    J.w = w;
+    J.part = part ? part + (long)f * G * P : nullptr;
+    J.img = img + (long)f * P;
+    J.done = done ? done + (long)f * gridDim.x : nullptr;
+    J.S = S; J.P = P; J.N = N; J.spg = spg; J.G = G;
+    J.t0dt = t0dt;
+    J.scale = (SFMT == PAT_SIG_F16 && scale) ? scale[f] : 1.0f;
+    J.pix = pix; J.sxy = sxy; J.nx = nx; J.h = h; J.x0 = x0; J.y0 = y0; J.inv_c = inv_c;
+    bp_block<DelayF32, SFMT, FILTERED, false, true>(J, dec, blockIdx.x, blockIdx.y);
+}
+
 // Frames of different geometries in one launch: workgroup b belongs to the
 // last descriptor whose block_begin <= b and covers (chunk, group) of that
 // frame exactly as a single-frame launch would, so a frame's image does not
@@ -478,6 +535,42 @@ int pat_launch_bp_multi(const pat_bp_desc *d_descs, int nd, int total_blocks, in
         else { if (vec4) PAT_BPM(PAT_TABLE_Q16, PAT_SIG_F16, true); else PAT_BPM(PAT_TABLE_Q16, PAT_SIG_F16, false); }
     }
 #undef PAT_BPM
+    PAT_HIP(hipGetLastError());
+    return PAT_OK;
+}
+
+int pat_launch_backproject_const(pat_ctx *ctx, int nx, int ny, double h, double c, const float *d_sxy, int S,
+                                 const int32_t *d_pix, int P, const void *sig, int sig_fmt, int sig_is_filtered,
+                                 const float *frame_scale, const float *w, int N, int F, double t0, double dt,
+                                 float *img, hipStream_t st) {
+    (void)ny;
+    if (S == 0) {
+        PAT_HIP(hipMemsetAsync(img, 0, (size_t)P * F * sizeof(float), st));
+        return PAT_OK;
+    }
+    const BpShape sh = bp_shape(S, P, F);
+    float *part = nullptr;
+    unsigned int *done = nullptr;
+    if (sh.groups > 1) {
+        int rc = pat_gather_scratch(ctx, P, F, single_part_bytes(S, P, F), &part, &done);
+        if (rc) return rc;
+    }
+    DelayF32 d;
+    const double inv = 1.0 / dt;
+    d.inv_hi = (float)inv;
+    d.inv_lo = (float)(inv - (double)d.inv_hi);
+    d.off = (float)(-t0 / dt);
+    d.umax = (float)(N - 1);
+    const dim3 grid(sh.chunks, sh.groups, F);
+    const float t0dt = (float)(t0 / dt);
+    const float x0 = (float)(-0.5 * (nx - 1) * h), y0 = (float)(-0.5 * (ny - 1) * h);
+    const float inv_c = (float)(1.0 / c);
+#define PAT_BPC(SF, FI)                                                                                         \
+    k_bp_const<SF, FI><<<grid, BP_THREADS, 0, st>>>(sig, frame_scale, w, S, P, N, sh.spg, sh.groups, d, t0dt, \
+                                                    part, img, done, d_pix, d_sxy, nx, (float)h, x0, y0, inv_c)
+    if (sig_fmt == PAT_SIG_F32) { if (sig_is_filtered) PAT_BPC(PAT_SIG_F32, true); else PAT_BPC(PAT_SIG_F32, false); }
+    else { if (sig_is_filtered) PAT_BPC(PAT_SIG_F16, true); else PAT_BPC(PAT_SIG_F16, false); }
+#undef PAT_BPC
     PAT_HIP(hipGetLastError());
     return PAT_OK;
 }

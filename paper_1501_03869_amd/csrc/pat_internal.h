@@ -33,6 +33,8 @@ struct pat_ctx {
     pat_devbuf gather_scratch;
     // gather completion counters (kept at zero between launches)
     pat_devbuf gather_done;
+    // sensor positions (float32) for the straight-ray gather
+    pat_devbuf sensors;
     // eikonal working memory
     pat_devbuf eik_tq, eik_f, eik_flags, eik_lists, eik_seeds, eik_count;
     uint32_t *eik_count_host = nullptr;  // pinned, 2 counters
@@ -77,6 +79,10 @@ bool pat_batch_eligible(int sig_fmt, int N, int F, const void *sig);
 int pat_launch_backproject_batch(pat_ctx *ctx, const void *table, int table_fmt, const void *sig, int sig_fmt,
                                  int sig_is_filtered, const float *frame_scale, const float *w, int S, int P, int N,
                                  int F, double t0, double dt, float *img, hipStream_t st);
+int pat_launch_backproject_const(pat_ctx *ctx, int nx, int ny, double h, double c, const float *d_sxy, int S,
+                                 const int32_t *d_pix, int P, const void *sig, int sig_fmt, int sig_is_filtered,
+                                 const float *frame_scale, const float *w, int N, int F, double t0, double dt,
+                                 float *img, hipStream_t st);
 int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const void *sig, int sig_fmt,
                            int sig_is_filtered, const float *frame_scale, const float *w, int S, int P,
                            int N, int F, double t0, double dt, float *img, hipStream_t st);
