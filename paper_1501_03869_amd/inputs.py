@@ -167,6 +167,15 @@ def config(name: str) -> Geometry:
     raise KeyError(name)
 
 
+def perturb_speed(speed: np.ndarray, seed: int, frac: float = 0.017) -> np.ndarray:
+    """Speed map with uncorrelated Gaussian errors added at every node, mean and
+    standard deviation both frac * max(speed) (the robustness study of the
+    paper's Section III uses 1.7 % for both)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = float(np.max(speed)) * frac
+    return (speed.astype(np.float64) + m + m * rng.standard_normal(speed.shape)).astype(np.float32)
+
+
 def paper_like_speed(seed: int, nx: int, ny: int, h: float) -> np.ndarray:
     """A fresh seeded skull map with the paper-scale generator (new maps in serving)."""
     return skull_speed(seed, nx, ny, h)

@@ -435,3 +435,29 @@ def test_fmm_bp_beats_conventional_bp(ctx, orc):
 
     print(f"[compare] correlation with the phantom: FMM-BP {corr(fmm):.3f}, conventional {corr(conv):.3f}", flush=True)
     assert corr(fmm) > corr(conv) + 0.05
+
+
+def test_speed_error_robustness(ctx, orc):
+    # the paper's robustness study: tables rebuilt from a speed map carrying
+    # 1.7 % (of max) uncorrelated Gaussian errors with a 1.7 % mean still
+    # reconstruct the phantom about as well, and better than one constant speed
+    geo = inputs.config("paper")
+    T = oracle_table(orc, geo)
+    p = inputs.frame_for(geo, T, 5)
+    nodes, _ = inputs.segment_phantom(inputs.SEED_PHANTOM + 5, geo.nx, geo.ny, geo.h)
+    truth = np.zeros(geo.nx * geo.ny)
+    truth[nodes] = 1.0
+    truth = truth[geo.pix]
+    bad = inputs.perturb_speed(geo.speed, 6000)
+    Tbad = ctx.eikonal_tables(dev(bad), geo.h, geo.sensors, dev(geo.pix))
+    Tgood = ctx.eikonal_tables(dev(geo.speed), geo.h, geo.sensors, dev(geo.pix))
+    imgs = {
+        "true map": ctx.backproject(Tgood, dev(p), geo.dt, filtered=False).cpu().numpy(),
+        "1.7% errors": ctx.backproject(Tbad, dev(p), geo.dt, filtered=False).cpu().numpy(),
+        "constant 1560": ctx.backproject_const(geo.nx, geo.ny, geo.h, 1560.0, geo.sensors, dev(geo.pix), dev(p),
+                                               geo.dt, filtered=False).cpu().numpy(),
+    }
+    corr = {k: float(np.corrcoef(np.maximum(v, 0), truth)[0, 1]) for k, v in imgs.items()}
+    print(f"[robustness] correlation with the phantom: {corr}", flush=True)
+    assert corr["1.7% errors"] > corr["constant 1560"]
+    assert corr["1.7% errors"] > 0.7 * corr["true map"]
