@@ -435,19 +435,25 @@ void pat_server::scheduler() {
         if (rc == PAT_OK && part_need > slot->part_cap) {
             if (slot->d_part) (void)hipFree(slot->d_part);
             slot->d_part = nullptr;
+            const size_t old = slot->part_cap * sizeof(float);
             slot->part_cap = 0;
             if (hipMalloc((void **)&slot->d_part, part_need * sizeof(float)) != hipSuccess) rc = PAT_ENOMEM;
             else slot->part_cap = part_need;
+            std::lock_guard<std::mutex> lk(mu);
+            used = used - std::min(used, old) + slot->part_cap * sizeof(float);
         }
         if (rc == PAT_OK && done_need > slot->done_cap) {
             if (slot->d_done) (void)hipFree(slot->d_done);
             slot->d_done = nullptr;
+            const size_t old = slot->done_cap * sizeof(unsigned int);
             slot->done_cap = 0;
             if (hipMalloc((void **)&slot->d_done, done_need * sizeof(unsigned int)) != hipSuccess ||
                 hipMemset(slot->d_done, 0, done_need * sizeof(unsigned int)) != hipSuccess)
                 rc = PAT_ENOMEM;
             else
                 slot->done_cap = done_need;
+            std::lock_guard<std::mutex> lk(mu);
+            used = used - std::min(used, old) + slot->done_cap * sizeof(unsigned int);
         }
         if (rc == PAT_OK) {
             for (int i = 0; i < nd; ++i) {
