@@ -461,3 +461,22 @@ def test_speed_error_robustness(ctx, orc):
     print(f"[robustness] correlation with the phantom: {corr}", flush=True)
     assert corr["1.7% errors"] > corr["constant 1560"]
     assert corr["1.7% errors"] > 0.7 * corr["true map"]
+
+
+def test_large_gather_full_size_sampled(ctx, orc):
+    # the 1024-sensor, 823592-pixel, 4096-sample workload at full size, with
+    # straight-ray delays (compact, realistic spread) from the oracle; the
+    # oracle recomputes 3000 sampled pixels one by one
+    from paper_1501_03869_amd import pat
+    geo = inputs.config("large")
+    pix = pat.tile_order(geo.nx, geo.ny, geo.pix, 32, 32)
+    T = np.empty((geo.S, geo.P), np.float32)
+    for s0 in range(0, geo.S, 128):
+        T[s0:s0 + 128] = orc.tables_const(geo.nx, geo.ny, geo.h, 1540.0, geo.sensors[s0:s0 + 128], pix)
+    p = inputs.random_signals(77, geo.S, geo.n_samples)
+    got = ctx.backproject(dev(T), dev(p), geo.dt, filtered=False).cpu().numpy()
+    sample = np.random.default_rng(78).choice(geo.P, 3000, replace=False)
+    ref = orc.backproject(np.ascontiguousarray(T[:, sample]).astype(np.float64), p, geo.dt)
+    err = rel_l2(got[sample], ref)
+    print(f"[gather] large full size, 3000 sampled pixels: rel L2 {err:.3e}", flush=True)
+    assert err <= IMG_TOL
