@@ -35,7 +35,8 @@ constexpr int BP_CHUNK = BP_THREADS * BP_PPT;      // pixels per workgroup
 constexpr int BP_SC = 8;                           // sensors staged together
 constexpr int BP_W = 512;                          // window samples per sensor
 constexpr int BP_RAW = BP_W + 2;                   // raw samples incl. both neighbours
-constexpr int BP_TARGET_BLOCKS = 1024;             // workgroups wanted per launch
+// Workgroups the chip holds at once: 256 CUs x 3 (48 KiB of LDS each).
+constexpr int BP_RESIDENT = 256 * 3;
 
 struct BpShape {
     int chunks;  // workgroups along pixels
@@ -43,14 +44,23 @@ struct BpShape {
     int spg;     // sensors per group (a multiple of BP_SC unless one group)
 };
 
+// Sensor groups per pixel chunk.  Problems whose pixel chunks fit in one wave
+// of resident workgroups split the sensors to fill that wave; larger ones are
+// cut into at least four waves (each workgroup keeping >= 4 sensor chunks to
+// pipeline) so that the last, partly filled wave costs little.
 BpShape bp_shape(int S, int P, int F) {
     BpShape s;
     s.chunks = (P + BP_CHUNK - 1) / BP_CHUNK;
     const long per_group = (long)s.chunks * std::max(F, 1);
     const int S1 = std::max(S, 1);
-    int G = (int)std::min<long>((BP_TARGET_BLOCKS + per_group - 1) / per_group, (S1 + BP_SC - 1) / BP_SC);
-    G = std::max(G, 1);
-    int spg = (S1 + G - 1) / G;
+    const int max_groups = std::max(1, (S1 + BP_SC - 1) / BP_SC);
+    long G = BP_RESIDENT / per_group;
+    if (G < 1) {
+        const long many = (4L * BP_RESIDENT + per_group - 1) / per_group;
+        G = std::min<long>(many, std::max(1, S1 / (4 * BP_SC)));
+    }
+    G = std::max<long>(1, std::min<long>(G, max_groups));
+    int spg = (int)((S1 + G - 1) / G);
     spg = ((spg + BP_SC - 1) / BP_SC) * BP_SC;
     s.spg = spg;
     s.groups = (S1 + spg - 1) / spg;

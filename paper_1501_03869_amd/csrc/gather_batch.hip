@@ -32,7 +32,7 @@ constexpr int BB_FB = 16;                   // frames per workgroup
 constexpr int BB_HALF = 128;                // window reach around the probe delay
 constexpr int BB_WS = 2 * BB_HALF + 16;     // staged samples per (sensor, frame)
 constexpr int BB_CHUNKS = BB_WS / 8;        // 8-sample copies per (sensor, frame)
-constexpr int BB_TARGET_BLOCKS = 1024;
+constexpr int BB_RESIDENT = 256 * 4;          // workgroups resident at once (35 KiB of LDS each)
 
 struct BbShape {
     int chunks, fgroups, groups, spg;
@@ -44,7 +44,8 @@ BbShape bb_shape(int S, int P, int F) {
     s.fgroups = (F + BB_FB - 1) / BB_FB;
     const long base = (long)s.chunks * s.fgroups;
     const int S1 = std::max(S, 1);
-    int G = (int)std::min<long>((BB_TARGET_BLOCKS + base - 1) / base, std::min(S1, 8));
+    // as many sensor groups as fit in one wave of resident workgroups (at most 8)
+    int G = (int)std::min<long>(std::max<long>(1, BB_RESIDENT / base), std::min(S1, 8));
     G = std::max(G, 1);
     s.spg = (S1 + G - 1) / G;
     s.groups = (S1 + s.spg - 1) / s.spg;
