@@ -138,7 +138,8 @@ int pat_table_to_q16(pat_ctx *ctx, const float *d_table, int64_t n, double t0, d
 
 /*
  * Host helper: reorder ROI node indices tile-major (tiles of tile_w x tile_h
- * nodes, tiles row-major, Z-order (Morton) inside a tile), so that every
+ * nodes; tile rows alternately left to right and right to left, so that
+ * consecutive tiles are neighbours; Z-order (Morton) inside a tile), so that every
  * aligned run of 64, 256 or 1024 pixels of a 32x32-tiled ROI is a compact
  * square or 2:1 patch: the gather's pixel blocks then need short time
  * windows.  Stable for equal keys; h_pix_out may not alias h_pix.  Host only.

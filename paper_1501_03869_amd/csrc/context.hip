@@ -131,7 +131,10 @@ extern "C" int pat_tile_order(int nx, int ny, const int32_t *h_pix, int P, int t
         int32_t k = h_pix[p];
         if (k < 0 || k >= n) return pat_fail(PAT_EINVAL, "pixel %d index %d out of range", p, k);
         int i = k % nx, j = k / nx;
-        uint64_t tile = (uint64_t)(j / tile_h) * tx + (i / tile_w);
+        // tile rows run alternately left to right and right to left, so that
+        // consecutive tiles are always neighbours
+        const int trow = j / tile_h, tcol = (trow & 1) ? tx - 1 - i / tile_w : i / tile_w;
+        uint64_t tile = (uint64_t)trow * tx + tcol;
         key[(size_t)p] = { (tile << 32) | morton2((uint32_t)(i % tile_w), (uint32_t)(j % tile_h)), k };
     }
     std::stable_sort(key.begin(), key.end(),

@@ -35,6 +35,8 @@ constexpr int BP_CHUNK = BP_THREADS * BP_PPT;      // pixels per workgroup
 constexpr int BP_SC = 8;                           // sensors staged together
 constexpr int BP_W = 512;                          // window samples per sensor
 constexpr int BP_RAW = BP_W + 2;                   // raw samples incl. both neighbours
+constexpr int BP_NPROBE = 16;                      // window probes per sensor: every 64th pixel
+constexpr int BP_MARGIN = 40;                      // window start below the smallest probed delay
 // Workgroups the chip holds at once: 256 CUs x 3 (48 KiB of LDS each).
 constexpr int BP_RESIDENT = 256 * 3;
 
@@ -143,7 +145,7 @@ __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c
         const float dx = px - J.sxy[2 * s], dy = py - J.sxy[2 * s + 1];
         return __float_as_uint(__builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy)) * J.inv_c);
     };
-    float px[BP_PPT], py[BP_PPT], qx = 0.0f, qy = 0.0f;  // pixel coordinates (conventional BP)
+    float px[BP_PPT], py[BP_PPT], qx[4], qy[4];  // pixel coordinates (conventional BP)
     if constexpr (CONSTC) {
 #pragma unroll
         for (int k = 0; k < BP_PPT; ++k) {
@@ -151,17 +153,34 @@ __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c
             px[k] = J.x0 + (float)(kk % J.nx) * J.h;
             py[k] = J.y0 + (float)(kk / J.nx) * J.h;
         }
-        const int kq = J.pix[pbase];
-        qx = J.x0 + (float)(kq % J.nx) * J.h;
-        qy = J.y0 + (float)(kq / J.nx) * J.h;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kq = J.pix[min(pbase + q * (BP_CHUNK - 1) / 3, P - 1)];
+            qx[q] = J.x0 + (float)(kq % J.nx) * J.h;
+            qy[q] = J.y0 + (float)(kq / J.nx) * J.h;
+        }
     }
-    // delay of the chunk's first pixel to each sensor of chunk i (window probes)
+    // Window probes of chunk i: per sensor, the smallest of the delays of
+    // every 64th pixel of the chunk.  Delays are compared as raw 32-bit
+    // patterns (a scalar min): for non-negative float32 seconds and for 16.16
+    // indices the order of the patterns is the order of the delays, and the
+    // non-contributing codes (NaN, negative, the 16.16 sentinel) sort last.
     auto probe = [&](int i, uint32_t (&pr)[BP_SC]) {
 #pragma unroll
         for (int j = 0; j < BP_SC; ++j) {
             const int s = s_begin + i * BP_SC + j;
-            if constexpr (CONSTC) pr[j] = (i < nchunk && s < s_end) ? ray(s, qx, qy) : 0xFFFFFFFFu;
-            else pr[j] = (i < nchunk && s < s_end) ? tab[(long)s * P + pbase] : 0xFFFFFFFFu;
+            uint32_t m = 0xFFFFFFFFu;
+            if (i < nchunk && s < s_end) {
+                if constexpr (CONSTC) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) m = min(m, ray(s, qx[q], qy[q]));
+                } else {
+#pragma unroll
+                    for (int q = 0; q < BP_NPROBE; ++q)
+                        m = min(m, tab[(long)s * P + min(pbase + q * (BP_CHUNK / BP_NPROBE), P - 1)]);
+                }
+            }
+            pr[j] = m;
         }
     };
     auto anchors = [&](const uint32_t (&pr)[BP_SC], int (&an)[BP_SC]) {
@@ -169,7 +188,7 @@ __device__ __forceinline__ void bp_block(const BpJob &J, const Delay &dec, int c
         for (int j = 0; j < BP_SC; ++j) {
             int n;
             float a;
-            an[j] = dec.decode(pr[j], N, n, a) ? n - BP_W / 2 : 0;
+            an[j] = dec.decode(pr[j], N, n, a) ? n - BP_MARGIN : 0;
         }
     };
     auto delays = [&](int i, uint32_t (&v)[BP_SC][BP_PPT]) {

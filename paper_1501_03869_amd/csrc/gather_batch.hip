@@ -29,8 +29,9 @@ using namespace pat_gather;
 
 constexpr int BB_THREADS = 256;
 constexpr int BB_FB = 16;                   // frames per workgroup
-constexpr int BB_HALF = 128;                // window reach around the probe delay
-constexpr int BB_WS = 2 * BB_HALF + 16;     // staged samples per (sensor, frame)
+constexpr int BB_WS = 272;                  // staged samples per (sensor, frame)
+constexpr int BB_NPROBE = 8;                // window probes per sensor: every 32nd pixel
+constexpr int BB_MARGIN = 40;               // window start below the smallest probed delay
 constexpr int BB_CHUNKS = BB_WS / 8;        // 8-sample copies per (sensor, frame)
 constexpr int BB_RESIDENT = 256 * 4;          // workgroups resident at once (35 KiB of LDS each)
 
@@ -172,13 +173,23 @@ __global__ void __launch_bounds__(BB_THREADS) k_bp_batch(const uint32_t *__restr
 #pragma unroll
     for (int f = 0; f < BB_FB; ++f) acc[f] = 0.0f;
 
-    // window start for sensor s: 8-aligned, reaching BB_HALF samples below
-    // the delay of the workgroup's first pixel (the probe)
-    auto probe = [&](int s) -> uint32_t { return s < s_end ? tab[(long)s * P + pbase] : 0xFFFFFFFFu; };
+    // window start for sensor s: 8-aligned, BB_MARGIN samples below the
+    // smallest delay of every 32nd pixel of the workgroup (a scalar min over
+    // the raw 32-bit delay codes, whose order is the order of the delays;
+    // non-contributing codes sort last)
+    auto probe = [&](int s) -> uint32_t {
+        uint32_t m = 0xFFFFFFFFu;
+        if (s < s_end) {
+#pragma unroll
+            for (int q = 0; q < BB_NPROBE; ++q)
+                m = min(m, tab[(long)s * P + min(pbase + q * (BB_THREADS / BB_NPROBE), P - 1)]);
+        }
+        return m;
+    };
     auto anchor_of = [&](uint32_t pr) -> int {
         int n;
         float a;
-        return dec.decode(pr, N, n, a) ? floor8(n - BB_HALF - 1) : 0;
+        return dec.decode(pr, N, n, a) ? floor8(n - BB_MARGIN - 1) : 0;
     };
     constexpr int NSLOT = (BB_FB * BB_CHUNKS + BB_THREADS - 1) / BB_THREADS;
     Raw8 rr[NSLOT];

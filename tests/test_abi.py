@@ -57,8 +57,13 @@ def test_tile_order_host_helper():
     out = pat.tile_order(nx, ny, pix, 8, 4)
     assert sorted(out.tolist()) == sorted(pix.tolist())
     i, j = out % nx, out // nx
-    key = [(((jj // 4) * ((nx + 7) // 8) + ii // 8) << 32) | _morton(ii % 8, jj % 4)
-           for ii, jj in zip(i.tolist(), j.tolist())]
+    tx = (nx + 7) // 8
+
+    def tile(ii, jj):  # serpentine tile rows
+        r = jj // 4
+        return r * tx + (tx - 1 - ii // 8 if r % 2 else ii // 8)
+
+    key = [(tile(ii, jj) << 32) | _morton(ii % 8, jj % 4) for ii, jj in zip(i.tolist(), j.tolist())]
     assert all(a < b for a, b in zip(key, key[1:]))
     # a full 32x32 tile: every aligned run of 256 pixels is a 16x16 square
     full = np.arange(64 * 64, dtype=np.int32)
@@ -66,6 +71,11 @@ def test_tile_order_host_helper():
     for r in range(0, 1024, 256):
         blk = o[r:r + 256]
         assert np.ptp(blk % 64) == 15 and np.ptp(blk // 64) == 15
+    # consecutive tiles are neighbours: along the order, tile coordinates never jump
+    o = pat.tile_order(100, 100, np.arange(100 * 100, dtype=np.int32), 32, 32)
+    ti, tj = (o % 100) // 32, (o // 100) // 32
+    step = np.abs(np.diff(ti)) + np.abs(np.diff(tj))
+    assert step.max() <= 1
     with pytest.raises(pat.PatError):
         pat.tile_order(nx, ny, np.array([nx * ny], np.int32), 8, 4)
 

@@ -438,9 +438,10 @@ def test_fmm_bp_beats_conventional_bp(ctx, orc):
 
 
 def test_speed_error_robustness(ctx, orc):
-    # the paper's robustness study: tables rebuilt from a speed map carrying
-    # 1.7 % (of max) uncorrelated Gaussian errors with a 1.7 % mean still
-    # reconstruct the phantom about as well, and better than one constant speed
+    # the paper's robustness study: tables rebuilt from a speed map whose skull
+    # speeds carry 1.7 % (of max) uncorrelated Gaussian errors with a 1.7 %
+    # mean still reconstruct the phantom about as well, and better than one
+    # constant speed
     geo = inputs.config("paper")
     T = oracle_table(orc, geo)
     p = inputs.frame_for(geo, T, 5)
