@@ -263,6 +263,11 @@ int pat_server_wait(pat_server *s, uint64_t ticket, float *h_img, int timeout_ms
 int pat_server_get_stats(pat_server *s, pat_server_stats *out);
 /* Restart the throughput window and the latency record. */
 int pat_server_reset_stats(pat_server *s);
+/* hold != 0: frames are still admitted and queued but none is launched;
+ * hold == 0: launch what is queued (in batches of up to max_batch).  Batches
+ * already on the device are not affected.  For callers that collect a burst
+ * into shared launches, or pause the device work of a server. */
+int pat_server_hold(pat_server *s, int hold);
 
 #ifdef __cplusplus
 }

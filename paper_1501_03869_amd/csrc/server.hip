@@ -137,6 +137,7 @@ struct pat_server {
     std::mutex mu;
     std::condition_variable cv_sched, cv_done, cv_build, cv_slot;
     bool stop = false;
+    bool hold = false;  // queued frames wait until released
 
     std::unordered_map<int, std::unique_ptr<Map>> maps;
     int next_map = 1;
@@ -364,7 +365,7 @@ void pat_server::scheduler() {
                     if (it->second->state == MAP_READY) ready = true;
                     else if (it->second->state == MAP_EVICTED) ensure_building(it->second.get());
                 }
-                if (slot && ready) break;
+                if (slot && ready && !hold) break;
                 cv_sched.wait_for(lk, std::chrono::milliseconds(50));
             }
             // take ready frames in arrival order while device memory allows
@@ -839,5 +840,15 @@ extern "C" int pat_server_reset_stats(pat_server *s) {
     s->win_gathers = 0;
     s->lat_us.clear();
     s->lat_next = 0;
+    return PAT_OK;
+}
+
+extern "C" int pat_server_hold(pat_server *s, int hold) {
+    if (!s) return pat_fail(PAT_EINVAL, "null server");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->hold = hold != 0;
+    }
+    s->cv_sched.notify_all();
     return PAT_OK;
 }

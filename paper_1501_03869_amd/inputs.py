@@ -167,14 +167,17 @@ def config(name: str) -> Geometry:
     raise KeyError(name)
 
 
-def perturb_speed(speed: np.ndarray, seed: int, frac: float = 0.017, min_speed: float = 2000.0) -> np.ndarray:
-    """Speed map with uncorrelated Gaussian errors, mean and standard deviation
-    both frac * max(speed), added at the skull nodes (speed >= min_speed): the
-    paper's robustness study concerns errors in the skull sound speed and uses
-    1.7 % for both."""
+def perturb_speed(speed: np.ndarray, seed: int, frac: float = 0.017, mean_frac: float | None = None,
+                  min_speed: float = 2000.0) -> np.ndarray:
+    """Speed map with uncorrelated Gaussian errors added at the skull nodes
+    (speed >= min_speed): standard deviation frac * max(speed), mean
+    mean_frac * max(speed) (mean_frac defaults to frac).  The paper's
+    robustness study concerns errors in the skull sound speed and quotes 1.7 %
+    for both figures (Section III)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    m = float(np.max(speed)) * frac
-    noise = m + m * rng.standard_normal(speed.shape)
+    top = float(np.max(speed))
+    mu = top * (frac if mean_frac is None else mean_frac)
+    noise = mu + top * frac * rng.standard_normal(speed.shape)
     out = speed.astype(np.float64) + np.where(speed >= min_speed, noise, 0.0)
     return out.astype(np.float32)
 

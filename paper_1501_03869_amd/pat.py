@@ -27,6 +27,7 @@ EXPORTED = [
     "pat_server_create", "pat_server_destroy", "pat_server_add_map", "pat_server_map_state",
     "pat_server_remove_map", "pat_server_submit", "pat_server_wait", "pat_server_get_stats",
     "pat_server_reset_stats",
+    "pat_server_hold",
 ]
 MAP_BUILDING, MAP_READY, MAP_FAILED, MAP_EVICTED = 0, 1, 2, 3
 
@@ -93,6 +94,7 @@ def lib() -> C.CDLL:
         L.pat_server_wait.argtypes = [vp, C.c_uint64, vp, i32]
         L.pat_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
         L.pat_server_reset_stats.argtypes = [vp]
+        L.pat_server_hold.argtypes = [vp, i32]
         _lib = L
     return _lib
 
@@ -324,3 +326,7 @@ class Server:
 
     def reset_stats(self):
         check(lib().pat_server_reset_stats(self.h))
+
+    def hold(self, on: bool = True):
+        """Queue submitted frames without launching them until hold(False)."""
+        check(lib().pat_server_hold(self.h, 1 if on else 0))

@@ -439,9 +439,12 @@ def test_fmm_bp_beats_conventional_bp(ctx, orc):
 
 def test_speed_error_robustness(ctx, orc):
     # the paper's robustness study: tables rebuilt from a speed map whose skull
-    # speeds carry 1.7 % (of max) uncorrelated Gaussian errors with a 1.7 %
-    # mean still reconstruct the phantom about as well, and better than one
-    # constant speed
+    # speeds carry 1.7 % (of max) uncorrelated Gaussian errors.  With zero-mean
+    # errors the image keeps its quality and stays better than one constant
+    # speed.  With the errors' mean also at +1.7 % the whole skull is uniformly
+    # faster: on this 7 mm skull, whose first arrivals partly travel along it,
+    # that shifts the delays by about 3 samples (more than the pulse width) and
+    # the image defocuses; that case is recorded, not claimed robust.
     geo = inputs.config("paper")
     T = oracle_table(orc, geo)
     p = inputs.frame_for(geo, T, 5)
@@ -449,19 +452,21 @@ def test_speed_error_robustness(ctx, orc):
     truth = np.zeros(geo.nx * geo.ny)
     truth[nodes] = 1.0
     truth = truth[geo.pix]
-    bad = inputs.perturb_speed(geo.speed, 6000)
-    Tbad = ctx.eikonal_tables(dev(bad), geo.h, geo.sensors, dev(geo.pix))
-    Tgood = ctx.eikonal_tables(dev(geo.speed), geo.h, geo.sensors, dev(geo.pix))
-    imgs = {
-        "true map": ctx.backproject(Tgood, dev(p), geo.dt, filtered=False).cpu().numpy(),
-        "1.7% errors": ctx.backproject(Tbad, dev(p), geo.dt, filtered=False).cpu().numpy(),
-        "constant 1560": ctx.backproject_const(geo.nx, geo.ny, geo.h, 1560.0, geo.sensors, dev(geo.pix), dev(p),
-                                               geo.dt, filtered=False).cpu().numpy(),
-    }
+    zero_mean = inputs.perturb_speed(geo.speed, 6000, mean_frac=0.0)
+    biased = inputs.perturb_speed(geo.speed, 6000)
+    tab = {k: ctx.eikonal_tables(dev(v), geo.h, geo.sensors, dev(geo.pix))
+           for k, v in (("true map", geo.speed), ("zero-mean errors", zero_mean), ("biased errors", biased))}
+    imgs = {k: ctx.backproject(t, dev(p), geo.dt, filtered=False).cpu().numpy() for k, t in tab.items()}
+    imgs["constant 1560"] = ctx.backproject_const(geo.nx, geo.ny, geo.h, 1560.0, geo.sensors, dev(geo.pix), dev(p),
+                                                  geo.dt, filtered=False).cpu().numpy()
     corr = {k: float(np.corrcoef(np.maximum(v, 0), truth)[0, 1]) for k, v in imgs.items()}
-    print(f"[robustness] correlation with the phantom: {corr}", flush=True)
-    assert corr["1.7% errors"] > corr["constant 1560"]
-    assert corr["1.7% errors"] > 0.7 * corr["true map"]
+    shift = {k: float(((tab[k] - tab["true map"]).cpu().numpy() / geo.dt).mean()) for k in tab}
+    print(f"[robustness] correlation with the phantom: {corr}; mean delay shift (samples): {shift}", flush=True)
+    assert corr["zero-mean errors"] > corr["constant 1560"]
+    assert corr["zero-mean errors"] > 0.9 * corr["true map"]
+    assert abs(shift["zero-mean errors"]) < 0.5
+    assert shift["biased errors"] < -1.0
+    assert corr["biased errors"] < corr["zero-mean errors"]
 
 
 def test_large_gather_full_size_sampled(ctx, orc):
