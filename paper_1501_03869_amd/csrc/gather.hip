@@ -504,7 +504,7 @@ int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const
         return pat_launch_backproject_batch(ctx, table, table_fmt, sig, sig_fmt, sig_is_filtered, frame_scale, w, S, P,
                                             N, F, t0, dt, img, st);
     const BpShape sh = bp_shape(S, P, F);
-    if (sh.groups > 1 && pat_px_eligible(sig_fmt, N, sig))
+    if (sh.groups > 1 && pat_px_eligible(sig_fmt, S, P, N, F, sig))
         return pat_launch_backproject_px(table, table_fmt, sig, sig_fmt, sig_is_filtered, frame_scale, w, S, P, N, F,
                                          t0, dt, img, st);
     float *part = nullptr;

@@ -74,7 +74,7 @@ int pat_launch_table_to_q16(const float *T, int64_t n, double t0, double dt, int
 // Gather scratch shared by the single-frame and batched kernels.
 size_t pat_gather_counter_bytes(int P, int F);
 // one-pixel-per-lane gather (no LDS windows, no partial sums in global memory)
-bool pat_px_eligible(int sig_fmt, int N, const void *sig);
+bool pat_px_eligible(int sig_fmt, int S, int P, int N, int F, const void *sig);
 int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig, int sig_fmt, int sig_is_filtered,
                               const float *frame_scale, const float *w, int S, int P, int N, int F, double t0,
                               double dt, float *img, hipStream_t st);

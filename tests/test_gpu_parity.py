@@ -177,6 +177,39 @@ def test_backproject_edges(ctx, orc):
     assert np.all(got[2:7] == 0)
 
 
+@pytest.mark.parametrize("sig,N,filtered,F", [("f32", 4, False, 1), ("f32", 4, True, 3), ("f16", 6, False, 1),
+                                               ("f16", 6, True, 3), ("f32", 37, False, 3), ("f16", 38, False, 1),
+                                               ("f16", 37, True, 1)])
+def test_backproject_split_sensor_edges(ctx, orc, sig, N, filtered, F):
+    # 40 sensors over 700 pixels: a shape whose sensors are split over several
+    # slots.  Every sensor row carries delays on the first sample, on the last
+    # (exactly), inside the last interval, just outside both ends and
+    # non-finite, so the record-end handling of the filter is exercised in
+    # waves that also hold interior delays.  N = 4 (FP32) and 6 (FP16) are
+    # the smallest records; an odd FP16 length takes the windowed kernel.
+    dt, S, P = 2.0 ** -24, 40, 700
+    T = inputs.random_table(21, S, P, N, dt, 0.0, frac_out=0.05)
+    edge = np.array([0.0, (N - 1) * dt, (N - 1.5) * dt, 0.5 * dt, -1e-12, (N - 1) * dt * 1.0001, np.inf, np.nan],
+                    np.float32)
+    for s in range(S):
+        T[s, (np.arange(edge.size) * 37 + 5 * s) % P] = edge
+    p = inputs.random_signals(22, S, N, F)
+    w = np.random.default_rng(23).uniform(0.5, 1.5, size=S).astype(np.float32)
+    if sig == "f16":
+        scale, h, p = _fp16_frames(p if F > 1 else p[None])
+        got = ctx.backproject(dev(T), dev(h if F > 1 else h[0]), dt, filtered=filtered, w=dev(w),
+                              frame_scale=dev(scale)).cpu().numpy()
+        p = p if F > 1 else p[0]
+    else:
+        got = ctx.backproject(dev(T), dev(p), dt, filtered=filtered, w=dev(w)).cpu().numpy()
+    b = p if filtered else orc.filt(p, dt)
+    ref = orc.gather(T.astype(np.float64), b, dt, w=w.astype(np.float64))
+    assert got.shape == ref.shape
+    err = rel_l2(got, ref)
+    assert err <= IMG_TOL, err
+    assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
 def test_backproject_empty_and_deterministic(ctx, orc):
     z = torch.zeros((0, 10), dtype=torch.float32, device="cuda")
     img = ctx.backproject(z, torch.zeros((0, 8), device="cuda"), 1e-8)
