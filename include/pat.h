@@ -88,9 +88,11 @@ int pat_ctx_destroy(pat_ctx *ctx);
  * allocate nothing (for example inside HIP graph capture).  Synchronous. */
 int pat_ctx_reserve(pat_ctx *ctx, int S, int P, int F);
 
-/* Bytes of partial-sum scratch pat_backproject needs for these sizes (0 when
- * one workgroup per pixel block covers all sensors); a small zeroed buffer of
- * completion counters comes on top.  Host-only, no GPU needed. */
+/* Upper bound of the partial-sum scratch pat_backproject may use for these
+ * sizes (0 when one workgroup per pixel block covers all sensors); a small
+ * zeroed buffer of completion counters comes on top.  Calls that take the
+ * split-sensor kernel (N >= 4 and 32-bit offsets suffice; see
+ * pat_backproject) use none.  Host-only, no GPU needed. */
 size_t pat_backproject_scratch_bytes(int S, int P, int F);
 
 /*
@@ -175,7 +177,11 @@ int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, doubl
  * pat_backproject_scratch_bytes(S, P, F) bytes (allocated on first need, or
  * up front by pat_ctx_reserve).  When F >= 2, N is a multiple of 8 (FP16) or
  * 4 (FP32) and d_sig is 16-byte aligned, one launch reads the table once for
- * all frames; otherwise each frame is gathered as a single frame.
+ * all frames.  Otherwise, when the frame needs its sensors split over several
+ * workgroups to fill the GPU, N >= 4 and 2*ceil(S/2) records of the table
+ * and of the signal stay below 2 GiB, the sensors are split inside one
+ * workgroup per 32-pixel tile (no scratch); else LDS-windowed workgroups
+ * over sensor groups add their partial sums in scratch.
  */
 int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
@@ -238,10 +244,12 @@ int pat_server_create(pat_ctx *ctx, const pat_server_config *cfg, pat_server **o
 int pat_server_destroy(pat_server *s);
 
 /* Register a speed map (host arrays are copied; same conventions as
- * pat_eikonal_tables) with its frames' sampling (t0, dt, N).  Its table is
- * built asynchronously on the server's build stream; frames may be submitted
- * at once and wait until it is ready.  PAT_EBUSY if its table and build
- * memory cannot fit in the budget even after evicting idle maps. */
+ * pat_eikonal_tables) with its frames' sampling (t0, dt, N >= 4).  Its table
+ * is built asynchronously on the server's build stream; frames may be
+ * submitted at once and wait until it is ready.  PAT_EBUSY if its table and
+ * build memory cannot fit in the budget even after evicting idle maps;
+ * PAT_EINVAL also when an eighth of its table or of a frame exceeds 2 GiB
+ * (the gather's 32-bit offsets). */
 int pat_server_add_map(pat_server *s, const float *h_speed, int nx, int ny, double h,
                        const double *h_sensor_xy, int S, const int32_t *h_pix, int P,
                        double t0, double dt, int N, int *map_id);

@@ -412,36 +412,6 @@ __global__ void __launch_bounds__(BP_THREADS) k_bp_const(const void *__restrict_
     bp_block<DelayF32, SFMT, FILTERED, false, true>(J, dec, blockIdx.x, blockIdx.y);
 }
 
-// Frames of different geometries in one launch: workgroup b belongs to the
-// last descriptor whose block_begin <= b and covers (chunk, group) of that
-// frame exactly as a single-frame launch would, so a frame's image does not
-// depend on its batch-mates.
-template <int TFMT, int SFMT, bool VEC4>
-__global__ void __launch_bounds__(BP_THREADS) k_bp_multi(const pat_bp_desc *__restrict__ descs, int nd) {
-    const int b = blockIdx.x;
-    int lo = 0, hi = nd - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (descs[mid].block_begin <= b) lo = mid; else hi = mid - 1;
-    }
-    const pat_bp_desc &D = descs[lo];
-    const int local = b - D.block_begin;
-    BpJob J;
-    J.tab = D.tab; J.sig = D.sig; J.w = D.w; J.part = D.part; J.img = D.img; J.done = D.done;
-    J.S = D.S; J.P = D.P; J.N = D.N; J.spg = D.spg; J.G = D.G;
-    J.t0dt = D.t0dt;
-    J.scale = D.scale;
-    const int c = local % D.chunks, g = local / D.chunks;
-    if constexpr (TFMT == PAT_TABLE_F32) {
-        DelayF32 dec;
-        dec.inv_hi = D.inv_hi; dec.inv_lo = D.inv_lo; dec.off = D.off; dec.umax = D.umax;
-        bp_block<DelayF32, SFMT, false, VEC4>(J, dec, c, g);
-    } else {
-        DelayQ16 dec;
-        bp_block<DelayQ16, SFMT, false, VEC4>(J, dec, c, g);
-    }
-}
-
 template <class Delay, int SFMT>
 int launch(bool filtered, bool vec4, dim3 grid, const uint32_t *tab, const void *sig, const float *scale,
            const float *w, int S, int P, int N, int spg, int G, Delay dec, float t0dt, float *part, float *img,
@@ -535,41 +505,6 @@ int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const
                : launch<DelayQ16, PAT_SIG_F16>(filt, vec4, grid, tab, sig, frame_scale, w, S, P, N, sh.spg, sh.groups, d, t0dt, part, img, done, st);
 }
 
-int pat_bp_frame_shape(pat_bp_desc *d, int S, int P, int N, double t0, double dt, size_t *part_floats) {
-    const BpShape sh = bp_shape(S, P, 1);
-    d->S = S;
-    d->P = P;
-    d->N = N;
-    d->spg = sh.spg;
-    d->G = sh.groups;
-    d->chunks = sh.chunks;
-    d->t0dt = (float)(t0 / dt);
-    const double inv = 1.0 / dt;
-    d->inv_hi = (float)inv;
-    d->inv_lo = (float)(inv - (double)d->inv_hi);
-    d->off = (float)(-t0 / dt);
-    d->umax = (float)(N - 1);
-    d->scale = 1.0f;
-    *part_floats = sh.groups > 1 ? (size_t)sh.groups * P : 0;
-    return sh.chunks * sh.groups;
-}
-
-int pat_launch_bp_multi(const pat_bp_desc *d_descs, int nd, int total_blocks, int table_fmt, int sig_fmt, bool vec4,
-                        hipStream_t st) {
-    if (nd <= 0 || total_blocks <= 0) return PAT_OK;
-    const dim3 grid(total_blocks);
-#define PAT_BPM(TF, SF, V4) k_bp_multi<TF, SF, V4><<<grid, BP_THREADS, 0, st>>>(d_descs, nd)
-    if (table_fmt == PAT_TABLE_F32) {
-        if (sig_fmt == PAT_SIG_F32) { if (vec4) PAT_BPM(PAT_TABLE_F32, PAT_SIG_F32, true); else PAT_BPM(PAT_TABLE_F32, PAT_SIG_F32, false); }
-        else { if (vec4) PAT_BPM(PAT_TABLE_F32, PAT_SIG_F16, true); else PAT_BPM(PAT_TABLE_F32, PAT_SIG_F16, false); }
-    } else {
-        if (sig_fmt == PAT_SIG_F32) { if (vec4) PAT_BPM(PAT_TABLE_Q16, PAT_SIG_F32, true); else PAT_BPM(PAT_TABLE_Q16, PAT_SIG_F32, false); }
-        else { if (vec4) PAT_BPM(PAT_TABLE_Q16, PAT_SIG_F16, true); else PAT_BPM(PAT_TABLE_Q16, PAT_SIG_F16, false); }
-    }
-#undef PAT_BPM
-    PAT_HIP(hipGetLastError());
-    return PAT_OK;
-}
 
 int pat_launch_backproject_const(pat_ctx *ctx, int nx, int ny, double h, double c, const float *d_sxy, int S,
                                  const int32_t *d_pix, int P, const void *sig, int sig_fmt, int sig_is_filtered,

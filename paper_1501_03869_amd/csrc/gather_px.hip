@@ -1,20 +1,21 @@
-// Back projection for frames too small to fill the GPU with LDS windows:
-// 32 pixels per tile, each lane one pixel and one of two sensor slots, the
-// sensors of a tile split over the slots of one workgroup and the partial sums
-// added in LDS in slot order.
+// Back projection for frames too small to fill the GPU with LDS windows, and
+// for the frame server: 32 pixels per tile, each lane one pixel and one of two
+// sensor slots, the sensors of a tile split over the slots of one workgroup
+// and the partial sums added in LDS in slot order.
 //
 // The sum is the delay-and-sum of Section II: the filtered signal b of every
 // sensor read at the pixel's delay with linear interpolation, weighted and
 // summed over sensors.  Each lane reads its delay from the table (coalesced
-// along pixels) and the raw samples n-1 .. n+2 around it with one 16-byte
-// load, then evaluates the UBP filter (p - t dp/dt, central differences) for
-// b[n] and b[n+1].  There is no LDS window, so no delay can miss one, and no
+// along pixels) and the raw samples n-1 .. n+2 around it with one vector load,
+// then evaluates the UBP filter (p - t dp/dt, central differences) for b[n]
+// and b[n+1].  There is no LDS window, so no delay can miss one, and no
 // workgroup depends on another: a launch is one pass with no partial sums in
 // global memory.
 //
 // Loads go through buffer descriptors whose base is the wave's first record
 // (scalar registers) and whose per-lane offset is 32 bits, so an address costs
-// one vector instruction; the descriptor's range also bounds every access.
+// one or two vector instructions; the descriptor's range also bounds every
+// access.
 #include <mutex>
 
 #include "gather_common.h"
@@ -27,11 +28,18 @@ namespace {
 constexpr int PX_T = 32;           // pixels per tile
 constexpr int PX_U = 4;            // sensors per slot per pipeline step
 constexpr int PX_MAX_WAVES = 16;   // waves per workgroup
+constexpr int PX_MULTI_WAVES = 8;  // waves per workgroup of the multi-frame kernel
 constexpr int PX_RSRC_W3 = 0x00020000;  // buffer descriptor word 3: raw 32-bit dwords
 
 struct PxShape {
     int tiles, waves, sps;  // sps: sensors per slot (two slots per wave)
 };
+
+int px_sps(int S, int W) {
+    const int S1 = std::max(S, 1);
+    W = std::max(1, std::min(W, (S1 + 1) / 2));
+    return (S1 + 2 * W - 1) / (2 * W);
+}
 
 // Waves per workgroup: as many as keep every workgroup of the launch resident
 // at once (blocks_per_cu(W) * CUs >= tiles * F), so that no compute unit runs
@@ -42,16 +50,21 @@ PxShape px_shape(int S, int P, int F, int cus, BlocksPerCu blocks_per_cu) {
     PxShape s;
     s.tiles = (P + PX_T - 1) / PX_T;
     const long wgs = (long)s.tiles * std::max(F, 1);
-    const int S1 = std::max(S, 1);
     int W = 1;
     for (int cand = PX_MAX_WAVES; cand >= 1; --cand) {
         if ((long)blocks_per_cu(cand) * cus >= wgs) { W = cand; break; }
     }
-    W = std::min(W, (S1 + 1) / 2);
-    W = std::max(W, 1);
-    s.sps = (S1 + 2 * W - 1) / (2 * W);
-    s.waves = (S1 + 2 * s.sps - 1) / (2 * s.sps);
+    s.sps = px_sps(S, W);
+    s.waves = (std::max(S, 1) + 2 * s.sps - 1) / (2 * s.sps);
     return s;
+}
+
+// 32-bit offsets: the records of one wave (2 * sps) of the table and the
+// signal, with room for the FP16 alignment residue
+bool px_offsets_fit(int sps, int P, int N, int sig_fmt) {
+    const size_t rows = 2 * (size_t)sps;
+    const size_t esz = sig_fmt == PAT_SIG_F16 ? 2 : 4;
+    return rows * (size_t)P * 4 < (1ull << 31) && (rows * (size_t)N + 8) * esz < (1ull << 31);
 }
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, uint32_t bytes) {
@@ -62,46 +75,15 @@ __device__ __forceinline__ float h2f(uint32_t bits16) {
     return __half2float(__ushort_as_half((unsigned short)bits16));
 }
 
-// q[0..3] = x[c .. c+3] of the record at byte offset roff, scaled for FP16.
-// FP16 needs N even and c <= N - 4: three dwords from the even half e <= c
-// (e + 5 <= N - 1), the wanted halves cut out of them.
-template <int SFMT>
-__device__ __forceinline__ void load4(__amdgpu_buffer_rsrc_t r, uint32_t roff, int soff, int c, int N, float sc,
-                                      float (&q)[4]) {
-    if constexpr (SFMT == PAT_SIG_F32) {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, roff + 4u * (uint32_t)c, soff, 0);
-        q[0] = __uint_as_float(v[0]); q[1] = __uint_as_float(v[1]);
-        q[2] = __uint_as_float(v[2]); q[3] = __uint_as_float(v[3]);
-    } else {
-        const int e = min(c & ~1, N - 6);
-        const int k = c - e;  // 0, 1 or 2
-        const auto d = __builtin_amdgcn_raw_buffer_load_b96(r, roff + 2u * (uint32_t)e, soff, 0);
-        const uint32_t mid0 = __builtin_amdgcn_alignbyte(d[1], d[0], 2);
-        const uint32_t mid1 = __builtin_amdgcn_alignbyte(d[2], d[1], 2);
-        const uint32_t e0 = k == 0 ? d[0] : (k == 1 ? mid0 : d[1]);
-        const uint32_t e1 = k == 0 ? d[1] : (k == 1 ? mid1 : d[2]);
-        q[0] = h2f(e0 & 0xFFFFu) * sc; q[1] = h2f(e0 >> 16) * sc;
-        q[2] = h2f(e1 & 0xFFFFu) * sc; q[3] = h2f(e1 >> 16) * sc;
-    }
-}
-
-// b[n], b[n+1] from filtered samples (n <= N - 2 always).
-template <int SFMT>
-__device__ __forceinline__ void load2(__amdgpu_buffer_rsrc_t r, uint32_t roff, int soff, int n, int N, float sc,
-                                      float &b0, float &b1) {
-    if constexpr (SFMT == PAT_SIG_F32) {
-        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, roff + 4u * (uint32_t)n, soff, 0);
-        b0 = __uint_as_float(v[0]);
-        b1 = __uint_as_float(v[1]);
-    } else {
-        const int e = min(n & ~1, N - 4);  // halves e .. e+3 (<= N-1, N even) hold n, n+1
-        const int k = n - e;                 // 0, 1 or 2
-        const auto d = __builtin_amdgcn_raw_buffer_load_b64(r, roff + 2u * (uint32_t)e, soff, 0);
-        const uint32_t pair = k == 0 ? d[0] : (k == 1 ? __builtin_amdgcn_alignbyte(d[1], d[0], 2) : d[1]);
-        b0 = h2f(pair & 0xFFFFu) * sc;
-        b1 = h2f(pair >> 16) * sc;
-    }
-}
+// One workgroup's work: tile `tile` of one frame, all S sensors.
+struct PxJob {
+    const uint32_t *tab;  // [S][P] delays
+    const void *sig;      // [S][N] samples of this frame
+    const float *w;       // [S] weights (read only when HAS_W)
+    float *img;           // [P] output of this frame
+    int S, P, N, sps;
+    float t0dt, scale;
+};
 
 // One pipeline stage: the delays of U sensors of this lane's slot, decoded,
 // and their samples.
@@ -111,22 +93,16 @@ struct Stage {
     float a[PX_U], w[PX_U], q[PX_U][4];
 };
 
+// The sensors of lanes in slot `half` of wave wv, summed for pixel `tile*32 +
+// lane%32`.  wv must be wave-uniform (a scalar) and sw = wv*2*sps < S.
 template <class Delay, int SFMT, bool FILTERED, bool HAS_W>
-__global__ void __launch_bounds__(64 * PX_MAX_WAVES)
-    k_bp_px(const uint32_t *__restrict__ tab, const void *__restrict__ sig, const float *__restrict__ scale,
-            const float *__restrict__ w, int S, int P, int N, int sps, Delay dec, float t0dt,
-            float *__restrict__ img) {
-    __shared__ float red[2 * PX_MAX_WAVES][PX_T];
-    const int f = blockIdx.y;
+__device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, int tile, int wv) {
+    const int S = J.S, P = J.P, N = J.N, sps = J.sps;
+    const float t0dt = J.t0dt, sc = J.scale;
     const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform: keeps descriptors scalar
-    const int nw = blockDim.x >> 6;
     const int half = lane >> 5;
-    const int px = lane & (PX_T - 1);
-    const int p = blockIdx.x * PX_T + px;
+    const int p = tile * PX_T + (lane & (PX_T - 1));
     const int pc = min(p, P - 1);  // lanes past the end read a valid column and add nothing
-    constexpr uint32_t esz = SFMT == PAT_SIG_F16 ? 2 : 4;
-    const float sc = (SFMT == PAT_SIG_F16 && scale) ? scale[f] : 1.0f;
 
     // the wave's two slots: sensors sw .. sw+sps-1 (lanes 0-31) and
     // sw+sps .. sw+2sps-1 (lanes 32-63), both clipped to S
@@ -135,11 +111,58 @@ __global__ void __launch_bounds__(64 * PX_MAX_WAVES)
     const int s_lo = sw + half * sps;
     const int s_hi = min(S, s_lo + sps);
     const int nstep = (sps + PX_U - 1) / PX_U;
-    const __amdgpu_buffer_rsrc_t rt = rsrc(tab + (size_t)sw * P, (uint32_t)nrows * (uint32_t)P * 4u);
-    const char *fsig = static_cast<const char *>(sig) + ((size_t)f * S + sw) * N * esz;
-    const __amdgpu_buffer_rsrc_t rs = rsrc(fsig, (uint32_t)nrows * (uint32_t)N * esz);
+    const __amdgpu_buffer_rsrc_t rt = rsrc(J.tab + (size_t)sw * P, (uint32_t)nrows * (uint32_t)P * 4u);
     const uint32_t toff = ((uint32_t)(half * sps) * (uint32_t)P + (uint32_t)pc) * 4u;
-    const uint32_t roff = (uint32_t)(half * sps) * (uint32_t)N * esz;
+    // signal descriptor: FP32 records start on dwords; FP16 records may not,
+    // so the base is rounded down to a dword and sample offsets count from
+    // there (res = 0 or 1 sample)
+    constexpr uint32_t esz = SFMT == PAT_SIG_F16 ? 2 : 4;
+    const uintptr_t sig0 = reinterpret_cast<uintptr_t>(J.sig) + (size_t)sw * N * esz;
+    const uint32_t res = (uint32_t)(sig0 & 3u) / esz;
+    // the range ends at the last dword holding a sample of the slots; every
+    // load below reads only dwords that hold at least one wanted sample
+    const __amdgpu_buffer_rsrc_t rs =
+        rsrc(reinterpret_cast<const void *>(sig0 & ~(uintptr_t)3), ((res + (uint32_t)nrows * N) * esz + 3u) & ~3u);
+    const uint32_t hl = res + (uint32_t)(half * sps) * (uint32_t)N;  // this lane's slot, in samples
+
+    // q[0..3] = x[c .. c+3] of slot record k, scaled for FP16
+    auto load4 = [&](int k, int c, float (&q)[4]) {
+        if constexpr (SFMT == PAT_SIG_F32) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, 4u * (hl + (uint32_t)c), k * N * 4, 0);
+            q[0] = __uint_as_float(v[0]); q[1] = __uint_as_float(v[1]);
+            q[2] = __uint_as_float(v[2]); q[3] = __uint_as_float(v[3]);
+        } else {
+            // two dwords from the even sample at or below c, and for an odd
+            // start the dword holding c+3 (else the first one again)
+            const uint32_t h = hl + (uint32_t)(k * N + c);
+            const bool odd = h & 1u;
+            const uint32_t e = 2u * (h & ~1u);
+            const auto d = __builtin_amdgcn_raw_buffer_load_b64(rs, e, 0, 0);
+            const uint32_t d2 = __builtin_amdgcn_raw_buffer_load_b32(rs, odd ? e + 8u : e, 0, 0);
+            const uint32_t e0 = odd ? __builtin_amdgcn_alignbyte(d[1], d[0], 2) : d[0];
+            const uint32_t e1 = odd ? __builtin_amdgcn_alignbyte(d2, d[1], 2) : d[1];
+            q[0] = h2f(e0 & 0xFFFFu) * sc; q[1] = h2f(e0 >> 16) * sc;
+            q[2] = h2f(e1 & 0xFFFFu) * sc; q[3] = h2f(e1 >> 16) * sc;
+        }
+    };
+    // b[n], b[n+1] of slot record k (filtered input; n <= N-2)
+    auto load2 = [&](int k, int n, float &b0, float &b1) {
+        if constexpr (SFMT == PAT_SIG_F32) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, 4u * (hl + (uint32_t)n), k * N * 4, 0);
+            b0 = __uint_as_float(v[0]);
+            b1 = __uint_as_float(v[1]);
+        } else {
+            // the dword holding n, and for odd n the one holding n+1
+            const uint32_t h = hl + (uint32_t)(k * N + n);
+            const bool odd = h & 1u;
+            const uint32_t e = 2u * (h & ~1u);
+            const uint32_t d0 = __builtin_amdgcn_raw_buffer_load_b32(rs, e, 0, 0);
+            const uint32_t d1 = __builtin_amdgcn_raw_buffer_load_b32(rs, odd ? e + 4u : e, 0, 0);
+            const uint32_t pair = odd ? __builtin_amdgcn_alignbyte(d1, d0, 2) : d0;
+            b0 = h2f(pair & 0xFFFFu) * sc;
+            b1 = h2f(pair >> 16) * sc;
+        }
+    };
 
     // Every step issues the same loads, so the waits between the stages are
     // static: a slot position past the slot's end (or a step past the last)
@@ -158,27 +181,25 @@ __global__ void __launch_bounds__(64 * PX_MAX_WAVES)
 #pragma unroll
         for (int j = 0; j < PX_U; ++j) {
             const int k = i * PX_U + j;  // sensor within the slot
+            const int kc = min(k, sps - 1);
             int n = 1;
             float a = 0.0f;
             const bool dok = dec.decode(st.d[j], N, n, a);
             const bool ok = dok & (s_lo + k < s_hi);
             float ws = 1.0f;
             if constexpr (HAS_W) {
-                const int kk = min(k, sps - 1);
-                const float ws0 = w[min(sw + kk, S - 1)];
-                const float ws1 = w[min(sw + sps + kk, S - 1)];
+                const float ws0 = J.w[min(sw + kc, S - 1)];
+                const float ws1 = J.w[min(sw + sps + kc, S - 1)];
                 ws = half ? ws1 : ws0;
             }
             st.w[j] = ok ? ws : 0.0f;
             st.n[j] = ok ? n : 1;
             st.a[j] = ok ? a : 0.0f;
-            const int soff = min(k, sps - 1) * N * (int)esz;
             if constexpr (FILTERED) {
-                load2<SFMT>(rs, roff, soff, st.n[j], N, sc, st.q[j][1], st.q[j][2]);
+                load2(kc, st.n[j], st.q[j][1], st.q[j][2]);
             } else {
                 end |= ok & ((n == 0) | (n == N - 2));
-                const int c = min(max(st.n[j] - 1, 0), N - 4);
-                load4<SFMT>(rs, roff, soff, c, N, sc, st.q[j]);
+                load4(kc, min(max(st.n[j] - 1, 0), N - 4), st.q[j]);
             }
         }
         return end;
@@ -227,13 +248,77 @@ __global__ void __launch_bounds__(64 * PX_MAX_WAVES)
         delays(i + 3, B);
         sum(B, __any(endB));
     }
+    return acc;
+}
 
-    red[wv * 2 + half][px] = acc;
+// One tile of one frame: every wave sums its slots, then the slot sums are
+// added in slot order.  Waves whose slots start past S add zero.
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W>
+__device__ __forceinline__ void px_block(const PxJob &J, const Delay &dec, int tile, int wv, int nw) {
+    __shared__ float red[2 * PX_MAX_WAVES][PX_T];
+    const int lane = threadIdx.x & 63;
+    const int px = lane & (PX_T - 1);
+    float acc = 0.0f;
+    if (wv * 2 * J.sps < J.S) acc = px_slot_sum<Delay, SFMT, FILTERED, HAS_W>(J, dec, tile, wv);
+    red[wv * 2 + (lane >> 5)][px] = acc;
     __syncthreads();
-    if (wv == 0 && half == 0 && p < P) {
+    const int p = tile * PX_T + px;
+    if (wv == 0 && lane < PX_T && p < J.P) {
         float s = 0.0f;
         for (int k = 0; k < 2 * nw; ++k) s += red[k][px];
-        img[(long)f * P + p] = s;
+        J.img[p] = s;
+    }
+}
+
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W>
+__global__ void __launch_bounds__(64 * PX_MAX_WAVES)
+    k_bp_px(const uint32_t *__restrict__ tab, const void *__restrict__ sig, const float *__restrict__ scale,
+            const float *__restrict__ w, int S, int P, int N, int sps, Delay dec, float t0dt,
+            float *__restrict__ img) {
+    const int f = blockIdx.y;
+    constexpr size_t esz = SFMT == PAT_SIG_F16 ? 2 : 4;
+    PxJob J;
+    J.tab = tab;
+    J.sig = static_cast<const char *>(sig) + (size_t)f * S * N * esz;
+    J.w = w;
+    J.img = img + (size_t)f * P;
+    J.S = S; J.P = P; J.N = N; J.sps = sps;
+    J.t0dt = t0dt;
+    J.scale = (SFMT == PAT_SIG_F16 && scale) ? scale[f] : 1.0f;
+    // a wave-uniform wave index keeps the descriptors in scalar registers
+    px_block<Delay, SFMT, FILTERED, HAS_W>(J, dec, blockIdx.x, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                                           blockDim.x >> 6);
+}
+
+// Frames of different geometries in one launch: workgroup b belongs to the
+// last descriptor whose block_begin <= b and computes one tile of that frame;
+// the frame's shape depends on its own S, P, N only, so its image does not
+// depend on its batch-mates.
+template <int TFMT, int SFMT>
+__global__ void __launch_bounds__(64 * PX_MULTI_WAVES) k_bp_px_multi(const pat_bp_desc *__restrict__ descs, int nd) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+    }
+    const pat_bp_desc &D = descs[lo];
+    PxJob J;
+    J.tab = D.tab; J.sig = D.sig; J.w = D.w; J.img = D.img;
+    J.S = D.S; J.P = D.P; J.N = D.N; J.sps = D.sps;
+    J.t0dt = D.t0dt;
+    J.scale = D.scale;
+    const int tile = b - D.block_begin;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if constexpr (TFMT == PAT_TABLE_F32) {
+        DelayF32 dec;
+        dec.inv_hi = D.inv_hi; dec.inv_lo = D.inv_lo; dec.off = D.off; dec.umax = D.umax;
+        if (D.w) px_block<DelayF32, SFMT, false, true>(J, dec, tile, wv, PX_MULTI_WAVES);
+        else px_block<DelayF32, SFMT, false, false>(J, dec, tile, wv, PX_MULTI_WAVES);
+    } else {
+        DelayQ16 dec;
+        if (D.w) px_block<DelayQ16, SFMT, false, true>(J, dec, tile, wv, PX_MULTI_WAVES);
+        else px_block<DelayQ16, SFMT, false, false>(J, dec, tile, wv, PX_MULTI_WAVES);
     }
 }
 
@@ -245,18 +330,21 @@ int launch_one(int S, int P, int F, const uint32_t *tab, const void *sig, const 
     static int cache_dev = -1, cache_cus = 0, cache_bpc[PX_MAX_WAVES + 1];
     int dev = 0;
     PAT_HIP(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lk(mu);
-    if (cache_dev != dev) {
-        PAT_HIP(hipDeviceGetAttribute(&cache_cus, hipDeviceAttributeMultiprocessorCount, dev));
-        for (int W = 1; W <= PX_MAX_WAVES; ++W)
-            PAT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&cache_bpc[W], k_bp_px<Delay, SFMT, FILTERED, HAS_W>,
-                                                                 64 * W, 0));
-        cache_dev = dev;
+    PxShape sh;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (cache_dev != dev) {
+            PAT_HIP(hipDeviceGetAttribute(&cache_cus, hipDeviceAttributeMultiprocessorCount, dev));
+            for (int W = 1; W <= PX_MAX_WAVES; ++W)
+                PAT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &cache_bpc[W], k_bp_px<Delay, SFMT, FILTERED, HAS_W>, 64 * W, 0));
+            cache_dev = dev;
+        }
+        sh = px_shape(S, P, F, cache_cus, [&](int W) { return cache_bpc[W]; });
     }
-    const PxShape sh = px_shape(S, P, F, cache_cus, [&](int W) { return cache_bpc[W]; });
     const dim3 grid(sh.tiles, F);
-    k_bp_px<Delay, SFMT, FILTERED, HAS_W><<<grid, dim3(64 * sh.waves), 0, st>>>(tab, sig, scale, w, S, P, N, sh.sps, dec,
-                                                                         t0dt, img);
+    k_bp_px<Delay, SFMT, FILTERED, HAS_W><<<grid, dim3(64 * sh.waves), 0, st>>>(tab, sig, scale, w, S, P, N, sh.sps,
+                                                                                dec, t0dt, img);
     PAT_HIP(hipGetLastError());
     return PAT_OK;
 }
@@ -274,14 +362,10 @@ int launch_px(bool filtered, int S, int P, int F, const uint32_t *tab, const voi
 }  // namespace
 
 bool pat_px_eligible(int sig_fmt, int S, int P, int N, int F, const void *sig) {
-    if (S <= 0 || P <= 0 || F <= 0) return false;
-    const size_t esz = sig_fmt == PAT_SIG_F16 ? 2 : 4;
-    if (sig_fmt == PAT_SIG_F16 && (N < 6 || N % 2 != 0 || (uintptr_t)sig % 4 != 0)) return false;
-    if (sig_fmt == PAT_SIG_F32 && (N < 4 || (uintptr_t)sig % 4 != 0)) return false;
-    // 32-bit buffer offsets: the two slots of a wave span at most 2*ceil(S/2)
-    // records (the shape with one wave per workgroup)
-    const size_t rows = 2 * (((size_t)S + 1) / 2);
-    return rows * (size_t)P * 4 < (1ull << 31) && rows * (size_t)N * esz < (1ull << 31);
+    if (S <= 0 || P <= 0 || F <= 0 || N < 4) return false;
+    if ((uintptr_t)sig % (sig_fmt == PAT_SIG_F16 ? 2 : 4) != 0) return false;
+    // the widest slots: one wave per workgroup
+    return px_offsets_fit(px_sps(S, 1), P, N, sig_fmt);
 }
 
 int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig, int sig_fmt, int sig_is_filtered,
@@ -305,4 +389,40 @@ int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig,
     return sig_fmt == PAT_SIG_F32
                ? launch_px<DelayQ16, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
                : launch_px<DelayQ16, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
+}
+
+bool pat_px_multi_eligible(int sig_fmt, int S, int P, int N) {
+    if (S <= 0 || P <= 0 || N < 4) return false;
+    return px_offsets_fit(px_sps(S, PX_MULTI_WAVES), P, N, sig_fmt);
+}
+
+int pat_px_frame_shape(pat_bp_desc *d, int S, int P, int N, double t0, double dt) {
+    d->S = S;
+    d->P = P;
+    d->N = N;
+    d->sps = px_sps(S, PX_MULTI_WAVES);
+    d->tiles = (P + PX_T - 1) / PX_T;
+    d->t0dt = (float)(t0 / dt);
+    const double inv = 1.0 / dt;
+    d->inv_hi = (float)inv;
+    d->inv_lo = (float)(inv - (double)d->inv_hi);
+    d->off = (float)(-t0 / dt);
+    d->umax = (float)(N - 1);
+    d->scale = 1.0f;
+    return d->tiles;
+}
+
+int pat_launch_px_multi(const pat_bp_desc *d_descs, int nd, int total_blocks, int table_fmt, int sig_fmt,
+                        hipStream_t st) {
+    if (nd <= 0 || total_blocks <= 0) return PAT_OK;
+    const dim3 grid(total_blocks), block(64 * PX_MULTI_WAVES);
+    if (table_fmt == PAT_TABLE_F32) {
+        if (sig_fmt == PAT_SIG_F32) k_bp_px_multi<PAT_TABLE_F32, PAT_SIG_F32><<<grid, block, 0, st>>>(d_descs, nd);
+        else k_bp_px_multi<PAT_TABLE_F32, PAT_SIG_F16><<<grid, block, 0, st>>>(d_descs, nd);
+    } else {
+        if (sig_fmt == PAT_SIG_F32) k_bp_px_multi<PAT_TABLE_Q16, PAT_SIG_F32><<<grid, block, 0, st>>>(d_descs, nd);
+        else k_bp_px_multi<PAT_TABLE_Q16, PAT_SIG_F16><<<grid, block, 0, st>>>(d_descs, nd);
+    }
+    PAT_HIP(hipGetLastError());
+    return PAT_OK;
 }

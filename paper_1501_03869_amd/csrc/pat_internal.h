@@ -44,27 +44,26 @@ struct pat_ctx {
 int pat_make_current(pat_ctx *ctx);
 
 // One frame of a mixed-geometry gather launch (device-visible).  The shape
-// fields come from pat_bp_frame_shape so that a frame is split exactly as a
-// single-frame pat_backproject call would split it.
+// fields come from pat_px_frame_shape and depend only on the frame's own
+// S, P, N, so a frame's image does not depend on its batch-mates.
 struct pat_bp_desc {
     const uint32_t *tab;   // [S][P] delay table of the frame's map
     const void *sig;       // [S][N] raw samples of the frame
     const float *w;        // [S] sensor weights or null
-    float *part;           // [G][P] partial sums (G > 1)
     float *img;            // [P] output
-    unsigned int *done;    // [chunks] zeroed completion counters (G > 1)
-    int S, P, N, spg, G, chunks;
+    int S, P, N, sps;      // sps: sensors per slot (two slots per wave)
+    int tiles;             // workgroups of this frame (32 pixels each)
+    int block_begin;       // first workgroup of this frame in the launch
     float t0dt, scale;                // t0/dt; FP16 frame scale (1 otherwise)
     float inv_hi, inv_lo, off, umax;  // float32-seconds delay decoding
-    int block_begin;                  // first workgroup of this frame
-    int pad_;
 };
 
+// Whether a map of this shape can go through the multi-frame gather.
+bool pat_px_multi_eligible(int sig_fmt, int S, int P, int N);
 // Fills the shape and decoding fields of d for one frame; returns the number
-// of workgroups it needs.  *part_floats receives the partial-sum length (0 if
-// G == 1).
-int pat_bp_frame_shape(pat_bp_desc *d, int S, int P, int N, double t0, double dt, size_t *part_floats);
-int pat_launch_bp_multi(const pat_bp_desc *d_descs, int nd, int total_blocks, int table_fmt, int sig_fmt, bool vec4,
+// of workgroups it needs.
+int pat_px_frame_shape(pat_bp_desc *d, int S, int P, int N, double t0, double dt);
+int pat_launch_px_multi(const pat_bp_desc *d_descs, int nd, int total_blocks, int table_fmt, int sig_fmt,
                         hipStream_t st);
 
 // Launchers (stream-ordered; arguments validated by the callers).

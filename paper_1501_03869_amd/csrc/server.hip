@@ -88,10 +88,6 @@ struct BatchSlot {
     pat_bp_desc *h_desc = nullptr;   // pinned
     pat_bp_desc *d_desc = nullptr;
     int desc_cap = 0;
-    float *d_part = nullptr;
-    size_t part_cap = 0;             // floats
-    unsigned int *d_done = nullptr;
-    size_t done_cap = 0;             // counters
     std::vector<Frame *> frames;
     bool busy = false;
 };
@@ -395,9 +391,7 @@ void pat_server::scheduler() {
         // descriptors
         int rc = PAT_OK;
         const int nd = (int)batch.size();
-        size_t part_need = 0, done_need = 0;
         int blocks = 0;
-        bool vec4 = true;
         std::vector<pat_bp_desc> desc((size_t)nd);
         {
             std::lock_guard<std::mutex> lk(mu);
@@ -405,20 +399,14 @@ void pat_server::scheduler() {
                 Frame *f = batch[(size_t)i];
                 Map *m = maps[f->map_id].get();
                 pat_bp_desc &d = desc[(size_t)i];
-                size_t pf = 0;
-                const int nb = pat_bp_frame_shape(&d, m->S, m->P, m->N, m->t0, m->dt, &pf);
+                const int nb = pat_px_frame_shape(&d, m->S, m->P, m->N, m->t0, m->dt);
                 d.tab = static_cast<const uint32_t *>(m->d_table);
                 d.sig = f->d_in;
                 d.w = nullptr;
                 d.img = f->d_out;
                 d.scale = cfg.sig_fmt == PAT_SIG_F16 ? f->scale : 1.0f;
                 d.block_begin = blocks;
-                d.part = reinterpret_cast<float *>(part_need);   // offsets for now
-                d.done = reinterpret_cast<unsigned int *>(done_need);
-                part_need += pf;
-                if (d.G > 1) done_need += (size_t)d.chunks;
                 blocks += nb;
-                if (m->P % 4) vec4 = false;
             }
         }
         if (nd > slot->desc_cap) {
@@ -433,42 +421,14 @@ void pat_server::scheduler() {
             else
                 slot->desc_cap = nd;
         }
-        if (rc == PAT_OK && part_need > slot->part_cap) {
-            if (slot->d_part) (void)hipFree(slot->d_part);
-            slot->d_part = nullptr;
-            const size_t old = slot->part_cap * sizeof(float);
-            slot->part_cap = 0;
-            if (hipMalloc((void **)&slot->d_part, part_need * sizeof(float)) != hipSuccess) rc = PAT_ENOMEM;
-            else slot->part_cap = part_need;
-            std::lock_guard<std::mutex> lk(mu);
-            used = used - std::min(used, old) + slot->part_cap * sizeof(float);
-        }
-        if (rc == PAT_OK && done_need > slot->done_cap) {
-            if (slot->d_done) (void)hipFree(slot->d_done);
-            slot->d_done = nullptr;
-            const size_t old = slot->done_cap * sizeof(unsigned int);
-            slot->done_cap = 0;
-            if (hipMalloc((void **)&slot->d_done, done_need * sizeof(unsigned int)) != hipSuccess ||
-                hipMemset(slot->d_done, 0, done_need * sizeof(unsigned int)) != hipSuccess)
-                rc = PAT_ENOMEM;
-            else
-                slot->done_cap = done_need;
-            std::lock_guard<std::mutex> lk(mu);
-            used = used - std::min(used, old) + slot->done_cap * sizeof(unsigned int);
-        }
         if (rc == PAT_OK) {
-            for (int i = 0; i < nd; ++i) {
-                pat_bp_desc &d = desc[(size_t)i];
-                d.part = d.G > 1 ? slot->d_part + reinterpret_cast<size_t>(d.part) : nullptr;
-                d.done = d.G > 1 ? slot->d_done + reinterpret_cast<size_t>(d.done) : nullptr;
-            }
             std::memcpy(slot->h_desc, desc.data(), sizeof(pat_bp_desc) * nd);
             hipStream_t st = slot->stream;
             for (Frame *f : batch)
                 if (hipMemcpyAsync(f->d_in, f->h_in, f->in_bytes, hipMemcpyHostToDevice, st) != hipSuccess) rc = PAT_EDEVICE;
             if (hipMemcpyAsync(slot->d_desc, slot->h_desc, sizeof(pat_bp_desc) * nd, hipMemcpyHostToDevice, st) != hipSuccess)
                 rc = PAT_EDEVICE;
-            if (rc == PAT_OK) rc = pat_launch_bp_multi(slot->d_desc, nd, blocks, cfg.table_fmt, cfg.sig_fmt, vec4, st);
+            if (rc == PAT_OK) rc = pat_launch_px_multi(slot->d_desc, nd, blocks, cfg.table_fmt, cfg.sig_fmt, st);
             for (Frame *f : batch)
                 if (rc == PAT_OK && hipMemcpyAsync(f->h_out, f->d_out, f->out_bytes, hipMemcpyDeviceToHost, st) != hipSuccess)
                     rc = PAT_EDEVICE;
@@ -632,8 +592,6 @@ extern "C" int pat_server_destroy(pat_server *s) {
         if (sl.ev) (void)hipEventDestroy(sl.ev);
         if (sl.h_desc) (void)hipHostFree(sl.h_desc);
         if (sl.d_desc) (void)hipFree(sl.d_desc);
-        if (sl.d_part) (void)hipFree(sl.d_part);
-        if (sl.d_done) (void)hipFree(sl.d_done);
     }
     for (auto &kv : s->maps)
         if (kv.second->d_table) (void)hipFree(kv.second->d_table);
@@ -656,8 +614,10 @@ extern "C" int pat_server_add_map(pat_server *s, const float *h_speed, int nx, i
                                   const double *h_sensor_xy, int S, const int32_t *h_pix, int P, double t0, double dt,
                                   int N, int *map_id) {
     if (!s || !map_id) return pat_fail(PAT_EINVAL, "null argument");
-    if (nx < 2 || ny < 2 || !(h > 0) || S <= 0 || P <= 0 || N < 2 || !(dt > 0) || !std::isfinite(t0))
+    if (nx < 2 || ny < 2 || !(h > 0) || S <= 0 || P <= 0 || N < 4 || !(dt > 0) || !std::isfinite(t0))
         return pat_fail(PAT_EINVAL, "bad map geometry");
+    if (!pat_px_multi_eligible(s->cfg.sig_fmt, S, P, N))
+        return pat_fail(PAT_EINVAL, "map too large for the frame server (S*P or S*N beyond 32-bit offsets)");
     if (!h_speed || !h_sensor_xy || !h_pix) return pat_fail(PAT_EINVAL, "null map data");
     if (s->cfg.table_fmt == PAT_TABLE_Q16 && N > 65535) return pat_fail(PAT_EINVAL, "16.16 tables need N <= 65535");
     const size_t n = (size_t)nx * ny;
