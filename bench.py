@@ -79,9 +79,8 @@ def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
         wall, ms = timed(fn, args.steps, args.warmup)
         res[name] = {"frames_per_launch": 1, "gathers_per_s": args.steps * S * P / wall,
                      "frames_per_s": args.steps / wall,
-        "timing_note": "value/frames_per_s: single-frame launches replayed from a HIP graph of up to 64 launches; "
-                       "device_ms_* and roofline: HIP events around each eager launch", "device_ms_p50": percentile(ms, 50),
-                     "device_ms_p99": percentile(ms, 99)}
+                     "timing_note": "eager single-frame launches (wall time); device_ms_*: HIP events around each",
+                     "device_ms_p50": percentile(ms, 50), "device_ms_p99": percentile(ms, 99)}
 
     single("v0_f32_table_f32_signal", table, frames, None)
     single("v1_q16_table_f32_signal", q16, frames, None)

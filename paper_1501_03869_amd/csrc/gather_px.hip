@@ -59,10 +59,10 @@ PxShape px_shape(int S, int P, int F, int cus, BlocksPerCu blocks_per_cu) {
     return s;
 }
 
-// 32-bit offsets: the records of one wave (2 * sps) of the table and the
-// signal, with room for the FP16 alignment residue
-bool px_offsets_fit(int sps, int P, int N, int sig_fmt) {
-    const size_t rows = 2 * (size_t)sps;
+// 32-bit offsets: a step's descriptors span 2*U records of the table and of
+// the signal, with room for the FP16 alignment residue
+bool px_offsets_fit(int P, int N, int sig_fmt) {
+    const size_t rows = 2 * (size_t)PX_U;
     const size_t esz = sig_fmt == PAT_SIG_F16 ? 2 : 4;
     return rows * (size_t)P * 4 < (1ull << 31) && (rows * (size_t)N + 8) * esz < (1ull << 31);
 }
@@ -93,8 +93,10 @@ struct Stage {
     float a[PX_U], w[PX_U], q[PX_U][4];
 };
 
-// The sensors of lanes in slot `half` of wave wv, summed for pixel `tile*32 +
-// lane%32`.  wv must be wave-uniform (a scalar) and sw = wv*2*sps < S.
+// The sensors of wave wv for pixel tile*32 + lane%32: the wave owns sensors
+// sw .. sw+2*sps-1 (sw = wv*2*sps, clipped to S); lanes 0-31 take the even
+// ones, lanes 32-63 the odd ones.  wv must be wave-uniform (a scalar) and
+// sw < S.
 template <class Delay, int SFMT, bool FILTERED, bool HAS_W>
 __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, int tile, int wv) {
     const int S = J.S, P = J.P, N = J.N, sps = J.sps;
@@ -103,61 +105,70 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     const int half = lane >> 5;
     const int p = tile * PX_T + (lane & (PX_T - 1));
     const int pc = min(p, P - 1);  // lanes past the end read a valid column and add nothing
-
-    // the wave's two slots: sensors sw .. sw+sps-1 (lanes 0-31) and
-    // sw+sps .. sw+2sps-1 (lanes 32-63), both clipped to S
     const int sw = wv * 2 * sps;
-    const int nrows = min(2 * sps, S - sw);
-    const int s_lo = sw + half * sps;
-    const int s_hi = min(S, s_lo + sps);
+    const int se = min(S, sw + 2 * sps);  // end of this wave's sensors
     const int nstep = (sps + PX_U - 1) / PX_U;
-    const __amdgpu_buffer_rsrc_t rt = rsrc(J.tab + (size_t)sw * P, (uint32_t)nrows * (uint32_t)P * 4u);
-    const uint32_t toff = ((uint32_t)(half * sps) * (uint32_t)P + (uint32_t)pc) * 4u;
-    // signal descriptor: FP32 records start on dwords; FP16 records may not,
-    // so the base is rounded down to a dword and sample offsets count from
-    // there (res = 0 or 1 sample)
     constexpr uint32_t esz = SFMT == PAT_SIG_F16 ? 2 : 4;
-    const uintptr_t sig0 = reinterpret_cast<uintptr_t>(J.sig) + (size_t)sw * N * esz;
-    const uint32_t res = (uint32_t)(sig0 & 3u) / esz;
-    // the range ends at the last dword holding a sample of the slots; every
-    // load below reads only dwords that hold at least one wanted sample
-    const __amdgpu_buffer_rsrc_t rs =
-        rsrc(reinterpret_cast<const void *>(sig0 & ~(uintptr_t)3), ((res + (uint32_t)nrows * N) * esz + 3u) & ~3u);
-    const uint32_t hl = res + (uint32_t)(half * sps) * (uint32_t)N;  // this lane's slot, in samples
+    // Step i covers sensors s0 + 2j + half (j < U) with s0 = sw + 2*i*U.  Its
+    // descriptors start at record s0 (scalar registers) and end at the last
+    // record the step may touch, so per-lane offsets stay below 2*U records
+    // however large the table is.  Signal records start on a dword for FP32;
+    // for FP16 the base is rounded down to a dword and sample offsets count
+    // from there (res = 0 or 1 sample).  Every load reads only dwords that
+    // hold at least one wanted value.
+    const uint32_t toff = ((uint32_t)(half * P) + (uint32_t)pc) * 4u;
+    auto step_s0 = [&](int i) { return min(sw + 2 * i * PX_U, se - 1); };
+    auto tab_rsrc = [&](int s0) {
+        return rsrc(J.tab + (size_t)s0 * P, (uint32_t)min(2 * PX_U, S - s0) * (uint32_t)P * 4u);
+    };
+    struct SigRsrc {
+        __amdgpu_buffer_rsrc_t r;
+        uint32_t res;
+    };
+    auto sig_rsrc = [&](int s0) {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(J.sig) + (size_t)s0 * N * esz;
+        SigRsrc g;
+        g.res = (uint32_t)(a & 3u) / esz;
+        const uint32_t n = (uint32_t)min(2 * PX_U, S - s0) * (uint32_t)N;
+        g.r = rsrc(reinterpret_cast<const void *>(a & ~(uintptr_t)3), ((g.res + n) * esz + 3u) & ~3u);
+        return g;
+    };
 
-    // q[0..3] = x[c .. c+3] of slot record k, scaled for FP16
-    auto load4 = [&](int k, int c, float (&q)[4]) {
+    // q[0..3] = x[c .. c+3] of record r = 2j + half of the step, scaled for FP16
+    auto load4 = [&](const SigRsrc &g, int j, int c, float (&q)[4]) {
         if constexpr (SFMT == PAT_SIG_F32) {
-            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, 4u * (hl + (uint32_t)c), k * N * 4, 0);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(g.r, 4u * ((uint32_t)(half * N) + (uint32_t)c),
+                                                                 2 * j * N * 4, 0);
             q[0] = __uint_as_float(v[0]); q[1] = __uint_as_float(v[1]);
             q[2] = __uint_as_float(v[2]); q[3] = __uint_as_float(v[3]);
         } else {
             // two dwords from the even sample at or below c, and for an odd
             // start the dword holding c+3 (else the first one again)
-            const uint32_t h = hl + (uint32_t)(k * N + c);
+            const uint32_t h = g.res + (uint32_t)((2 * j + half) * N + c);
             const bool odd = h & 1u;
             const uint32_t e = 2u * (h & ~1u);
-            const auto d = __builtin_amdgcn_raw_buffer_load_b64(rs, e, 0, 0);
-            const uint32_t d2 = __builtin_amdgcn_raw_buffer_load_b32(rs, odd ? e + 8u : e, 0, 0);
+            const auto d = __builtin_amdgcn_raw_buffer_load_b64(g.r, e, 0, 0);
+            const uint32_t d2 = __builtin_amdgcn_raw_buffer_load_b32(g.r, odd ? e + 8u : e, 0, 0);
             const uint32_t e0 = odd ? __builtin_amdgcn_alignbyte(d[1], d[0], 2) : d[0];
             const uint32_t e1 = odd ? __builtin_amdgcn_alignbyte(d2, d[1], 2) : d[1];
             q[0] = h2f(e0 & 0xFFFFu) * sc; q[1] = h2f(e0 >> 16) * sc;
             q[2] = h2f(e1 & 0xFFFFu) * sc; q[3] = h2f(e1 >> 16) * sc;
         }
     };
-    // b[n], b[n+1] of slot record k (filtered input; n <= N-2)
-    auto load2 = [&](int k, int n, float &b0, float &b1) {
+    // b[n], b[n+1] of record 2j + half of the step (filtered input; n <= N-2)
+    auto load2 = [&](const SigRsrc &g, int j, int n, float &b0, float &b1) {
         if constexpr (SFMT == PAT_SIG_F32) {
-            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, 4u * (hl + (uint32_t)n), k * N * 4, 0);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(g.r, 4u * ((uint32_t)(half * N) + (uint32_t)n),
+                                                                2 * j * N * 4, 0);
             b0 = __uint_as_float(v[0]);
             b1 = __uint_as_float(v[1]);
         } else {
             // the dword holding n, and for odd n the one holding n+1
-            const uint32_t h = hl + (uint32_t)(k * N + n);
+            const uint32_t h = g.res + (uint32_t)((2 * j + half) * N + n);
             const bool odd = h & 1u;
             const uint32_t e = 2u * (h & ~1u);
-            const uint32_t d0 = __builtin_amdgcn_raw_buffer_load_b32(rs, e, 0, 0);
-            const uint32_t d1 = __builtin_amdgcn_raw_buffer_load_b32(rs, odd ? e + 4u : e, 0, 0);
+            const uint32_t d0 = __builtin_amdgcn_raw_buffer_load_b32(g.r, e, 0, 0);
+            const uint32_t d1 = __builtin_amdgcn_raw_buffer_load_b32(g.r, odd ? e + 4u : e, 0, 0);
             const uint32_t pair = odd ? __builtin_amdgcn_alignbyte(d1, d0, 2) : d0;
             b0 = h2f(pair & 0xFFFFu) * sc;
             b1 = h2f(pair >> 16) * sc;
@@ -165,41 +176,40 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     };
 
     // Every step issues the same loads, so the waits between the stages are
-    // static: a slot position past the slot's end (or a step past the last)
-    // re-reads the slot's last record and contributes nothing.
+    // static: a step past the last re-reads the wave's last records, and a
+    // sensor past the wave's end reads zeros (outside the descriptor) and
+    // contributes nothing.
     auto delays = [&](int i, Stage &st) {
+        const __amdgpu_buffer_rsrc_t rt = tab_rsrc(step_s0(i));
 #pragma unroll
-        for (int j = 0; j < PX_U; ++j) {
-            const int k = min(i * PX_U + j, sps - 1);
-            st.d[j] = __builtin_amdgcn_raw_buffer_load_b32(rt, toff, k * P * 4, 0);
-        }
+        for (int j = 0; j < PX_U; ++j) st.d[j] = __builtin_amdgcn_raw_buffer_load_b32(rt, toff, 2 * j * P * 4, 0);
     };
     // decode the delays of step i and issue its sample loads; returns whether
     // a contributing lane sits at an end of its record (n = 0 or N-2)
     auto samples = [&](int i, Stage &st) -> bool {
+        const int s0 = sw + 2 * i * PX_U;
+        const SigRsrc g = sig_rsrc(step_s0(i));
         bool end = false;
 #pragma unroll
         for (int j = 0; j < PX_U; ++j) {
-            const int k = i * PX_U + j;  // sensor within the slot
-            const int kc = min(k, sps - 1);
             int n = 1;
             float a = 0.0f;
             const bool dok = dec.decode(st.d[j], N, n, a);
-            const bool ok = dok & (s_lo + k < s_hi);
+            const bool ok = dok & (s0 + 2 * j + half < se);
             float ws = 1.0f;
             if constexpr (HAS_W) {
-                const float ws0 = J.w[min(sw + kc, S - 1)];
-                const float ws1 = J.w[min(sw + sps + kc, S - 1)];
+                const float ws0 = J.w[min(s0 + 2 * j, S - 1)];
+                const float ws1 = J.w[min(s0 + 2 * j + 1, S - 1)];
                 ws = half ? ws1 : ws0;
             }
             st.w[j] = ok ? ws : 0.0f;
             st.n[j] = ok ? n : 1;
             st.a[j] = ok ? a : 0.0f;
             if constexpr (FILTERED) {
-                load2(kc, st.n[j], st.q[j][1], st.q[j][2]);
+                load2(g, j, st.n[j], st.q[j][1], st.q[j][2]);
             } else {
                 end |= ok & ((n == 0) | (n == N - 2));
-                load4(kc, min(max(st.n[j] - 1, 0), N - 4), st.q[j]);
+                load4(g, j, min(max(st.n[j] - 1, 0), N - 4), st.q[j]);
             }
         }
         return end;
@@ -364,8 +374,7 @@ int launch_px(bool filtered, int S, int P, int F, const uint32_t *tab, const voi
 bool pat_px_eligible(int sig_fmt, int S, int P, int N, int F, const void *sig) {
     if (S <= 0 || P <= 0 || F <= 0 || N < 4) return false;
     if ((uintptr_t)sig % (sig_fmt == PAT_SIG_F16 ? 2 : 4) != 0) return false;
-    // the widest slots: one wave per workgroup
-    return px_offsets_fit(px_sps(S, 1), P, N, sig_fmt);
+    return px_offsets_fit(P, N, sig_fmt);
 }
 
 int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig, int sig_fmt, int sig_is_filtered,
@@ -393,7 +402,7 @@ int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig,
 
 bool pat_px_multi_eligible(int sig_fmt, int S, int P, int N) {
     if (S <= 0 || P <= 0 || N < 4) return false;
-    return px_offsets_fit(px_sps(S, PX_MULTI_WAVES), P, N, sig_fmt);
+    return px_offsets_fit(P, N, sig_fmt);
 }
 
 int pat_px_frame_shape(pat_bp_desc *d, int S, int P, int N, double t0, double dt) {
