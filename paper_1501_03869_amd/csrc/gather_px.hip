@@ -75,6 +75,20 @@ __device__ __forceinline__ float h2f(uint32_t bits16) {
     return __half2float(__ushort_as_half((unsigned short)bits16));
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin by workgroup index, each
+// XCD with its own L2.  Tile rows of the table are 128 bytes that generally
+// straddle two cache lines, shared with the neighbouring tiles, so
+// neighbouring tiles are kept on one XCD: launch slot b (8 * ceil(T/8) slots)
+// runs tile x*q + min(x, r) + k of the T tiles (x = b % 8, k = b / 8,
+// T = 8q + r), i.e. XCD x takes one contiguous run of tiles; -1 for the at
+// most 7 slots with no tile.
+__device__ __forceinline__ int xcd_tile(int b, int T) {
+    const int q = T >> 3, r = T & 7, x = b & 7, k = b >> 3;
+    return k < q + (x < r ? 1 : 0) ? x * q + min(x, r) + k : -1;
+}
+
+__host__ __device__ inline int xcd_slots(int T) { return (T + 7) & ~7; }
+
 // One workgroup's work: tile `tile` of one frame, all S sensors.
 struct PxJob {
     const uint32_t *tab;  // [S][P] delays
@@ -296,7 +310,9 @@ __global__ void __launch_bounds__(64 * PX_MAX_WAVES)
     J.t0dt = t0dt;
     J.scale = (SFMT == PAT_SIG_F16 && scale) ? scale[f] : 1.0f;
     // a wave-uniform wave index keeps the descriptors in scalar registers
-    px_block<Delay, SFMT, FILTERED, HAS_W>(J, dec, blockIdx.x, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+    const int tile = xcd_tile(blockIdx.x, (P + PX_T - 1) / PX_T);
+    if (tile < 0) return;
+    px_block<Delay, SFMT, FILTERED, HAS_W>(J, dec, tile, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
                                            blockDim.x >> 6);
 }
 
@@ -318,7 +334,8 @@ __global__ void __launch_bounds__(64 * PX_MULTI_WAVES) k_bp_px_multi(const pat_b
     J.S = D.S; J.P = D.P; J.N = D.N; J.sps = D.sps;
     J.t0dt = D.t0dt;
     J.scale = D.scale;
-    const int tile = b - D.block_begin;
+    const int tile = xcd_tile(b - D.block_begin, D.tiles);
+    if (tile < 0) return;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if constexpr (TFMT == PAT_TABLE_F32) {
         DelayF32 dec;
@@ -352,7 +369,7 @@ int launch_one(int S, int P, int F, const uint32_t *tab, const void *sig, const 
         }
         sh = px_shape(S, P, F, cache_cus, [&](int W) { return cache_bpc[W]; });
     }
-    const dim3 grid(sh.tiles, F);
+    const dim3 grid(xcd_slots(sh.tiles), F);
     k_bp_px<Delay, SFMT, FILTERED, HAS_W><<<grid, dim3(64 * sh.waves), 0, st>>>(tab, sig, scale, w, S, P, N, sh.sps,
                                                                                 dec, t0dt, img);
     PAT_HIP(hipGetLastError());
@@ -410,7 +427,7 @@ int pat_px_frame_shape(pat_bp_desc *d, int S, int P, int N, double t0, double dt
     d->P = P;
     d->N = N;
     d->sps = px_sps(S, PX_MULTI_WAVES);
-    d->tiles = (P + PX_T - 1) / PX_T;
+    d->tiles = (P + PX_T - 1) / PX_T;  // launch slots: xcd_slots(tiles), a multiple of 8
     d->t0dt = (float)(t0 / dt);
     const double inv = 1.0 / dt;
     d->inv_hi = (float)inv;
@@ -418,7 +435,7 @@ int pat_px_frame_shape(pat_bp_desc *d, int S, int P, int N, double t0, double dt
     d->off = (float)(-t0 / dt);
     d->umax = (float)(N - 1);
     d->scale = 1.0f;
-    return d->tiles;
+    return xcd_slots(d->tiles);
 }
 
 int pat_launch_px_multi(const pat_bp_desc *d_descs, int nd, int total_blocks, int table_fmt, int sig_fmt,

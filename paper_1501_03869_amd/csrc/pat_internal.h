@@ -52,8 +52,8 @@ struct pat_bp_desc {
     const float *w;        // [S] sensor weights or null
     float *img;            // [P] output
     int S, P, N, sps;      // sps: sensors per slot (two slots per wave)
-    int tiles;             // workgroups of this frame (32 pixels each)
-    int block_begin;       // first workgroup of this frame in the launch
+    int tiles;             // 32-pixel tiles of this frame
+    int block_begin;       // first workgroup of this frame in the launch (a multiple of 8)
     float t0dt, scale;                // t0/dt; FP16 frame scale (1 otherwise)
     float inv_hi, inv_lo, off, umax;  // float32-seconds delay decoding
 };
@@ -61,7 +61,8 @@ struct pat_bp_desc {
 // Whether a map of this shape can go through the multi-frame gather.
 bool pat_px_multi_eligible(int sig_fmt, int S, int P, int N);
 // Fills the shape and decoding fields of d for one frame; returns the number
-// of workgroups it needs.
+// of workgroups it needs (a multiple of 8, so that the next frame's
+// block_begin stays a multiple of 8).
 int pat_px_frame_shape(pat_bp_desc *d, int S, int P, int N, double t0, double dt);
 int pat_launch_px_multi(const pat_bp_desc *d_descs, int nd, int total_blocks, int table_fmt, int sig_fmt,
                         hipStream_t st);
