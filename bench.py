@@ -33,6 +33,32 @@ sys.path.insert(0, ROOT)
 METRIC = "BP pixel·sensor gathers/s, frames/s, p50/p99 frame latency @512 sensors"
 HBM_PEAK_GBS = 8000.0
 
+# Memory traffic of the single-frame gather kernel per launch, from two
+# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch, mean over the dispatches), each scaled by the same counter's
+# reading for a plain 256 MB device copy (--copy-calibration 256: FETCH_SIZE
+# reads 125012 KiB of 250000 KiB moved, factor 2.0; WRITE_SIZE reads 250000,
+# factor 1.0).  Valid only for the kernel sources they were taken on: the
+# SHA-256 of the files below; any change makes the field null until the
+# counters are taken again.  Summaries: profiles/k_bp_px_*_hbm_counters.md.
+TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_common.h")
+TRAFFIC_SHA = "e4989fde3e523b0b0bb3b9851ac10d1dd61a3445ccc28bec81263c437f402874:" \
+              "a37bc85842687f9694ec167ede1da698e9c9a9ebb1e9dba9e7802a2916df1515"
+FETCH_FACTOR = 250000.0 / 125012.33
+WRITE_FACTOR = 1.0
+TRAFFIC_KIB = {"paper": (25477.65, 83.39), "large": (1903187.46, 3283.76)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+
+
+def measured_traffic(config: str):
+    """Bytes per launch from the stored counters, or None if the kernel changed."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    sha = ":".join(hashlib.sha256(open(os.path.join(here, f), "rb").read()).hexdigest() for f in TRAFFIC_SOURCES)
+    if sha != TRAFFIC_SHA or config not in TRAFFIC_KIB:
+        return None
+    fetch, write = TRAFFIC_KIB[config]
+    return (fetch * FETCH_FACTOR + write * WRITE_FACTOR) * 1024.0
+
 
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
@@ -321,11 +347,20 @@ def main():
         r = i % args.frames
         ctx.backproject(table, frames[r], geo.dt, geo.t0, filtered=False, out=img[r], stream=st or stream)
 
-    # (a) per-launch device time: HIP events around every launch on its stream
+    # (a) per-launch device time: HIP events around every launch on its
+    # stream (p50/p99), and two events around the whole run of back-to-back
+    # launches (the mean launch duration the roofline uses)
     _, dev_ms = timed(step, args.steps, args.warmup)
     S, P, N = geo.S, geo.P, geo.n_samples
     bytes_per_frame = 4 * S * P + 4 * S * N + 4 * P
-    avg_kernel_s = float(np.mean(dev_ms)) * 1e-3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(args.steps):
+        step(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    avg_kernel_s = e0.elapsed_time(e1) * 1e-3 / args.steps
     achieved = bytes_per_frame / avg_kernel_s / 1e9
 
     # (b) throughput: the same single-frame launches, captured back to back in
@@ -390,7 +425,9 @@ def main():
                    "sensors": S, "pixels": P, "samples": N, "frames_per_step": 1, "table_format": "f32"},
         "frames_per_s": args.steps / wall,
         "timing_note": "value/frames_per_s: single-frame launches replayed from a HIP graph of up to 64 launches; "
-                       "device_ms_* and roofline: HIP events around each eager launch",
+                       "device_ms_*: HIP events around each eager launch; roofline: HIP events around the run of "
+                       "back-to-back eager launches (mean launch duration)",
+        "device_ms_per_frame_mean": avg_kernel_s * 1e3,
         "device_ms_per_frame_p50": percentile(dev_ms, 50),
         "device_ms_per_frame_p99": percentile(dev_ms, 99),
         "latency_ms_p50": percentile(lat, 50),
@@ -399,9 +436,12 @@ def main():
         "table_build_s": build_s,
         "table_build_rounds": est["rounds"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_bp: fused UBP filter + delay-and-sum gather, one launch per frame",
-                     "algorithmic_bytes_per_launch": bytes_per_frame},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
+                     "kernel": "pat_backproject, one launch per frame (k_bp_px at these shapes: fused UBP filter "
+                               "+ delay-and-sum gather, sensors split inside 32-pixel-tile workgroups)",
+                     "algorithmic_bytes_per_launch": bytes_per_frame,
+                     "traffic_note": "bytes per launch from FETCH_SIZE + WRITE_SIZE scaled by a plain copy's "
+                                     "counters; null when not measured for this config or kernel source"},
         "paper_context": "123.79 ms for 512 sensors x 21323 pixels on an NVIDIA Tesla C2075, transfers included",
     }
     if not args.no_variants:
