@@ -104,7 +104,7 @@ struct PxJob {
 struct Stage {
     uint32_t d[PX_U];
     int n[PX_U];
-    float a[PX_U], w[PX_U], q[PX_U][4];
+    float k[PX_U], a[PX_U], w[PX_U], q[PX_U][4];
 };
 
 // The sensors of wave wv for pixel tile*32 + lane%32: the wave owns sensors
@@ -199,7 +199,10 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         for (int j = 0; j < PX_U; ++j) st.d[j] = __builtin_amdgcn_raw_buffer_load_b32(rt, toff, 2 * j * P * 4, 0);
     };
     // decode the delays of step i and issue its sample loads; returns whether
-    // a contributing lane sits at an end of its record (n = 0 or N-2)
+    // a decodable delay of the step sits at an end of its record (n = 0 or
+    // N-2).  Whether a slot position holds a sensor at all is decided per
+    // half-wave with scalar arithmetic and folded into the weight.
+    const float t0h = 0.5f * t0dt;
     auto samples = [&](int i, Stage &st) -> bool {
         const int s0 = sw + 2 * i * PX_U;
         const SigRsrc g = sig_rsrc(step_s0(i));
@@ -209,21 +212,21 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             int n = 1;
             float a = 0.0f;
             const bool dok = dec.decode(st.d[j], N, n, a);
-            const bool ok = dok & (s0 + 2 * j + half < se);
-            float ws = 1.0f;
+            float ws0 = s0 + 2 * j < se ? 1.0f : 0.0f;
+            float ws1 = s0 + 2 * j + 1 < se ? 1.0f : 0.0f;
             if constexpr (HAS_W) {
-                const float ws0 = J.w[min(s0 + 2 * j, S - 1)];
-                const float ws1 = J.w[min(s0 + 2 * j + 1, S - 1)];
-                ws = half ? ws1 : ws0;
+                ws0 *= J.w[min(s0 + 2 * j, S - 1)];
+                ws1 *= J.w[min(s0 + 2 * j + 1, S - 1)];
             }
-            st.w[j] = ok ? ws : 0.0f;
-            st.n[j] = ok ? n : 1;
-            st.a[j] = ok ? a : 0.0f;
+            st.w[j] = dok ? (half ? ws1 : ws0) : 0.0f;
+            st.a[j] = dok ? a : 0.0f;
+            st.n[j] = n;
+            st.k[j] = fmaf((float)n, 0.5f, t0h);  // (n + t0/dt) / 2
             if constexpr (FILTERED) {
-                load2(g, j, st.n[j], st.q[j][1], st.q[j][2]);
+                load2(g, j, min(max(n, 0), N - 2), st.q[j][1], st.q[j][2]);
             } else {
-                end |= ok & ((n == 0) | (n == N - 2));
-                load4(g, j, min(max(st.n[j] - 1, 0), N - 4), st.q[j]);
+                end |= dok & ((n == 0) | (n == N - 2));
+                load4(g, j, min(max(n - 1, 0), N - 4), st.q[j]);
             }
         }
         return end;
@@ -232,7 +235,6 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     auto sum = [&](const Stage &st, bool any_end) {
 #pragma unroll
         for (int j = 0; j < PX_U; ++j) {
-            const int n = st.n[j];
             float b0, b1;
             if constexpr (FILTERED) {
                 b0 = st.q[j][1];
@@ -241,10 +243,10 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
                 // every contributing lane has 1 <= n <= N-3, so q = p[n-1 .. n+2]
                 // and both samples take central differences:
                 // b[m] = p[m] - (m + t0/dt) * (p[m+1] - p[m-1]) / 2
-                const float k0 = ((float)n + t0dt) * 0.5f;
-                b0 = fmaf(-k0, st.q[j][2] - st.q[j][0], st.q[j][1]);
-                b1 = fmaf(-(k0 + 0.5f), st.q[j][3] - st.q[j][1], st.q[j][2]);
+                b0 = fmaf(-st.k[j], st.q[j][2] - st.q[j][0], st.q[j][1]);
+                b1 = fmaf(-(st.k[j] + 0.5f), st.q[j][3] - st.q[j][1], st.q[j][2]);
             } else {  // q = p[c .. c+3] with c = n-1 clipped to [0, N-4]
+                const int n = min(max(st.n[j], 0), N - 2);
                 const int sh = (n - 1) - min(max(n - 1, 0), N - 4);  // -1 at n = 0, +1 at n = N-2
                 const float pm = sh == 1 ? st.q[j][1] : st.q[j][0];
                 const float p0 = sh < 0 ? st.q[j][0] : (sh == 0 ? st.q[j][1] : st.q[j][2]);
@@ -257,19 +259,21 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         }
     };
 
-    // two stages alternate: while step i is summed from one, the delays of
-    // step i+2 and the samples of step i+1 are in flight in the other
+    // Two stages alternate.  Loads are issued in the order they are needed
+    // (vector loads complete in order): the delays of step i+2, then the
+    // samples of step i+1 (whose delays came two issues earlier), then step i
+    // is summed from samples issued one half-iteration before.
     Stage A, B;
     delays(0, A);
     delays(1, B);
     bool endA = samples(0, A), endB = false;
     for (int i = 0; i < nstep; i += 2) {
-        endB = samples(i + 1, B);
         delays(i + 2, A);
+        endB = samples(i + 1, B);
         sum(A, __any(endA));
         if (i + 1 >= nstep) break;
-        endA = samples(i + 2, A);
         delays(i + 3, B);
+        endA = samples(i + 2, A);
         sum(B, __any(endB));
     }
     return acc;
