@@ -175,13 +175,15 @@ int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, doubl
  * Accumulation is FP32 in a fixed order, so results are bitwise reproducible
  * for fixed inputs and sizes.  Uses context scratch of
  * pat_backproject_scratch_bytes(S, P, F) bytes (allocated on first need, or
- * up front by pat_ctx_reserve).  When F >= 2, N is a multiple of 8 (FP16) or
- * 4 (FP32) and d_sig is 16-byte aligned, one launch reads the table once for
- * all frames.  Otherwise, when the frame needs its sensors split over several
- * workgroups to fill the GPU, N >= 4 and 2*ceil(S/2) records of the table
- * and of the signal stay below 2 GiB, the sensors are split inside one
- * workgroup per 32-pixel tile (no scratch); else LDS-windowed workgroups
- * over sensor groups add their partial sums in scratch.
+ * up front by pat_ctx_reserve).  Kernel choice (results agree to the stated
+ * tolerances, not bitwise, across kernels): with F >= 2, a table above
+ * 128 MiB, N a multiple of 8 (FP16) or 4 (FP32) and d_sig 16-byte aligned,
+ * one launch reads the table once per 16 frames; otherwise, when N >= 4 and
+ * d_sig is aligned to its sample size, the sensors of each 32-pixel tile
+ * are split inside one workgroup (no scratch) for several frames or for a
+ * frame too small to fill the GPU otherwise; the remaining shapes use
+ * LDS-windowed workgroups over sensor groups, which add their partial sums
+ * in scratch.
  */
 int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,

@@ -470,11 +470,20 @@ int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const
         PAT_HIP(hipMemsetAsync(img, 0, (size_t)P * F * sizeof(float), st));
         return PAT_OK;
     }
-    if (pat_batch_eligible(sig_fmt, N, F, sig))
+    // Kernel choice.  Several frames whose table stays in the 256 MB Infinity
+    // Cache between frames are fastest with the split-sensor kernel, one
+    // table read per frame (paper workload, 64 frames: 10 us per frame against
+    // 17 for the batched kernel); a larger table is read once per 16 frames
+    // by the batched kernel (1024^2 workload: 0.64 against 0.88 ms per
+    // frame).  A single frame that would split its sensors over workgroups
+    // takes the split-sensor kernel; the rest take the windowed kernel.
+    const bool px_ok = pat_px_eligible(sig_fmt, S, P, N, F, sig);
+    const size_t table_bytes = (size_t)S * P * 4;
+    if (F >= 2 && pat_batch_eligible(sig_fmt, N, F, sig) && (!px_ok || table_bytes > PAT_CACHED_TABLE_BYTES))
         return pat_launch_backproject_batch(ctx, table, table_fmt, sig, sig_fmt, sig_is_filtered, frame_scale, w, S, P,
                                             N, F, t0, dt, img, st);
     const BpShape sh = bp_shape(S, P, F);
-    if (sh.groups > 1 && pat_px_eligible(sig_fmt, S, P, N, F, sig))
+    if (px_ok && (sh.groups > 1 || F >= 2))
         return pat_launch_backproject_px(table, table_fmt, sig, sig_fmt, sig_is_filtered, frame_scale, w, S, P, N, F,
                                          t0, dt, img, st);
     float *part = nullptr;

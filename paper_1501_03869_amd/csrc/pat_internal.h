@@ -73,6 +73,9 @@ int pat_launch_table_to_q16(const float *T, int64_t n, double t0, double dt, int
                             hipStream_t st);
 // Gather scratch shared by the single-frame and batched kernels.
 size_t pat_gather_counter_bytes(int P, int F);
+// Tables up to this size are taken to stay cached between frames (half of
+// the 256 MB Infinity Cache, leaving the rest to the frames streaming past).
+constexpr size_t PAT_CACHED_TABLE_BYTES = 128ull << 20;
 // one-pixel-per-lane gather (no LDS windows, no partial sums in global memory)
 bool pat_px_eligible(int sig_fmt, int S, int P, int N, int F, const void *sig);
 int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig, int sig_fmt, int sig_is_filtered,

@@ -321,6 +321,39 @@ def test_backproject_batched_matches_oracle(ctx, orc, F, sig, filtered, q16):
         assert err <= IMG_TOL
 
 
+@pytest.mark.parametrize("F,sig,filtered,q16", [(2, "f32", False, False), (3, "f16", True, True),
+                                                (2, "f16", False, True)])
+def test_backproject_batched_large_table(ctx, orc, F, sig, filtered, q16):
+    # a table above 128 MiB (1088 sensors x 31000 pixels, straight-ray delays
+    # on the 256^2 grid) takes the batched kernel, which reads it once per 16
+    # frames; smaller tables go through the split-sensor kernel per frame
+    from paper_1501_03869_amd import pat
+    geo = inputs.config("paper")
+    dt, N, S, P = 4e-8, 2048, 1088, 31000
+    allpix = pat.tile_order(geo.nx, geo.ny, np.arange(geo.nx * geo.ny, dtype=np.int32), 32, 32)[:P]
+    sensors = inputs.ring_sensors(S, 24.5e-3)
+    T = orc.tables_const(geo.nx, geo.ny, geo.h, 1540.0, sensors, allpix).astype(np.float32)
+    assert T.nbytes > 128 * 2 ** 20
+    p = inputs.random_signals(31, S, N, F)
+    w = np.random.default_rng(32).uniform(0.5, 1.5, S).astype(np.float32)
+    tab = ctx.table_to_q16(dev(T), dt, N) if q16 else dev(T)
+    if sig == "f16":
+        scale, h, vals = _fp16_frames(p)
+        got = ctx.backproject(tab, dev(h), dt, filtered=filtered, w=dev(w), frame_scale=dev(scale))
+    else:
+        vals = p.astype(np.float64)
+        got = ctx.backproject(tab, dev(p), dt, filtered=filtered, w=dev(w))
+    got = got.cpu().numpy()
+    b = vals if filtered else orc.filt(vals, dt)
+    if q16:
+        ref = orc.gather_q16(tab.cpu().numpy().view(np.uint32), b, w.astype(np.float64))
+    else:
+        ref = orc.gather(T.astype(np.float64), b, dt, 0.0, w.astype(np.float64))
+    err = rel_l2(got, ref)
+    print(f"[batch-large] F={F} {sig} filtered={filtered} q16={q16} rel L2 {err:.3e}", flush=True)
+    assert err <= IMG_TOL
+
+
 def _v3_error_bound(q, T64, p, scale, dt, w):
     """A-priori per-pixel bound of |img_V3 - img_FP64| for one frame: 16.16
     delays, binary16 samples with a per-frame scale, FP32 arithmetic.
