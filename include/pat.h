@@ -125,6 +125,9 @@ typedef struct pat_eikonal_stats {
     int64_t rounds;          /* relaxation rounds (kernel launches), all chunks */
     int64_t tile_visits;     /* tiles processed over all rounds */
     int64_t guard_hits;      /* FP64 fallbacks of the quadratic solve */
+    int64_t sweeps;          /* in-tile relaxation sweeps over all tile visits; each
+                                sweep applies the local update to the tile's
+                                32 x 32 nodes once */
     double lsb_seconds;      /* fixed-point unit of the working times */
     double seconds;          /* wall time of the call */
 } pat_eikonal_stats;

@@ -189,6 +189,7 @@ __global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ 
     if (sides) atomicOr(&side_bits, sides);
     __syncthreads();
     if (tid == 0) {
+        atomicAdd(reinterpret_cast<unsigned long long *>(counters + 2), (unsigned long long)min(it + 1, LOCAL_ITER_CAP));
         const unsigned sb = side_bits;
         uint32_t *cnt_next = counters;
         const uint32_t base = (uint32_t)m * g.tiles_per_map;
@@ -293,7 +294,7 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
                            static_cast<uint32_t *>(ctx->eik_lists.ptr) + max_tiles };
     int *seed_ij = static_cast<int *>(ctx->eik_seeds.ptr);
     uint32_t *seed_val = reinterpret_cast<uint32_t *>(seed_ij + 2 * chunk);
-    uint32_t *counters = static_cast<uint32_t *>(ctx->eik_count.ptr);  // [0] next count, [1] guard hits
+    uint32_t *counters = static_cast<uint32_t *>(ctx->eik_count.ptr);  // [0] next count, [1] guard hits, [2..3] sweeps
 
     PAT_HIP(hipMemcpyAsync(Fd, Fh.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice, st));
     PAT_HIP(hipMemsetAsync(ctx->eik_flags.ptr, 0, (size_t)2 * max_tiles * sizeof(uint32_t), st));
@@ -351,7 +352,7 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
             k_eik_tile<<<dim3(cnt), EK_THREADS, 0, st>>>(Tq, Fd, g, seed_ij, seed_val, lists[cur], flags[cur],
                                                          lists[cur ^ 1], flags[cur ^ 1], counters);
             PAT_HIP(hipGetLastError());
-            PAT_HIP(hipMemcpyAsync(ctx->eik_count_host, counters, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            PAT_HIP(hipMemcpyAsync(ctx->eik_count_host, counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
             PAT_HIP(hipStreamSynchronize(st));
             visits += cnt;
             cnt = ctx->eik_count_host[0];
@@ -367,6 +368,7 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
     ctx->last_eik.rounds = rounds;
     ctx->last_eik.tile_visits = visits;
     ctx->last_eik.guard_hits = ctx->eik_count_host[1];
+    ctx->last_eik.sweeps = (int64_t)ctx->eik_count_host[2] | ((int64_t)ctx->eik_count_host[3] << 32);
     ctx->last_eik.seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     return PAT_OK;

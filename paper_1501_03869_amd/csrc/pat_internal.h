@@ -37,7 +37,7 @@ struct pat_ctx {
     pat_devbuf sensors;
     // eikonal working memory
     pat_devbuf eik_tq, eik_f, eik_flags, eik_lists, eik_seeds, eik_count;
-    uint32_t *eik_count_host = nullptr;  // pinned, 2 counters
+    uint32_t *eik_count_host = nullptr;  // pinned: next-round count, guard hits, sweeps (64-bit)
     pat_eikonal_stats last_eik{};
 };
 

@@ -55,7 +55,7 @@ class ServerStats(C.Structure):
 
 class EikonalStats(C.Structure):
     _fields_ = [("rounds", C.c_int64), ("tile_visits", C.c_int64), ("guard_hits", C.c_int64),
-                ("lsb_seconds", C.c_double), ("seconds", C.c_double)]
+                ("sweeps", C.c_int64), ("lsb_seconds", C.c_double), ("seconds", C.c_double)]
 
 
 _lib = None
