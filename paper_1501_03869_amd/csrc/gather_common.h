@@ -23,6 +23,17 @@ struct DelayF32 {
     __device__ __forceinline__ bool decode(uint32_t bits, int N, int &n, float &a) const {
         return decode(__uint_as_float(bits), N, n, a);
     }
+    // The same decoding without branches: n and a are computed for every
+    // lane (from u clamped to 0 when the delay does not contribute).
+    __device__ __forceinline__ bool decode_bf(uint32_t bits, int N, int &n, float &a) const {
+        const float T = __uint_as_float(bits);
+        const float u = fmaf(T, inv_hi, fmaf(T, inv_lo, off));
+        const bool ok = u >= 0.0f && u <= umax;  // also rejects NaN and inf
+        const float uc = ok ? u : 0.0f;
+        n = min((int)uc, N - 2);
+        a = uc - (float)n;
+        return ok;
+    }
     // Window-relative, branch-free decoding for an LDS window that starts at
     // sample an: idx = floor(u) - an and a = frac(u) with u' = u - an computed
     // directly (the anchor folds into the offset, so u' keeps more fraction
@@ -56,6 +67,14 @@ struct DelayQ16 {
             a = 1.0f;
         }
         return true;
+    }
+    __device__ __forceinline__ bool decode_bf(uint32_t q, int N, int &n, float &a) const {
+        const bool ok = q != 0xFFFFFFFFu;
+        const int n0 = (int)(q >> 16);
+        const bool last = n0 > N - 2;  // only u = N-1 exactly
+        n = last ? N - 2 : n0;
+        a = last ? 1.0f : (float)(q & 0xFFFFu) * (1.0f / 65536.0f);
+        return ok;
     }
     struct Win { int an; };
     __device__ __forceinline__ Win window(int an) const { return Win{ an }; }

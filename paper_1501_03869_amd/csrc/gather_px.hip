@@ -211,7 +211,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         for (int j = 0; j < PX_U; ++j) {
             int n = 1;
             float a = 0.0f;
-            const bool dok = dec.decode(st.d[j], N, n, a);
+            const bool dok = dec.decode_bf(st.d[j], N, n, a);
             float ws0 = s0 + 2 * j < se ? 1.0f : 0.0f;
             float ws1 = s0 + 2 * j + 1 < se ? 1.0f : 0.0f;
             if constexpr (HAS_W) {
@@ -219,7 +219,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
                 ws1 *= J.w[min(s0 + 2 * j + 1, S - 1)];
             }
             st.w[j] = dok ? (half ? ws1 : ws0) : 0.0f;
-            st.a[j] = dok ? a : 0.0f;
+            st.a[j] = a;  // 0 when the delay does not contribute
             st.n[j] = n;
             st.k[j] = fmaf((float)n, 0.5f, t0h);  // (n + t0/dt) / 2
             if constexpr (FILTERED) {
