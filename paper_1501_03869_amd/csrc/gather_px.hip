@@ -263,17 +263,24 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     // (vector loads complete in order): the delays of step i+2, then the
     // samples of step i+1 (whose delays came two issues earlier), then step i
     // is summed from samples issued one half-iteration before.
+    // The scheduling barriers keep the issue order as written.
     Stage A, B;
     delays(0, A);
     delays(1, B);
+    __builtin_amdgcn_sched_barrier(0);
     bool endA = samples(0, A), endB = false;
+    __builtin_amdgcn_sched_barrier(0);
     for (int i = 0; i < nstep; i += 2) {
         delays(i + 2, A);
+        __builtin_amdgcn_sched_barrier(0);
         endB = samples(i + 1, B);
+        __builtin_amdgcn_sched_barrier(0);
         sum(A, __any(endA));
         if (i + 1 >= nstep) break;
         delays(i + 3, B);
+        __builtin_amdgcn_sched_barrier(0);
         endA = samples(i + 2, A);
+        __builtin_amdgcn_sched_barrier(0);
         sum(B, __any(endB));
     }
     return acc;
