@@ -519,12 +519,14 @@ int pat_launch_backproject_const(pat_ctx *ctx, int nx, int ny, double h, double 
                                  const int32_t *d_pix, int P, const void *sig, int sig_fmt, int sig_is_filtered,
                                  const float *frame_scale, const float *w, int N, int F, double t0, double dt,
                                  float *img, hipStream_t st) {
-    (void)ny;
     if (S == 0) {
         PAT_HIP(hipMemsetAsync(img, 0, (size_t)P * F * sizeof(float), st));
         return PAT_OK;
     }
     const BpShape sh = bp_shape(S, P, F);
+    if ((sh.groups > 1 || F >= 2) && pat_px_eligible(sig_fmt, S, P, N, F, sig))
+        return pat_launch_backproject_px_const(nx, h, c, d_sxy, S, d_pix, P, sig, sig_fmt, sig_is_filtered,
+                                               frame_scale, w, N, F, t0, dt, img, ny, st);
     float *part = nullptr;
     unsigned int *done = nullptr;
     if (sh.groups > 1) {

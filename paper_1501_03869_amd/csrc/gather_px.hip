@@ -97,6 +97,12 @@ struct PxJob {
     float *img;           // [P] output of this frame
     int S, P, N, sps;
     float t0dt, scale;
+    // straight-ray delays |x - s| / c instead of a table (conventional back
+    // projection): pixel node indices, sensor positions, grid
+    const int32_t *pix;
+    const float *sxy;     // [S][2] metres
+    int nx;
+    float h, x0, y0, inv_c;
 };
 
 // One pipeline stage: the delays of U sensors of this lane's slot, decoded,
@@ -111,7 +117,7 @@ struct Stage {
 // sw .. sw+2*sps-1 (sw = wv*2*sps, clipped to S); lanes 0-31 take the even
 // ones, lanes 32-63 the odd ones.  wv must be wave-uniform (a scalar) and
 // sw < S.
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W>
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, bool CONSTC = false>
 __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, int tile, int wv) {
     const int S = J.S, P = J.P, N = J.N, sps = J.sps;
     const float t0dt = J.t0dt, sc = J.scale;
@@ -193,10 +199,28 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     // static: a step past the last re-reads the wave's last records, and a
     // sensor past the wave's end reads zeros (outside the descriptor) and
     // contributes nothing.
+    float pxx = 0.0f, pxy = 0.0f;  // this lane's pixel position (straight-ray delays)
+    if constexpr (CONSTC) {
+        const int k = J.pix[pc];
+        pxx = J.x0 + (float)(k % J.nx) * J.h;
+        pxy = J.y0 + (float)(k / J.nx) * J.h;
+    }
     auto delays = [&](int i, Stage &st) {
-        const __amdgpu_buffer_rsrc_t rt = tab_rsrc(step_s0(i));
+        if constexpr (CONSTC) {
+            const int s0 = step_s0(i);
 #pragma unroll
-        for (int j = 0; j < PX_U; ++j) st.d[j] = __builtin_amdgcn_raw_buffer_load_b32(rt, toff, 2 * j * P * 4, 0);
+            for (int j = 0; j < PX_U; ++j) {
+                const int sa = min(s0 + 2 * j, S - 1), sb = min(s0 + 2 * j + 1, S - 1);
+                const float sx = half ? J.sxy[2 * sb] : J.sxy[2 * sa];
+                const float sy = half ? J.sxy[2 * sb + 1] : J.sxy[2 * sa + 1];
+                const float dx = pxx - sx, dy = pxy - sy;
+                st.d[j] = __float_as_uint(__builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy)) * J.inv_c);
+            }
+        } else {
+            const __amdgpu_buffer_rsrc_t rt = tab_rsrc(step_s0(i));
+#pragma unroll
+            for (int j = 0; j < PX_U; ++j) st.d[j] = __builtin_amdgcn_raw_buffer_load_b32(rt, toff, 2 * j * P * 4, 0);
+        }
     };
     // decode the delays of step i and issue its sample loads; returns whether
     // a decodable delay of the step sits at an end of its record (n = 0 or
@@ -288,13 +312,13 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
 
 // One tile of one frame: every wave sums its slots, then the slot sums are
 // added in slot order.  Waves whose slots start past S add zero.
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W>
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, bool CONSTC = false>
 __device__ __forceinline__ void px_block(const PxJob &J, const Delay &dec, int tile, int wv, int nw) {
     __shared__ float red[2 * PX_MAX_WAVES][PX_T];
     const int lane = threadIdx.x & 63;
     const int px = lane & (PX_T - 1);
     float acc = 0.0f;
-    if (wv * 2 * J.sps < J.S) acc = px_slot_sum<Delay, SFMT, FILTERED, HAS_W>(J, dec, tile, wv);
+    if (wv * 2 * J.sps < J.S) acc = px_slot_sum<Delay, SFMT, FILTERED, HAS_W, CONSTC>(J, dec, tile, wv);
     red[wv * 2 + (lane >> 5)][px] = acc;
     __syncthreads();
     const int p = tile * PX_T + px;
@@ -305,11 +329,20 @@ __device__ __forceinline__ void px_block(const PxJob &J, const Delay &dec, int t
     }
 }
 
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W>
+// Straight-ray geometry of the conventional back projection (unused with a
+// table).
+struct PxGeom {
+    const int32_t *pix;
+    const float *sxy;
+    int nx;
+    float h, x0, y0, inv_c;
+};
+
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, bool CONSTC>
 __global__ void __launch_bounds__(64 * PX_MAX_WAVES)
     k_bp_px(const uint32_t *__restrict__ tab, const void *__restrict__ sig, const float *__restrict__ scale,
             const float *__restrict__ w, int S, int P, int N, int sps, Delay dec, float t0dt,
-            float *__restrict__ img) {
+            float *__restrict__ img, PxGeom geo) {
     const int f = blockIdx.y;
     constexpr size_t esz = SFMT == PAT_SIG_F16 ? 2 : 4;
     PxJob J;
@@ -320,11 +353,13 @@ __global__ void __launch_bounds__(64 * PX_MAX_WAVES)
     J.S = S; J.P = P; J.N = N; J.sps = sps;
     J.t0dt = t0dt;
     J.scale = (SFMT == PAT_SIG_F16 && scale) ? scale[f] : 1.0f;
+    J.pix = geo.pix; J.sxy = geo.sxy; J.nx = geo.nx;
+    J.h = geo.h; J.x0 = geo.x0; J.y0 = geo.y0; J.inv_c = geo.inv_c;
     // a wave-uniform wave index keeps the descriptors in scalar registers
     const int tile = xcd_tile(blockIdx.x, (P + PX_T - 1) / PX_T);
     if (tile < 0) return;
-    px_block<Delay, SFMT, FILTERED, HAS_W>(J, dec, tile, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
-                                           blockDim.x >> 6);
+    px_block<Delay, SFMT, FILTERED, HAS_W, CONSTC>(J, dec, tile, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+                                                   blockDim.x >> 6);
 }
 
 // Frames of different geometries in one launch: workgroup b belongs to the
@@ -360,9 +395,9 @@ __global__ void __launch_bounds__(64 * PX_MULTI_WAVES) k_bp_px_multi(const pat_b
     }
 }
 
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W>
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, bool CONSTC = false>
 int launch_one(int S, int P, int F, const uint32_t *tab, const void *sig, const float *scale, const float *w, int N,
-               Delay dec, float t0dt, float *img, hipStream_t st) {
+               Delay dec, float t0dt, float *img, hipStream_t st, const PxGeom &geo = PxGeom{}) {
     // occupancy per block size, computed once per kernel and device
     static std::mutex mu;
     static int cache_dev = -1, cache_cus = 0, cache_bpc[PX_MAX_WAVES + 1];
@@ -375,14 +410,14 @@ int launch_one(int S, int P, int F, const uint32_t *tab, const void *sig, const 
             PAT_HIP(hipDeviceGetAttribute(&cache_cus, hipDeviceAttributeMultiprocessorCount, dev));
             for (int W = 1; W <= PX_MAX_WAVES; ++W)
                 PAT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &cache_bpc[W], k_bp_px<Delay, SFMT, FILTERED, HAS_W>, 64 * W, 0));
+                    &cache_bpc[W], k_bp_px<Delay, SFMT, FILTERED, HAS_W, CONSTC>, 64 * W, 0));
             cache_dev = dev;
         }
         sh = px_shape(S, P, F, cache_cus, [&](int W) { return cache_bpc[W]; });
     }
     const dim3 grid(xcd_slots(sh.tiles), F);
-    k_bp_px<Delay, SFMT, FILTERED, HAS_W><<<grid, dim3(64 * sh.waves), 0, st>>>(tab, sig, scale, w, S, P, N, sh.sps,
-                                                                                dec, t0dt, img);
+    k_bp_px<Delay, SFMT, FILTERED, HAS_W, CONSTC><<<grid, dim3(64 * sh.waves), 0, st>>>(
+        tab, sig, scale, w, S, P, N, sh.sps, dec, t0dt, img, geo);
     PAT_HIP(hipGetLastError());
     return PAT_OK;
 }
@@ -397,7 +432,44 @@ int launch_px(bool filtered, int S, int P, int F, const uint32_t *tab, const voi
                     : launch_one<Delay, SFMT, false, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
 }
 
+template <int SFMT>
+int launch_px_const(bool filtered, int S, int P, int F, const void *sig, const float *scale, const float *w, int N,
+                    DelayF32 dec, float t0dt, float *img, hipStream_t st, const PxGeom &geo) {
+    if (w)
+        return filtered
+                   ? launch_one<DelayF32, SFMT, true, true, true>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo)
+                   : launch_one<DelayF32, SFMT, false, true, true>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo);
+    return filtered
+               ? launch_one<DelayF32, SFMT, true, false, true>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo)
+               : launch_one<DelayF32, SFMT, false, false, true>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo);
+}
+
 }  // namespace
+
+int pat_launch_backproject_px_const(int nx, double h, double c, const float *d_sxy, int S, const int32_t *d_pix,
+                                    int P, const void *sig, int sig_fmt, int sig_is_filtered, const float *frame_scale,
+                                    const float *w, int N, int F, double t0, double dt, float *img, int ny,
+                                    hipStream_t st) {
+    DelayF32 d;
+    const double inv = 1.0 / dt;
+    d.inv_hi = (float)inv;
+    d.inv_lo = (float)(inv - (double)d.inv_hi);
+    d.off = (float)(-t0 / dt);
+    d.umax = (float)(N - 1);
+    PxGeom g;
+    g.pix = d_pix;
+    g.sxy = d_sxy;
+    g.nx = nx;
+    g.h = (float)h;
+    g.x0 = (float)(-0.5 * (nx - 1) * h);
+    g.y0 = (float)(-0.5 * (ny - 1) * h);
+    g.inv_c = (float)(1.0 / c);
+    const float t0dt = (float)(t0 / dt);
+    const bool filt = sig_is_filtered != 0;
+    return sig_fmt == PAT_SIG_F32
+               ? launch_px_const<PAT_SIG_F32>(filt, S, P, F, sig, frame_scale, w, N, d, t0dt, img, st, g)
+               : launch_px_const<PAT_SIG_F16>(filt, S, P, F, sig, frame_scale, w, N, d, t0dt, img, st, g);
+}
 
 bool pat_px_eligible(int sig_fmt, int S, int P, int N, int F, const void *sig) {
     if (S <= 0 || P <= 0 || F <= 0 || N < 4) return false;

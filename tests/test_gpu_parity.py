@@ -461,20 +461,29 @@ def test_q16_at_the_sample_limit(ctx, orc):
 
 # ----------------------------------------------------------------------------- conventional BP
 
-@pytest.mark.parametrize("F,filtered", [(1, False), (3, True)])
-def test_backproject_const_matches_oracle(ctx, orc, F, filtered):
-    # straight-ray delays computed per gather against the oracle's |x - s| / c table
+@pytest.mark.parametrize("F,filtered,S,sig", [(1, False, 512, "f32"), (3, True, 512, "f32"), (2, False, 512, "f16"),
+                                               (1, False, 8, "f32"), (2, True, 8, "f16")])
+def test_backproject_const_matches_oracle(ctx, orc, F, filtered, S, sig):
+    # straight-ray delays computed per gather against the oracle's |x - s| / c
+    # table; 512 sensors split over workgroups, 8 fit in one
     geo = inputs.config("paper")
     pix = geo.pix[:9001]
+    sensors = geo.sensors[:: geo.S // S][:S]
     c = 1560.0
-    p = inputs.random_signals(31, geo.S, geo.n_samples, F)
-    T = orc.tables_const(geo.nx, geo.ny, geo.h, c, geo.sensors, pix)
-    got = ctx.backproject_const(geo.nx, geo.ny, geo.h, c, geo.sensors, dev(pix), dev(p), geo.dt,
-                                filtered=filtered).cpu().numpy()
+    p = inputs.random_signals(31, S, geo.n_samples, F)
+    T = orc.tables_const(geo.nx, geo.ny, geo.h, c, sensors, pix)
+    if sig == "f16":
+        scale, h, vals = _fp16_frames(p if F > 1 else p[None])
+        got = ctx.backproject_const(geo.nx, geo.ny, geo.h, c, sensors, dev(pix), dev(h if F > 1 else h[0]), geo.dt,
+                                    filtered=filtered, frame_scale=dev(scale)).cpu().numpy()
+        p = vals if F > 1 else vals[0]
+    else:
+        got = ctx.backproject_const(geo.nx, geo.ny, geo.h, c, sensors, dev(pix), dev(p), geo.dt,
+                                    filtered=filtered).cpu().numpy()
     b = p if filtered else orc.filt(p, geo.dt)
     ref = orc.gather(T, b, geo.dt)
     err = rel_l2(got, ref)
-    print(f"[const] F={F} filtered={filtered} rel L2 {err:.3e}", flush=True)
+    print(f"[const] F={F} filtered={filtered} S={S} {sig} rel L2 {err:.3e}", flush=True)
     assert err <= 3e-4
 
 
