@@ -42,11 +42,11 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 of the files below; any change makes the field null until the
 # counters are taken again.  Summaries: profiles/k_bp_px_*_hbm_counters.md.
 TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_common.h")
-TRAFFIC_SHA = "e4989fde3e523b0b0bb3b9851ac10d1dd61a3445ccc28bec81263c437f402874:" \
-              "a37bc85842687f9694ec167ede1da698e9c9a9ebb1e9dba9e7802a2916df1515"
-FETCH_FACTOR = 250000.0 / 125012.33
+TRAFFIC_SHA = "00f1132b3bd80dff52284d542073f345d3366c96d257a7d15d9e5f5c80974408:" \
+              "929644709dbf60bb072c43dfc23c2ee332cfcd7183960112783b1274ca458d26"
+FETCH_FACTOR = 250000.0 / 125012.38
 WRITE_FACTOR = 1.0
-TRAFFIC_KIB = {"paper": (25477.65, 83.39), "large": (1903187.46, 3283.76)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+TRAFFIC_KIB = {"paper": (25506.94, 83.42), "large": (1901651.06, 3307.79)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 
 
 def measured_traffic(config: str):

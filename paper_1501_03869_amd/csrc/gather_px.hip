@@ -154,7 +154,9 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         return g;
     };
 
-    // q[0..3] = x[c .. c+3] of record r = 2j + half of the step, scaled for FP16
+    // q[0..3] = x[c .. c+3] of record r = 2j + half of the step.  FP16: the
+    // raw dwords and the start's parity are kept, and the samples are cut out
+    // (unscaled) only when they are summed, so nothing waits for the load here.
     auto load4 = [&](const SigRsrc &g, int j, int c, float (&q)[4]) {
         if constexpr (SFMT == PAT_SIG_F32) {
             const auto v = __builtin_amdgcn_raw_buffer_load_b128(g.r, 4u * ((uint32_t)(half * N) + (uint32_t)c),
@@ -169,29 +171,52 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             const uint32_t e = 2u * (h & ~1u);
             const auto d = __builtin_amdgcn_raw_buffer_load_b64(g.r, e, 0, 0);
             const uint32_t d2 = __builtin_amdgcn_raw_buffer_load_b32(g.r, odd ? e + 8u : e, 0, 0);
-            const uint32_t e0 = odd ? __builtin_amdgcn_alignbyte(d[1], d[0], 2) : d[0];
-            const uint32_t e1 = odd ? __builtin_amdgcn_alignbyte(d2, d[1], 2) : d[1];
-            q[0] = h2f(e0 & 0xFFFFu) * sc; q[1] = h2f(e0 >> 16) * sc;
-            q[2] = h2f(e1 & 0xFFFFu) * sc; q[3] = h2f(e1 >> 16) * sc;
+            q[0] = __uint_as_float(d[0]);
+            q[1] = __uint_as_float(d[1]);
+            q[2] = __uint_as_float(d2);
+            q[3] = odd ? 1.0f : 0.0f;
+        }
+    };
+    // the four samples of a stage slot as floats (FP16: unscaled)
+    auto taps = [&](const float (&q)[4], float (&p)[4]) {
+        if constexpr (SFMT == PAT_SIG_F32) {
+            p[0] = q[0]; p[1] = q[1]; p[2] = q[2]; p[3] = q[3];
+        } else {
+            const bool odd = q[3] != 0.0f;
+            const uint32_t d0 = __float_as_uint(q[0]), d1 = __float_as_uint(q[1]), d2 = __float_as_uint(q[2]);
+            const uint32_t e0 = odd ? __builtin_amdgcn_alignbyte(d1, d0, 2) : d0;
+            const uint32_t e1 = odd ? __builtin_amdgcn_alignbyte(d2, d1, 2) : d1;
+            p[0] = h2f(e0 & 0xFFFFu); p[1] = h2f(e0 >> 16);
+            p[2] = h2f(e1 & 0xFFFFu); p[3] = h2f(e1 >> 16);
         }
     };
     // b[n], b[n+1] of record 2j + half of the step (filtered input; n <= N-2)
-    auto load2 = [&](const SigRsrc &g, int j, int n, float &b0, float &b1) {
+    // into q[1], q[2]; FP16: the dword holding n, the one holding n+1 (for
+    // odd n) and the parity, cut out when summed
+    auto load2 = [&](const SigRsrc &g, int j, int n, float (&q)[4]) {
         if constexpr (SFMT == PAT_SIG_F32) {
             const auto v = __builtin_amdgcn_raw_buffer_load_b64(g.r, 4u * ((uint32_t)(half * N) + (uint32_t)n),
                                                                 2 * j * N * 4, 0);
-            b0 = __uint_as_float(v[0]);
-            b1 = __uint_as_float(v[1]);
+            q[1] = __uint_as_float(v[0]);
+            q[2] = __uint_as_float(v[1]);
         } else {
-            // the dword holding n, and for odd n the one holding n+1
             const uint32_t h = g.res + (uint32_t)((2 * j + half) * N + n);
             const bool odd = h & 1u;
             const uint32_t e = 2u * (h & ~1u);
-            const uint32_t d0 = __builtin_amdgcn_raw_buffer_load_b32(g.r, e, 0, 0);
-            const uint32_t d1 = __builtin_amdgcn_raw_buffer_load_b32(g.r, odd ? e + 4u : e, 0, 0);
-            const uint32_t pair = odd ? __builtin_amdgcn_alignbyte(d1, d0, 2) : d0;
-            b0 = h2f(pair & 0xFFFFu) * sc;
-            b1 = h2f(pair >> 16) * sc;
+            q[1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(g.r, e, 0, 0));
+            q[2] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(g.r, odd ? e + 4u : e, 0, 0));
+            q[3] = odd ? 1.0f : 0.0f;
+        }
+    };
+    auto pair = [&](const float (&q)[4], float &b0, float &b1) {
+        if constexpr (SFMT == PAT_SIG_F32) {
+            b0 = q[1];
+            b1 = q[2];
+        } else {
+            const uint32_t d0 = __float_as_uint(q[1]), d1 = __float_as_uint(q[2]);
+            const uint32_t e = q[3] != 0.0f ? __builtin_amdgcn_alignbyte(d1, d0, 2) : d0;
+            b0 = h2f(e & 0xFFFFu);
+            b1 = h2f(e >> 16);
         }
     };
 
@@ -247,7 +272,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             st.n[j] = n;
             st.k[j] = fmaf((float)n, 0.5f, t0h);  // (n + t0/dt) / 2
             if constexpr (FILTERED) {
-                load2(g, j, min(max(n, 0), N - 2), st.q[j][1], st.q[j][2]);
+                load2(g, j, min(max(n, 0), N - 2), st.q[j]);
             } else {
                 end |= dok & ((n == 0) | (n == N - 2));
                 load4(g, j, min(max(n - 1, 0), N - 4), st.q[j]);
@@ -261,23 +286,26 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         for (int j = 0; j < PX_U; ++j) {
             float b0, b1;
             if constexpr (FILTERED) {
-                b0 = st.q[j][1];
-                b1 = st.q[j][2];
-            } else if (!any_end) {
-                // every contributing lane has 1 <= n <= N-3, so q = p[n-1 .. n+2]
-                // and both samples take central differences:
-                // b[m] = p[m] - (m + t0/dt) * (p[m+1] - p[m-1]) / 2
-                b0 = fmaf(-st.k[j], st.q[j][2] - st.q[j][0], st.q[j][1]);
-                b1 = fmaf(-(st.k[j] + 0.5f), st.q[j][3] - st.q[j][1], st.q[j][2]);
-            } else {  // q = p[c .. c+3] with c = n-1 clipped to [0, N-4]
-                const int n = min(max(st.n[j], 0), N - 2);
-                const int sh = (n - 1) - min(max(n - 1, 0), N - 4);  // -1 at n = 0, +1 at n = N-2
-                const float pm = sh == 1 ? st.q[j][1] : st.q[j][0];
-                const float p0 = sh < 0 ? st.q[j][0] : (sh == 0 ? st.q[j][1] : st.q[j][2]);
-                const float p1 = sh < 0 ? st.q[j][1] : (sh == 0 ? st.q[j][2] : st.q[j][3]);
-                const float p2 = sh < 0 ? st.q[j][2] : st.q[j][3];
-                b0 = ubp(pm, p0, p1, n, N, t0dt);
-                b1 = ubp(p0, p1, p2, n + 1, N, t0dt);
+                pair(st.q[j], b0, b1);
+            } else {
+                float q[4];
+                taps(st.q[j], q);
+                if (!any_end) {
+                    // every contributing lane has 1 <= n <= N-3, so q = p[n-1 .. n+2]
+                    // and both samples take central differences:
+                    // b[m] = p[m] - (m + t0/dt) * (p[m+1] - p[m-1]) / 2
+                    b0 = fmaf(-st.k[j], q[2] - q[0], q[1]);
+                    b1 = fmaf(-(st.k[j] + 0.5f), q[3] - q[1], q[2]);
+                } else {  // q = p[c .. c+3] with c = n-1 clipped to [0, N-4]
+                    const int n = min(max(st.n[j], 0), N - 2);
+                    const int sh = (n - 1) - min(max(n - 1, 0), N - 4);  // -1 at n = 0, +1 at n = N-2
+                    const float pm = sh == 1 ? q[1] : q[0];
+                    const float p0 = sh < 0 ? q[0] : (sh == 0 ? q[1] : q[2]);
+                    const float p1 = sh < 0 ? q[1] : (sh == 0 ? q[2] : q[3]);
+                    const float p2 = sh < 0 ? q[2] : q[3];
+                    b0 = ubp(pm, p0, p1, n, N, t0dt);
+                    b1 = ubp(p0, p1, p2, n + 1, N, t0dt);
+                }
             }
             acc = fmaf(st.w[j], fmaf(st.a[j], b1 - b0, b0), acc);
         }
@@ -307,7 +335,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         __builtin_amdgcn_sched_barrier(0);
         sum(B, __any(endB));
     }
-    return acc;
+    return acc * sc;  // the FP16 frame scale (1 otherwise); filter and interpolation are linear
 }
 
 // One tile of one frame: every wave sums its slots, then the slot sums are
