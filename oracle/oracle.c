@@ -24,6 +24,8 @@
  *      in time (Section II-C, Eq. BP; weights default to 1 as in the paper).
  *   5. orc_table_to_q16 / orc_gather_q16: the same gather from a delay table
  *      stored as a 16.16 fixed-point fractional sample index.
+ *   6. orc_seed3 / orc_fmm3 / orc_tables3: steps 1-2 on a 3-D grid with the
+ *      6-neighbour Godunov update (3-D reconstruction, Section IV).
  *
  * Readings where the paper is silent (all FP64):
  *   - nodes carry the speed; missing neighbours beyond the grid edge are +inf;
@@ -291,6 +293,202 @@ int orc_tables_const(int nx, int ny, double h, double c, const double *sxy, int 
         }
     }
     return 0;
+}
+
+/* ---------------------------------------------------------- 3-D eikonal */
+/*
+ * The same method on a 3-D grid, the extension the paper anticipates for 3-D
+ * reconstruction (Section IV): node (i, j, l) with index k = (l ny + j) nx + i
+ * at ((i - (nx-1)/2) h, (j - (ny-1)/2) h, (l - (nz-1)/2) h), a 6-neighbour
+ * stencil, missing neighbours +inf, and the first-order Godunov update with
+ * the three upwind minima.  With nz = 1 every z-neighbour is missing and
+ * everything below reduces, operation for operation, to the 2-D code above.
+ */
+
+/* Godunov update from the smallest accepted neighbours along x, y and z.
+ * Sorted a <= b <= c: one-sided a + fh if that is not above b; else the
+ * two-sided root of (T-a)^2 + (T-b)^2 = fh^2 if that is not above c; else the
+ * three-sided root of (T-a)^2 + (T-b)^2 + (T-c)^2 = fh^2.  Each root is
+ * written relative to a (incremental form). */
+static double godunov3(double a, double b, double c, double fh) {
+    double t;
+    if (b < a) { t = a; a = b; b = t; }
+    if (c < b) { t = b; b = c; c = t; }
+    if (b < a) { t = a; a = b; b = t; }
+    if (isinf(a)) return INFINITY;
+    double d = b - a;
+    if (isinf(d) || d >= fh) return a + fh;
+    double x = 0.5 * (d + sqrt(2.0 * fh * fh - d * d));
+    double e = c - a;
+    if (isinf(e) || x <= e) return a + x;
+    double sum = d + e;
+    double disc = sum * sum - 3.0 * (d * d + e * e - fh * fh);
+    return a + (sum + sqrt(disc)) / 3.0;
+}
+
+static void upwind3(int nx, int ny, int nz, long m, const unsigned char *state, const double *T,
+                    double *a, double *b, double *c) {
+    long nxy = (long)nx * ny;
+    int i = (int)(m % nx), j = (int)((m / nx) % ny), l = (int)(m / nxy);
+    *a = *b = *c = INFINITY;
+    if (i > 0 && state[m - 1] == ORC_KNOWN) *a = fmin(*a, T[m - 1]);
+    if (i < nx - 1 && state[m + 1] == ORC_KNOWN) *a = fmin(*a, T[m + 1]);
+    if (j > 0 && state[m - nx] == ORC_KNOWN) *b = fmin(*b, T[m - nx]);
+    if (j < ny - 1 && state[m + nx] == ORC_KNOWN) *b = fmin(*b, T[m + nx]);
+    if (l > 0 && state[m - nxy] == ORC_KNOWN) *c = fmin(*c, T[m - nxy]);
+    if (l < nz - 1 && state[m + nxy] == ORC_KNOWN) *c = fmin(*c, T[m + nxy]);
+}
+
+/* Fast marching over a 3-D grid; arguments as orc_fmm. */
+int orc_fmm3(int nx, int ny, int nz, double h, const double *slow, const unsigned char *frozen, double *T,
+             long *npop) {
+    long nxy = (long)nx * ny, n = nxy * nz;
+    unsigned char *state = (unsigned char *)calloc((size_t)n, 1);
+    orc_heap hp = { 0, 0, 0 };
+    if (!state) return -1;
+    for (long k = 0; k < n; ++k) {
+        if (frozen[k]) state[k] = ORC_KNOWN;
+        else T[k] = INFINITY;
+    }
+    const int di[6] = { -1, 1, 0, 0, 0, 0 }, dj[6] = { 0, 0, -1, 1, 0, 0 }, dl[6] = { 0, 0, 0, 0, -1, 1 };
+    long pops = 0;
+    int rc = 0;
+    for (long k = 0; k < n; ++k) {
+        if (!frozen[k]) continue;
+        int i = (int)(k % nx), j = (int)((k / nx) % ny), l = (int)(k / nxy);
+        for (int q = 0; q < 6; ++q) {
+            int ii = i + di[q], jj = j + dj[q], ll = l + dl[q];
+            if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || ll < 0 || ll >= nz) continue;
+            long m = ((long)ll * ny + jj) * nx + ii;
+            if (state[m] != ORC_KNOWN) state[m] = ORC_TRIAL;
+        }
+    }
+    for (long m = 0; m < n && rc == 0; ++m) {
+        if (state[m] != ORC_TRIAL) continue;
+        double a, b, c;
+        upwind3(nx, ny, nz, m, state, T, &a, &b, &c);
+        T[m] = godunov3(a, b, c, slow[m] * h);
+        if (heap_push(&hp, T[m], (int32_t)m)) rc = -1;
+    }
+    while (rc == 0 && hp.n > 0) {
+        orc_item it = heap_pop(&hp);
+        long k = it.idx;
+        if (state[k] == ORC_KNOWN || it.key != T[k]) continue; /* stale entry */
+        state[k] = ORC_KNOWN;
+        ++pops;
+        int i = (int)(k % nx), j = (int)((k / nx) % ny), l = (int)(k / nxy);
+        for (int q = 0; q < 6; ++q) {
+            int ii = i + di[q], jj = j + dj[q], ll = l + dl[q];
+            if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || ll < 0 || ll >= nz) continue;
+            long m = ((long)ll * ny + jj) * nx + ii;
+            if (state[m] == ORC_KNOWN) continue;
+            double a, b, c;
+            upwind3(nx, ny, nz, m, state, T, &a, &b, &c);
+            double t = godunov3(a, b, c, slow[m] * h);
+            if (t < T[m]) {
+                T[m] = t;
+                state[m] = ORC_TRIAL;
+                if (heap_push(&hp, t, (int32_t)m)) { rc = -1; break; }
+            }
+        }
+    }
+    free(hp.a);
+    free(state);
+    if (npop) *npop = pops;
+    return rc;
+}
+
+/* Point-source initial condition in 3-D (as orc_seed): nodes within r0 of
+ * (sx, sy, sz) frozen at |x_k - s| * slow(n*).  Returns the frozen count, or
+ * -1 when the source is outside the grid's bounding box. */
+int orc_seed3(int nx, int ny, int nz, double h, const double *slow, double sx, double sy, double sz, double r0,
+              unsigned char *frozen, double *T) {
+    double x0 = -0.5 * (nx - 1) * h, y0 = -0.5 * (ny - 1) * h, z0 = -0.5 * (nz - 1) * h;
+    double gi = (sx - x0) / h, gj = (sy - y0) / h, gl = (sz - z0) / h;
+    if (!(gi >= 0.0 && gi <= nx - 1 && gj >= 0.0 && gj <= ny - 1 && gl >= 0.0 && gl <= nz - 1)) return -1;
+    int is = (int)floor(gi + 0.5), js = (int)floor(gj + 0.5), ls = (int)floor(gl + 0.5);
+    if (is > nx - 1) is = nx - 1;
+    if (js > ny - 1) js = ny - 1;
+    if (ls > nz - 1) ls = nz - 1;
+    double fs = slow[((long)ls * ny + js) * nx + is];
+    int rad = (int)ceil(r0 / h) + 1;
+    int cnt = 0;
+    memset(frozen, 0, (size_t)nx * ny * nz);
+    for (int l = ls - rad; l <= ls + rad; ++l) {
+        if (l < 0 || l >= nz) continue;
+        for (int j = js - rad; j <= js + rad; ++j) {
+            if (j < 0 || j >= ny) continue;
+            for (int i = is - rad; i <= is + rad; ++i) {
+                if (i < 0 || i >= nx) continue;
+                double dx = (x0 + i * h) - sx, dy = (y0 + j * h) - sy, dz = (z0 + l * h) - sz;
+                double r = sqrt(dx * dx + dy * dy + dz * dz);
+                if (r <= r0) {
+                    long k = ((long)l * ny + j) * nx + i;
+                    frozen[k] = 1;
+                    T[k] = r * fs;
+                    ++cnt;
+                }
+            }
+        }
+    }
+    return cnt;
+}
+
+/* 3-D delay table (as orc_tables): speed float32 [nz][ny][nx], sensors
+ * [S][3] metres, voxel indices pix[P]; returns 0, -1 bad input, -2 memory. */
+int orc_tables3(int nx, int ny, int nz, double h, const float *speed, const double *sxyz, int S,
+                const int32_t *pix, long P, double *table, int nthreads) {
+    long n = (long)nx * ny * nz;
+    for (long p = 0; p < P; ++p)
+        if (pix[p] < 0 || pix[p] >= n) return -1;
+    double *slow = (double *)malloc((size_t)n * sizeof(double));
+    if (!slow) return -2;
+    for (long k = 0; k < n; ++k) {
+        double c = (double)speed[k];
+        if (!(c > 0.0) || isinf(c)) { free(slow); return -1; }
+        slow[k] = 1.0 / c;
+    }
+    int rc = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+        double *T = (double *)malloc((size_t)n * sizeof(double));
+        unsigned char *fr = (unsigned char *)malloc((size_t)n);
+        if (!T || !fr) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            rc = -2;
+        }
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int s = 0; s < S; ++s) {
+            if (!T || !fr) continue;
+            int c = orc_seed3(nx, ny, nz, h, slow, sxyz[3 * s], sxyz[3 * s + 1], sxyz[3 * s + 2], 2.0 * h, fr, T);
+            if (c < 0) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+                rc = -1;
+                continue;
+            }
+            if (orc_fmm3(nx, ny, nz, h, slow, fr, T, 0)) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+                rc = -2;
+                continue;
+            }
+            for (long p = 0; p < P; ++p) table[(long)s * P + p] = T[pix[p]];
+        }
+        free(T);
+        free(fr);
+    }
+    free(slow);
+    return rc;
 }
 
 /* -------------------------------------------------------------- filter */

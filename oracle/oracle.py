@@ -61,6 +61,14 @@ def lib():
         L.orc_table_to_q16.restype = None
         L.orc_gather_q16.argtypes = [_u32, _dp, C.c_void_p, C.c_int, C.c_long, C.c_int, C.c_int, _dp, C.c_int]
         L.orc_gather_q16.restype = None
+        L.orc_fmm3.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, _dp, _u8, _dp, C.POINTER(C.c_long)]
+        L.orc_fmm3.restype = C.c_int
+        L.orc_seed3.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, _dp, C.c_double, C.c_double, C.c_double,
+                                C.c_double, _u8, _dp]
+        L.orc_seed3.restype = C.c_int
+        L.orc_tables3.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, _fp, _dp, C.c_int, _i32, C.c_long, _dp,
+                                  C.c_int]
+        L.orc_tables3.restype = C.c_int
         L.orc_max_threads.argtypes = []
         L.orc_max_threads.restype = C.c_int
         _lib = L
@@ -191,3 +199,53 @@ def gather_q16(q: np.ndarray, b: np.ndarray, w=None, nthreads: int = 0) -> np.nd
 def backproject(T: np.ndarray, p: np.ndarray, dt: float, t0: float = 0.0, w=None, nthreads: int = 0) -> np.ndarray:
     """Full back projection of raw signals: filter, then gather."""
     return gather(T, filt(p, dt, t0), dt, t0, w, nthreads)
+
+
+# ----------------------------------------------------------------------------- 3-D
+
+def fmm3(slow: np.ndarray, frozen: np.ndarray, T0: np.ndarray, h: float):
+    """Fast marching on a [nz][ny][nx] slowness grid from a frozen set.  Returns (T, pops)."""
+    nz, ny, nx = slow.shape
+    T = np.ascontiguousarray(T0, dtype=np.float64).copy()
+    pops = C.c_long(0)
+    rc = lib().orc_fmm3(nx, ny, nz, float(h), np.ascontiguousarray(slow, dtype=np.float64),
+                        np.ascontiguousarray(frozen, dtype=np.uint8), T, C.byref(pops))
+    if rc:
+        raise MemoryError("orc_fmm3")
+    return T, int(pops.value)
+
+
+def seed3(slow: np.ndarray, h: float, sx: float, sy: float, sz: float, r0: float | None = None):
+    """3-D point-source initial condition (frozen mask, T with frozen values set)."""
+    nz, ny, nx = slow.shape
+    fr = np.zeros((nz, ny, nx), dtype=np.uint8)
+    T = np.full((nz, ny, nx), np.inf)
+    c = lib().orc_seed3(nx, ny, nz, float(h), np.ascontiguousarray(slow, dtype=np.float64), float(sx), float(sy),
+                        float(sz), float(2.0 * h if r0 is None else r0), fr, T)
+    if c < 0:
+        raise ValueError("source outside the grid")
+    return fr.astype(bool), T
+
+
+def travel_time_map3(speed: np.ndarray, h: float, sx: float, sy: float, sz: float) -> np.ndarray:
+    """Full 3-D first-arrival map [nz][ny][nx] (seconds) from one point source."""
+    slow = 1.0 / np.asarray(speed, dtype=np.float64)
+    fr, T0 = seed3(slow, h, sx, sy, sz)
+    T, _ = fmm3(slow, fr, T0, h)
+    return T
+
+
+def tables3(speed: np.ndarray, h: float, sensors: np.ndarray, pix: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """3-D delay table T[S][P] (seconds, float64); speed [nz][ny][nx], sensors [S][3]."""
+    speed = np.ascontiguousarray(speed, dtype=np.float32)
+    nz, ny, nx = speed.shape
+    sxyz = np.ascontiguousarray(sensors, dtype=np.float64)
+    pix = np.ascontiguousarray(pix, dtype=np.int32)
+    S, P = sxyz.shape[0], pix.shape[0]
+    out = np.empty((S, P), dtype=np.float64)
+    rc = lib().orc_tables3(nx, ny, nz, float(h), speed, sxyz, S, pix, P, out, int(nthreads))
+    if rc == -1:
+        raise ValueError("orc_tables3: invalid input")
+    if rc:
+        raise MemoryError("orc_tables3")
+    return out

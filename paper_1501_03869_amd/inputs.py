@@ -322,3 +322,107 @@ def poisson_arrivals(rate_hz: float, duration_s: float, seed: int = SEED_ARRIVAL
     n = int(rate_hz * duration_s * 1.5) + 16
     t = np.cumsum(rng.exponential(1.0 / rate_hz, size=n))
     return t[t < duration_s]
+
+
+# ----------------------------------------------------------------------------- 3-D
+
+@dataclasses.dataclass
+class Geometry3:
+    """A 3-D imaging geometry: node-centred grid [nz][ny][nx], sensors on a sphere."""
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    h: float                 # metres
+    speed: np.ndarray        # float32 [nz][ny][nx], m/s
+    sensors: np.ndarray      # float64 [S][3], metres, grid-centred
+    pix: np.ndarray          # int32 [P], voxel indices (l*ny + j)*nx + i
+    n_samples: int
+    dt: float
+    t0: float = 0.0
+
+    @property
+    def S(self) -> int:
+        return int(self.sensors.shape[0])
+
+    @property
+    def P(self) -> int:
+        return int(self.pix.shape[0])
+
+
+def node_coords3(nx: int, ny: int, nz: int, h: float):
+    """(x[nx], y[ny], z[nz]) node coordinates in metres (grid-centred)."""
+    x, y = node_coords(nx, ny, h)
+    z = (np.arange(nz, dtype=np.float64) - (nz - 1) / 2.0) * h
+    return x, y, z
+
+
+def radius_map3(nx: int, ny: int, nz: int, h: float) -> np.ndarray:
+    x, y, z = node_coords3(nx, ny, nz, h)
+    return np.sqrt(z[:, None, None] ** 2 + y[None, :, None] ** 2 + x[None, None, :] ** 2)
+
+
+def sphere_sensors(S: int, R: float) -> np.ndarray:
+    """S sensors on a sphere of radius R (Fibonacci lattice), [S][3] metres."""
+    k = np.arange(S, dtype=np.float64) + 0.5
+    zc = 1.0 - 2.0 * k / S
+    rho = np.sqrt(np.maximum(0.0, 1.0 - zc * zc))
+    phi = np.pi * (3.0 - math.sqrt(5.0)) * k
+    return R * np.stack([rho * np.cos(phi), rho * np.sin(phi), zc], axis=1)
+
+
+def ball_voxels(nx: int, ny: int, nz: int, h: float, r: float) -> np.ndarray:
+    """Row-major voxel indices with radius < r."""
+    return np.flatnonzero(radius_map3(nx, ny, nz, h).ravel() < r).astype(np.int32)
+
+
+def head_speed3(seed: int, n: int, h: float, r_brain=11e-3, r_skull=14e-3, ell=2e-3, c_brain=1540.0,
+                brain_var=0.02, c_lo=2200.0, c_hi=3000.0, c_out=1540.0) -> np.ndarray:
+    """3-D analogue of skull_speed: brain ball with +-2 % smooth variation, skull
+    shell 2200..3000 m/s from a smooth random field, coupling medium outside."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rad = radius_map3(n, n, n, h)
+    brain = rad < r_brain
+    skull = (rad >= r_brain) & (rad < r_skull)
+    sig = (ell / math.sqrt(2.0)) / h
+    u = gaussian_filter(rng.standard_normal((n, n, n)), sigma=sig, mode="wrap")
+    v = gaussian_filter(rng.standard_normal((n, n, n)), sigma=sig, mode="wrap")
+    us = u[skull]
+    u = (u - us.min()) / (us.max() - us.min())
+    v = v / np.abs(v[brain]).max()
+    c = np.full((n, n, n), c_out, dtype=np.float64)
+    c[brain] = c_brain * (1.0 + brain_var * v[brain])
+    c[skull] = c_lo + (c_hi - c_lo) * u[skull]
+    return c.astype(np.float32)
+
+
+def config3(name: str) -> Geometry3:
+    """Named 3-D geometries.
+
+    tiny3 : 20^3, h = 0.5 mm, random medium 1400..3000 m/s, 6 sensors inside
+            the grid, all voxels.
+    head3 : 64^3, h = 0.5 mm, brain ball r < 11 mm, skull shell 11..14 mm,
+            256 sensors on a sphere r = 15 mm, 1024 samples at 20 MHz,
+            the voxels with r < 11 mm."""
+    if name == "tiny3":
+        n, h = 20, 0.5e-3
+        rng = np.random.Generator(np.random.PCG64(SEED_MAP + 30))
+        speed = rng.uniform(1400.0, 3000.0, size=(n, n, n)).astype(np.float32)
+        sens = rng.uniform(-4e-3, 4e-3, size=(6, 3))
+        return Geometry3(name, n, n, n, h, speed, sens, np.arange(n ** 3, dtype=np.int32), 512, 5e-8)
+    if name == "head3":
+        n, h = 64, 0.5e-3
+        return Geometry3(name, n, n, n, h, head_speed3(SEED_MAP + 31, n, h), sphere_sensors(256, 15e-3),
+                         ball_voxels(n, n, n, h, 11e-3), 1024, 5e-8)
+    raise KeyError(name)
+
+
+def source_distances3(geo: Geometry3, src_nodes: np.ndarray) -> np.ndarray:
+    """|x_k - s| in metres, [S][K]."""
+    x, y, z = node_coords3(geo.nx, geo.ny, geo.nz, geo.h)
+    i = src_nodes % geo.nx
+    j = (src_nodes // geo.nx) % geo.ny
+    l = src_nodes // (geo.nx * geo.ny)
+    d = np.stack([x[i], y[j], z[l]], axis=1)  # [K][3]
+    return np.linalg.norm(d[None, :, :] - geo.sensors[:, None, :], axis=2)
