@@ -13,8 +13,14 @@ Also timed (extra keys of the same JSON line): the 16.16-table and FP16
 variants, 64-frame batched launches replayed from a HIP graph, and a short
 serving mix (Poisson frames over three resident maps plus table builds).
 
+--config selects another workload: "large" (1024x1024 grid, 1024 sensors),
+the serving geometries, or the 3-D "head3" (64^3 voxel grid, 256 sensors on a
+sphere; tables from pat_eikonal_tables_3d, the same gather with voxels as
+pixels).
+
 Prints one JSON line.  Usage:
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-variants] [--serve SECONDS]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--config NAME] [--no-cpu] [--no-variants]
+                    [--serve SECONDS]
 """
 from __future__ import annotations
 
@@ -31,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "BP pixel·sensor gathers/s, frames/s, p50/p99 frame latency @512 sensors"
+VOLUME_CONFIGS = ("tiny3", "head3")  # 3-D geometries: voxels are gathered like pixels
 HBM_PEAK_GBS = 8000.0
 
 # Memory traffic of the single-frame gather kernel per launch, from two
@@ -79,7 +86,8 @@ def cpu_baseline(geo, table, frames, budget_s=12.0):
             break
     gathers = n * geo.S * geo.P
     return {"value": gathers / el, "unit": "gathers/s", "cores": orc.max_threads(), "kind": "oracle",
-            "sample": f"{n} whole frames ({geo.S} sensors x {geo.P} pixels) of the same workload, FP64 filter + "
+            "sample": f"{n} whole frames ({geo.S} sensors x {geo.P} {'voxels' if hasattr(geo, 'nz') else 'pixels'}) "
+                      f"of the same workload, FP64 filter + "
                       f"gather, {el:.1f} s"}
 
 
@@ -302,27 +310,37 @@ def main():
         return
     dev = torch.device("cuda:0")
     ctx = pat.Context(0)
-    geo = inputs.config(args.config)
-    print(f"[bench] {geo.name}: grid {geo.nx}x{geo.ny} S={geo.S} P={geo.P} N={geo.n_samples}", file=sys.stderr,
-          flush=True)
+    vol = args.config in VOLUME_CONFIGS
+    geo = inputs.config3(args.config) if vol else inputs.config(args.config)
+    grid = f"{geo.nx}x{geo.ny}x{geo.nz}" if vol else f"{geo.nx}x{geo.ny}"
+    print(f"[bench] {geo.name}: grid {grid} S={geo.S} P={geo.P} N={geo.n_samples}", file=sys.stderr, flush=True)
 
-    # ROI in 32x32-tile, Z-order-inside order: compact pixel blocks for the gather
-    geo.pix = pat.tile_order(geo.nx, geo.ny, geo.pix, 32, 32)
+    if vol:
+        # ROI in 4x4x2-voxel tiles: 32 neighbouring voxels per gather tile
+        geo.pix = pat.tile_order_3d(geo.nx, geo.ny, geo.nz, geo.pix, 4, 4, 2)
+    else:
+        # ROI in 32x32-tile, Z-order-inside order: compact pixel blocks for the gather
+        geo.pix = pat.tile_order(geo.nx, geo.ny, geo.pix, 32, 32)
     speed = torch.from_numpy(geo.speed).to(dev)
     pix = torch.from_numpy(geo.pix).to(dev)
+    build = ctx.eikonal_tables_3d if vol else ctx.eikonal_tables
+    build(speed, geo.h, geo.sensors, pix)  # first call: allocations and code loading
     torch.cuda.synchronize()
     t = time.perf_counter()
-    table = ctx.eikonal_tables(speed, geo.h, geo.sensors, pix)
+    table = build(speed, geo.h, geo.sensors, pix)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t
     est = ctx.eikonal_stats()
     print(f"[bench] tables built in {build_s:.3f} s ({est['rounds']} rounds)", file=sys.stderr, flush=True)
 
     table_h = table.cpu().numpy()
-    # the large grid's vascular phantom has tens of thousands of nodes: point
-    # absorbers keep its frame synthesis short (the content does not change the work)
-    phantom = "points" if geo.nx * geo.ny > 512 * 512 else "segments"
-    frames_h = [inputs.frame_for(geo, table_h, f, phantom=phantom) for f in range(args.frames)]
+    if vol:
+        frames_h = [inputs.frame_for3(geo, table_h, f) for f in range(args.frames)]
+    else:
+        # the large grid's vascular phantom has tens of thousands of nodes: point
+        # absorbers keep its frame synthesis short (the content does not change the work)
+        phantom = "points" if geo.nx * geo.ny > 512 * 512 else "segments"
+        frames_h = [inputs.frame_for(geo, table_h, f, phantom=phantom) for f in range(args.frames)]
     frames = torch.from_numpy(np.stack(frames_h)).to(dev)
     img = torch.empty((args.frames, geo.P), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
@@ -419,8 +437,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{geo.name}: {geo.nx}x{geo.ny} grid h={geo.h * 1e3:g} mm, {S} sensors, {P} ROI "
-                               f"pixels, {N} samples at {1e-6 / geo.dt:g} MHz, FP32 table + FP32 signals, "
+        "config": {"workload": f"{geo.name}: {grid} grid h={geo.h * 1e3:g} mm, {S} sensors, {P} ROI "
+                               f"{'voxels' if vol else 'pixels'}, {N} samples at {1e-6 / geo.dt:g} MHz, "
+                               f"FP32 table + FP32 signals, "
                                f"fused filter+gather, one frame per step",
                    "sensors": S, "pixels": P, "samples": N, "frames_per_step": 1, "table_format": "f32"},
         "frames_per_s": args.steps / wall,
@@ -435,6 +454,8 @@ def main():
         "latency_note": "host frame -> H2D -> fused filter+gather -> D2H image, synchronous, pinned buffers",
         "table_build_s": build_s,
         "table_build_rounds": est["rounds"],
+        "table_build_note": "pat_eikonal_tables" + ("_3d" if vol else "") + " wall time for all sensors (second "
+                            "call), host validation and seeding included",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
                      "kernel": "pat_backproject, one launch per frame (k_bp_px at these shapes: fused UBP filter "
@@ -446,7 +467,7 @@ def main():
     }
     if not args.no_variants:
         out["variants"] = run_variants(ctx, geo, table, frames, frames_h, stream, timed, args)
-    if args.serve > 0:
+    if args.serve > 0 and not vol:
         out["serving"] = [run_serving(ctx, args.serve, v) for v in ("v0", "v3")]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(geo, table_h, frames_h)

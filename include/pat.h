@@ -120,14 +120,42 @@ int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, int ny, doubl
                        const double *h_sensor_xy, int S, const int32_t *d_pix, int P,
                        float *d_table, void *stream);
 
-/* Statistics of the calling context's last pat_eikonal_tables call. */
+/*
+ * 3-D delay tables (3-D reconstruction, anticipated in Section IV): the same
+ * first-order upwind scheme on a 6-neighbour grid, each node updated from the
+ * upwind minima along x, y and z (one-, two- or three-sided root, whichever
+ * stays causal).  The delay-and-sum gather is unchanged: a voxel is a "pixel"
+ * of pat_backproject.
+ *
+ *   d_speed   float32 [nz][ny][nx] speed of sound (m/s), finite and > 0.
+ *   nx, ny, nz  grid size, each >= 1, at least 2 nodes, at most 2^30 nodes.
+ *   h         node spacing (metres), > 0, the same along all axes.
+ *   h_sensor_xyz  float64 [S][3] sensor positions (metres, grid-centred:
+ *             node (i, j, l) sits at ((i - (nx-1)/2) h, (j - (ny-1)/2) h,
+ *             (l - (nz-1)/2) h)), each inside the grid's bounding box.
+ *   d_vox     int32 [P] region-of-interest node indices k = (l*ny + j)*nx + i,
+ *             each in [0, nx*ny*nz).  Any order; the table follows it.
+ *   d_table   float32 [S][P] output, seconds.
+ *
+ * Seeding as in pat_eikonal_tables (nodes within 2h fixed at the straight-ray
+ * time at the nearest node's speed).  Relaxation runs on 8 x 8 x 8 bricks;
+ * statistics (pat_eikonal_last_stats) count bricks as tiles.  Synchronises
+ * `stream`.  PAT_EINVAL for bad sizes, speeds, sensors or voxel indices;
+ * PAT_ENOCONV if the relaxation exceeds its round cap (never expected).
+ */
+int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx, int ny, int nz, double h,
+                          const double *h_sensor_xyz, int S, const int32_t *d_vox, int P,
+                          float *d_table, void *stream);
+
+/* Statistics of the calling context's last pat_eikonal_tables or
+ * pat_eikonal_tables_3d call. */
 typedef struct pat_eikonal_stats {
     int64_t rounds;          /* relaxation rounds (kernel launches), all chunks */
-    int64_t tile_visits;     /* tiles processed over all rounds */
+    int64_t tile_visits;     /* tiles (3-D: bricks) processed over all rounds */
     int64_t guard_hits;      /* FP64 fallbacks of the quadratic solve */
     int64_t sweeps;          /* in-tile relaxation sweeps over all tile visits; each
                                 sweep applies the local update to the tile's
-                                32 x 32 nodes once */
+                                32 x 32 nodes (3-D: the brick's 8 x 8 x 8) once */
     double lsb_seconds;      /* fixed-point unit of the working times */
     double seconds;          /* wall time of the call */
 } pat_eikonal_stats;
@@ -151,6 +179,17 @@ int pat_table_to_q16(pat_ctx *ctx, const float *d_table, int64_t n, double t0, d
  */
 int pat_tile_order(int nx, int ny, const int32_t *h_pix, int P, int tile_w, int tile_h,
                    int32_t *h_pix_out);
+
+/*
+ * Host helper, the 3-D form of pat_tile_order for voxel indices
+ * k = (l*ny + j)*nx + i: tiles of tile_w x tile_h x tile_d voxels (each side
+ * <= 1024) snake through each layer of tiles (rows and layers alternate
+ * direction); Morton order inside a tile.  With 4 x 4 x 2 tiles every aligned
+ * run of 32 voxels of a full tile is one compact brick.  Stable for equal
+ * keys; h_vox_out may not alias h_vox.  Host only.
+ */
+int pat_tile_order_3d(int nx, int ny, int nz, const int32_t *h_vox, int P, int tile_w, int tile_h,
+                      int tile_d, int32_t *h_vox_out);
 
 /*
  * UBP filter (Section II-C): b[r][n] = p[r][n] - t_n * D[r][n] with

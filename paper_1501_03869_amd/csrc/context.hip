@@ -145,6 +145,49 @@ extern "C" int pat_tile_order(int nx, int ny, const int32_t *h_pix, int P, int t
     return PAT_OK;
 }
 
+// Morton index of local brick coordinates: interleaved bits of i, j and l.
+static uint64_t morton3(uint32_t i, uint32_t j, uint32_t l) {
+    uint64_t r = 0;
+    for (int b = 0; b < 10; ++b) {
+        r |= (uint64_t)((i >> b) & 1u) << (3 * b);
+        r |= (uint64_t)((j >> b) & 1u) << (3 * b + 1);
+        r |= (uint64_t)((l >> b) & 1u) << (3 * b + 2);
+    }
+    return r;
+}
+
+extern "C" int pat_tile_order_3d(int nx, int ny, int nz, const int32_t *h_vox, int P, int tile_w, int tile_h,
+                                 int tile_d, int32_t *h_vox_out) {
+    if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz > (1LL << 31) - 1 || P < 0 || tile_w < 1 ||
+        tile_h < 1 || tile_d < 1 || tile_w > 1024 || tile_h > 1024 || tile_d > 1024)
+        return pat_fail(PAT_EINVAL, "bad sizes %dx%dx%d P=%d tile=%dx%dx%d", nx, ny, nz, P, tile_w, tile_h, tile_d);
+    if (P > 0 && (!h_vox || !h_vox_out)) return pat_fail(PAT_EINVAL, "null voxel array");
+    if (P > 0 && h_vox == h_vox_out) return pat_fail(PAT_EINVAL, "h_vox_out aliases h_vox");
+    const long n = (long)nx * ny * nz;
+    const int tx = (nx + tile_w - 1) / tile_w, ty = (ny + tile_h - 1) / tile_h;
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)P);
+    for (int p = 0; p < P; ++p) {
+        const int32_t k = h_vox[p];
+        if (k < 0 || k >= n) return pat_fail(PAT_EINVAL, "voxel %d index %d out of range", p, k);
+        const int i = (int)(k % nx), j = (int)((k / nx) % ny), l = (int)(k / ((long)nx * ny));
+        // tiles snake through each layer (rows alternate direction, and so do
+        // layers), so that consecutive tiles are always neighbours
+        const int tl = l / tile_d;
+        int tr = j / tile_h;
+        if (tl & 1) tr = ty - 1 - tr;
+        const int tc = (tr & 1) ? tx - 1 - i / tile_w : i / tile_w;
+        const uint64_t tile = ((uint64_t)tl * ty + tr) * tx + tc;
+        key[(size_t)p] = { (tile << 30) | morton3((uint32_t)(i % tile_w), (uint32_t)(j % tile_h),
+                                                  (uint32_t)(l % tile_d)), k };
+    }
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<uint64_t, int32_t> &a, const std::pair<uint64_t, int32_t> &b) {
+                         return a.first < b.first;
+                     });
+    for (int p = 0; p < P; ++p) h_vox_out[p] = key[(size_t)p].second;
+    return PAT_OK;
+}
+
 static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 extern "C" int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, double dt, float *d_b,

@@ -228,7 +228,8 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
     if (S < 0 || P < 0) return pat_fail(PAT_EINVAL, "negative sensor or pixel count");
     if (!d_speed) return pat_fail(PAT_EINVAL, "null speed map");
     if (S > 0 && !h_sensor_xy) return pat_fail(PAT_EINVAL, "null sensor positions");
-    if (P > 0 && (!d_pix || !d_table)) return pat_fail(PAT_EINVAL, "null pixel list or table");
+    if (P > 0 && !d_pix) return pat_fail(PAT_EINVAL, "null pixel list");
+    if ((long long)S * P > 0 && !d_table) return pat_fail(PAT_EINVAL, "null table");
     ctx->last_eik = pat_eikonal_stats{};
     const long n = (long)nx * ny;
 

@@ -230,15 +230,17 @@ def segment_phantom(seed: int, nx: int, ny: int, h: float, count=40, r_max=15.5e
 # ----------------------------------------------------------------------------- signals
 
 def npulse_signals(src_delay: np.ndarray, src_amp: np.ndarray, src_dist: np.ndarray,
-                   n_samples: int, dt: float, t0: float = 0.0, sigma: float = PULSE_SIGMA) -> np.ndarray:
+                   n_samples: int, dt: float, t0: float = 0.0, sigma: float = PULSE_SIGMA,
+                   spreading: float = 0.5) -> np.ndarray:
     """Sum of Gaussian-derivative N-pulses, one per (sensor, source).
 
     src_delay[S][K]: arrival time of source k at sensor s (seconds, supplied by
     the caller); src_amp[K]; src_dist[S][K]: source-sensor distance in metres
-    (for the 1/sqrt(r[mm]) cylindrical spreading).  Pulse:
-    A r^-1/2 (-tau/sigma) exp(1/2 - tau^2/(2 sigma^2)), tau = t - delay, whose
-    peak magnitude is A/sqrt(r).  Only +-5 sigma around each arrival is
-    evaluated.  Returns float32 [S][n_samples]."""
+    (for the r[mm]^-spreading amplitude decay: 1/2 cylindrical in 2-D, 1
+    spherical in 3-D).  Pulse: A r^-spreading (-tau/sigma) exp(1/2 -
+    tau^2/(2 sigma^2)), tau = t - delay, whose peak magnitude is
+    A r^-spreading.  Only +-5 sigma around each arrival is evaluated.
+    Returns float32 [S][n_samples]."""
     S, K = src_delay.shape
     out = np.zeros((S, n_samples), dtype=np.float64)
     half = int(math.ceil(5.0 * sigma / dt)) + 1
@@ -249,7 +251,7 @@ def npulse_signals(src_delay: np.ndarray, src_amp: np.ndarray, src_dist: np.ndar
         if not ok.any():
             continue
         d = d[ok]
-        a = src_amp[ok] / np.sqrt(src_dist[s][ok] * 1e3)
+        a = src_amp[ok] * (src_dist[s][ok] * 1e3) ** -spreading
         n0 = np.floor((d - t0) / dt).astype(np.int64)
         idx = n0[:, None] + offs[None, :]
         tau = (t0 + idx * dt) - d[:, None]
@@ -426,3 +428,15 @@ def source_distances3(geo: Geometry3, src_nodes: np.ndarray) -> np.ndarray:
     l = src_nodes // (geo.nx * geo.ny)
     d = np.stack([x[i], y[j], z[l]], axis=1)  # [K][3]
     return np.linalg.norm(d[None, :, :] - geo.sensors[:, None, :], axis=2)
+
+
+def frame_for3(geo: Geometry3, table: np.ndarray, frame: int = 0, count: int = 8) -> np.ndarray:
+    """One synthetic 3-D frame p[S][N]: count point absorbers at random ROI
+    voxels (amplitudes U[0.5, 1]), N-pulses with spherical (1/r) spreading,
+    arrival times from the table's columns."""
+    rng = np.random.Generator(np.random.PCG64(SEED_PHANTOM + 100 + frame))
+    c = rng.choice(geo.P, size=min(count, geo.P), replace=False)
+    amp = 0.5 + 0.5 * rng.random(c.size)
+    nodes = geo.pix[c].astype(np.int64)
+    delay = np.asarray(table, dtype=np.float64)[:, c]
+    return npulse_signals(delay, amp, source_distances3(geo, nodes), geo.n_samples, geo.dt, geo.t0, spreading=1.0)

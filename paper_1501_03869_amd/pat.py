@@ -22,8 +22,8 @@ SIG_F32, SIG_F16 = 0, 1
 
 EXPORTED = [
     "pat_last_error", "pat_version", "pat_ctx_create", "pat_ctx_destroy", "pat_ctx_reserve",
-    "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_last_stats", "pat_table_to_q16",
-    "pat_tile_order", "pat_filter", "pat_backproject", "pat_backproject_const",
+    "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_3d", "pat_eikonal_last_stats", "pat_table_to_q16",
+    "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_const",
     "pat_server_create", "pat_server_destroy", "pat_server_add_map", "pat_server_map_state",
     "pat_server_remove_map", "pat_server_submit", "pat_server_wait", "pat_server_get_stats",
     "pat_server_reset_stats",
@@ -78,9 +78,11 @@ def lib() -> C.CDLL:
         L.pat_backproject_scratch_bytes.argtypes = [i32, i32, i32]
         L.pat_backproject_scratch_bytes.restype = sz
         L.pat_eikonal_tables.argtypes = [vp, vp, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
+        L.pat_eikonal_tables_3d.argtypes = [vp, vp, i32, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
         L.pat_eikonal_last_stats.argtypes = [vp, C.POINTER(EikonalStats)]
         L.pat_table_to_q16.argtypes = [vp, vp, i64, dbl, dbl, i32, vp, vp]
         L.pat_tile_order.argtypes = [i32, i32, vp, i32, i32, i32, vp]
+        L.pat_tile_order_3d.argtypes = [i32, i32, i32, vp, i32, i32, i32, i32, vp]
         L.pat_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp]
         L.pat_backproject.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp, i32, i32, i32, i32, dbl, dbl, vp, vp]
         L.pat_backproject_const.argtypes = [vp, i32, i32, dbl, dbl, vp, i32, vp, i32, vp, i32, i32, vp, vp, i32, i32,
@@ -159,12 +161,31 @@ class Context:
         _need(pix, torch.int32, "pix")
         ny, nx = speed.shape
         sxy = np.ascontiguousarray(sensors, dtype=np.float64)
+        if sxy.ndim != 2 or sxy.shape[1] != 2:
+            raise ValueError("sensors must be [S][2]")
         S, P = sxy.shape[0], pix.shape[0]
         if table is None:
             table = torch.empty((S, P), dtype=torch.float32, device=speed.device)
         _need(table, torch.float32, "table")
         check(lib().pat_eikonal_tables(self.h, _ptr(speed), nx, ny, float(h), sxy.ctypes.data, S, _ptr(pix), P,
                                        _ptr(table), _stream(stream)))
+        return table
+
+    def eikonal_tables_3d(self, speed, h: float, sensors: np.ndarray, vox, table=None, stream=None):
+        """speed: float32 [nz][ny][nx] device; sensors: host float64 [S][3]; vox: int32 [P] device."""
+        import torch
+        _need(speed, torch.float32, "speed")
+        _need(vox, torch.int32, "vox")
+        nz, ny, nx = speed.shape
+        sxyz = np.ascontiguousarray(sensors, dtype=np.float64)
+        if sxyz.ndim != 2 or sxyz.shape[1] != 3:
+            raise ValueError("sensors must be [S][3]")
+        S, P = sxyz.shape[0], vox.shape[0]
+        if table is None:
+            table = torch.empty((S, P), dtype=torch.float32, device=speed.device)
+        _need(table, torch.float32, "table")
+        check(lib().pat_eikonal_tables_3d(self.h, _ptr(speed), nx, ny, nz, float(h), sxyz.ctypes.data, S, _ptr(vox),
+                                          P, _ptr(table), _stream(stream)))
         return table
 
     def eikonal_stats(self) -> dict:
@@ -248,6 +269,16 @@ def tile_order(nx: int, ny: int, pix: np.ndarray, tile_w: int = 16, tile_h: int 
     src = np.ascontiguousarray(pix, dtype=np.int32)
     out = np.empty_like(src)
     check(lib().pat_tile_order(nx, ny, src.ctypes.data, src.shape[0], tile_w, tile_h, out.ctypes.data))
+    return out
+
+
+def tile_order_3d(nx: int, ny: int, nz: int, vox: np.ndarray, tile_w: int = 4, tile_h: int = 4,
+                  tile_d: int = 2) -> np.ndarray:
+    """Host helper: ROI voxel indices in tile-major order (3-D)."""
+    src = np.ascontiguousarray(vox, dtype=np.int32)
+    out = np.empty_like(src)
+    check(lib().pat_tile_order_3d(nx, ny, nz, src.ctypes.data, src.shape[0], tile_w, tile_h, tile_d,
+                                  out.ctypes.data))
     return out
 
 

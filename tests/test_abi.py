@@ -80,6 +80,33 @@ def test_tile_order_host_helper():
         pat.tile_order(nx, ny, np.array([nx * ny], np.int32), 8, 4)
 
 
+def test_tile_order_3d_host_helper():
+    nx, ny, nz = 13, 11, 9
+    rng = np.random.default_rng(1)
+    vox = rng.permutation(nx * ny * nz)[:700].astype(np.int32)
+    out = pat.tile_order_3d(nx, ny, nz, vox, 4, 4, 2)
+    assert sorted(out.tolist()) == sorted(vox.tolist())
+    # every full 4x4x2 tile is one aligned run of 32 compact voxels
+    n = 16
+    o = pat.tile_order_3d(n, n, n, np.arange(n ** 3, dtype=np.int32), 4, 4, 2)
+    for r in range(0, n ** 3, 32):
+        blk = o[r:r + 32]
+        i, j, l = blk % n, (blk // n) % n, blk // (n * n)
+        assert np.ptp(i) == 3 and np.ptp(j) == 3 and np.ptp(l) == 1
+    # consecutive tiles are neighbours: along the order, tile coordinates never jump
+    ti, tj, tl = (o % n) // 4, ((o // n) % n) // 4, (o // (n * n)) // 2
+    step = np.abs(np.diff(ti)) + np.abs(np.diff(tj)) + np.abs(np.diff(tl))
+    assert step.max() <= 1
+    # inside a tile: Morton order of the local coordinates
+    t0 = o[:32]
+    loc = [(int(a % n) % 4, int((a // n) % n) % 4, int(a // (n * n)) % 2) for a in t0]
+    mort = [sum((((x >> b) & 1) << (3 * b)) | (((y >> b) & 1) << (3 * b + 1)) | (((z >> b) & 1) << (3 * b + 2))
+                for b in range(3)) for x, y, z in loc]
+    assert mort == sorted(mort)
+    with pytest.raises(pat.PatError):
+        pat.tile_order_3d(nx, ny, nz, np.array([nx * ny * nz], np.int32), 4, 4, 2)
+
+
 def test_scratch_size_is_host_only():
     assert pat.backproject_scratch_bytes(0, 10, 1) == 0
     # several sensor groups at this size: at least two partial images

@@ -1,0 +1,183 @@
+"""3-D delay tables (6-neighbour first-order Godunov, brick-parallel
+relaxation) against the 3-D fast-marching oracle, and a 3-D end-to-end
+reconstruction (GPU tables, GPU fused filter and gather) against the
+all-oracle pipeline.  The gather kernels are the 2-D ones with voxels as
+pixels, so only the tables are new here."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1501_03869_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+T_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1501_03869_amd import pat
+    c = pat.Context(0)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def max_rel(a, b):
+    # max relative error; where the reference is exactly zero (a sensor on a
+    # node) the value must be exactly zero too
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    z = b == 0
+    assert np.all(a[z] == 0)
+    return float((np.abs(a[~z] - b[~z]) / np.abs(b[~z])).max())
+
+
+def gpu_table3(ctx, speed, h, sensors, vox):
+    t = ctx.eikonal_tables_3d(dev(speed), h, sensors, dev(vox))
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def test_tiny3_full_map(ctx, orc):
+    geo = inputs.config3("tiny3")
+    print(f"[eik3] tiny3 S={geo.S} P={geo.P}", flush=True)
+    ref = orc.tables3(geo.speed, geo.h, geo.sensors, geo.pix)
+    got = gpu_table3(ctx, geo.speed, geo.h, geo.sensors, geo.pix)
+    st = ctx.eikonal_stats()
+    err = max_rel(got, ref)
+    print(f"[eik3] tiny3 max rel err {err:.3e} stats {st}", flush=True)
+    assert np.all(np.isfinite(got))
+    assert err <= T_TOL
+    assert st["guard_hits"] == 0
+
+
+def test_ragged_grid_and_corner_sensors(ctx, orc):
+    # sizes that are not brick multiples, strong random contrast, sensors on
+    # corners, edges and faces of the bounding box, scrambled voxel subset
+    rng = np.random.default_rng(31)
+    nx, ny, nz, h = 19, 13, 11, 0.4e-3
+    c = rng.uniform(1400, 3200, size=(nz, ny, nx)).astype(np.float32)
+    x, y, z = inputs.node_coords3(nx, ny, nz, h)
+    sens = np.array([[x[0], y[0], z[0]], [x[-1], y[-1], z[-1]], [x[-1], y[0], z[5]], [0.0, 0.0, 0.0],
+                     [x[3] + 0.37 * h, y[7] - 0.2 * h, z[-1]], [x[-1], 0.1 * h, -0.3 * h]])
+    vox = rng.permutation(nx * ny * nz)[: nx * ny * nz - 29].astype(np.int32)
+    print(f"[eik3] ragged {nx}x{ny}x{nz}", flush=True)
+    ref = orc.tables3(c, h, sens, vox)
+    got = gpu_table3(ctx, c, h, sens, vox)
+    err = max_rel(got, ref)
+    print(f"[eik3] ragged max rel err {err:.3e}", flush=True)
+    assert err <= T_TOL
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_single_layer_reduces_to_2d(ctx, orc, axis):
+    # one node thick along z (axis 0) or x (axis 2): the 3-D tables are the 2-D
+    # oracle's tables of the remaining plane
+    rng = np.random.default_rng(40 + axis)
+    a, b, h = 37, 29, 0.3e-3
+    c2 = rng.uniform(1400, 3000, size=(a, b)).astype(np.float32)
+    u, v = inputs.node_coords(b, a, h)
+    s2 = np.stack([rng.uniform(u[0], u[-1], 4), rng.uniform(v[0], v[-1], 4)], 1)
+    pix = rng.permutation(a * b)[:500].astype(np.int32)
+    ref = orc.tables(c2, h, s2, pix)
+    if axis == 0:
+        c3, s3 = c2[None], np.concatenate([s2, np.zeros((4, 1))], 1)
+    else:
+        # the plane's columns become y and its rows z; x is the singleton axis
+        c3, s3 = c2[:, :, None], np.concatenate([np.zeros((4, 1)), s2], 1)
+    print(f"[eik3] single layer axis {axis} shape {c3.shape}", flush=True)
+    got = gpu_table3(ctx, np.ascontiguousarray(c3), h, s3, pix)
+    assert max_rel(got, ref) <= T_TOL
+
+
+def test_random_small_volumes(ctx, orc):
+    # property sweep over small random volumes (including 2-node-thick slabs
+    # and sizes straddling brick edges) with random in-box sensors
+    rng = np.random.default_rng(2025)
+    for case in range(10):
+        nx, ny, nz = (int(v) for v in rng.integers(2, 20, size=3))
+        if case == 0:
+            nx, ny, nz = 2, 17, 9
+        if case == 1:
+            nx, ny, nz = 9, 9, 2
+        h = float(rng.uniform(0.05e-3, 0.5e-3))
+        c = rng.uniform(1000, 4000, size=(nz, ny, nx)).astype(np.float32)
+        x, y, z = inputs.node_coords3(nx, ny, nz, h)
+        S = int(rng.integers(1, 5))
+        sens = np.stack([rng.uniform(x[0], x[-1], S), rng.uniform(y[0], y[-1], S), rng.uniform(z[0], z[-1], S)], 1)
+        n = nx * ny * nz
+        vox = rng.permutation(n)[: int(rng.integers(1, n + 1))].astype(np.int32)
+        print(f"[eik3] random case {case} {nx}x{ny}x{nz} S={S}", flush=True)
+        ref = orc.tables3(c, h, sens, vox)
+        got = gpu_table3(ctx, c, h, sens, vox)
+        assert max_rel(got, ref) <= T_TOL, (case, nx, ny, nz)
+
+
+def test_head3_full_size_sampled(ctx, orc):
+    # the 64^3 head geometry with all 256 sensors; the oracle recomputes a
+    # sample of sensors one by one
+    geo = inputs.config3("head3")
+    print(f"[eik3] head3 S={geo.S} P={geo.P}", flush=True)
+    got = gpu_table3(ctx, geo.speed, geo.h, geo.sensors, geo.pix)
+    st = ctx.eikonal_stats()
+    print(f"[eik3] head3 stats {st}", flush=True)
+    assert st["guard_hits"] == 0
+    for s in (0, 97, 128, 255):
+        ref = orc.tables3(geo.speed, geo.h, geo.sensors[s:s + 1], geo.pix)[0]
+        err = max_rel(got[s], ref)
+        print(f"[eik3] head3 sensor {s} max rel err {err:.3e}", flush=True)
+        assert err <= T_TOL
+
+
+def test_head3_end_to_end(ctx, orc):
+    # 3-D reconstruction: GPU tables + fused filter/gather against the
+    # all-oracle pipeline on a reduced sensor set (spherical spreading)
+    geo = inputs.config3("head3")
+    sens = geo.sensors[::4]
+    rng = np.random.default_rng(inputs.SEED_PHANTOM + 3)
+    nodes = rng.choice(geo.pix, size=6, replace=False).astype(np.int64)
+    amp = rng.uniform(0.5, 1.0, size=6)
+    Tref = orc.tables3(geo.speed, geo.h, sens, geo.pix)
+    Tsrc = orc.tables3(geo.speed, geo.h, sens, nodes.astype(np.int32))
+    g = inputs.Geometry3(geo.name, geo.nx, geo.ny, geo.nz, geo.h, geo.speed, sens, geo.pix, geo.n_samples, geo.dt)
+    p = inputs.npulse_signals(Tsrc, amp, inputs.source_distances3(g, nodes), geo.n_samples, geo.dt, spreading=1.0)
+    Tg = ctx.eikonal_tables_3d(dev(geo.speed), geo.h, sens, dev(geo.pix))
+    got = ctx.backproject(Tg, dev(p), geo.dt, filtered=False).cpu().numpy()
+    ref = orc.backproject(Tref, p, geo.dt)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"[e2e3] head3 rel L2 {err:.3e}", flush=True)
+    assert err <= 2e-3
+    # the reconstruction peaks at the absorbers: every absorber voxel is a local
+    # maximum of |image| over its 6 neighbours inside the ROI
+    img = np.zeros(geo.nx * geo.ny * geo.nz)
+    img[geo.pix] = np.abs(ref)
+    strides = (1, geo.nx, geo.nx * geo.ny)
+    for k in nodes:
+        assert all(img[k] >= img[k + d] and img[k] >= img[k - d] for d in strides)
+
+
+def test_rejects_bad_input(ctx):
+    from paper_1501_03869_amd import pat
+    geo = inputs.config3("tiny3")
+    bad = geo.speed.copy()
+    bad[3, 2, 1] = 0.0
+    with pytest.raises(pat.PatError) as e:
+        ctx.eikonal_tables_3d(dev(bad), geo.h, geo.sensors, dev(geo.pix))
+    assert e.value.code == pat.PAT_EINVAL
+    with pytest.raises(pat.PatError):
+        ctx.eikonal_tables_3d(dev(geo.speed), geo.h, geo.sensors * 10, dev(geo.pix))
+    with pytest.raises(pat.PatError):
+        ctx.eikonal_tables_3d(dev(geo.speed), geo.h, geo.sensors, dev(np.array([geo.speed.size], np.int32)))
+    with pytest.raises(pat.PatError):
+        ctx.eikonal_tables_3d(dev(geo.speed[:1, :1, :1]), geo.h, np.zeros((1, 3)), dev(np.array([0], np.int32)))
+    with pytest.raises(ValueError):
+        ctx.eikonal_tables_3d(dev(geo.speed), geo.h, geo.sensors[:, :2], dev(geo.pix))
+    # S = 0 or P = 0: nothing to do, no error
+    t = ctx.eikonal_tables_3d(dev(geo.speed), geo.h, np.zeros((0, 3)), dev(geo.pix))
+    assert t.shape == (0, geo.P)
