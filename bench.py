@@ -53,7 +53,7 @@ TRAFFIC_SHA = "7aeaa9eddf56ac600813067e99c5297130f3658e7c2f97ed343d0925d911135b:
               "929644709dbf60bb072c43dfc23c2ee332cfcd7183960112783b1274ca458d26"
 FETCH_FACTOR = 250000.0 / 125012.36
 WRITE_FACTOR = 1.0
-TRAFFIC_KIB = {"paper": (25566.98, 83.38), "large": (1914208.27, 3311.77)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+TRAFFIC_KIB = {"paper": (25566.98, 83.38), "large": (1914208.27, 3311.77), "head3": (24928.29, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 
 
 def measured_traffic(config: str):
