@@ -34,6 +34,21 @@ struct DelayF32 {
         a = uc - (float)n;
         return ok;
     }
+    // Fast-path decoding for an integer range lo <= u < hi (lo >= 0): u is
+    // clamped to [lo, hi) (median of three against lo and the float just
+    // below hi), n = floor and a = fraction of the clamped value, so
+    // lo <= n <= hi-1 for every lane and n, a are exact where u lies in the
+    // range.  Returns whether it does (the clamp changed nothing; never for
+    // NaN or inf).
+    __device__ __forceinline__ bool decode_in(uint32_t bits, int lo, int hi, int &n, float &a) const {
+        const float T = __uint_as_float(bits);
+        const float u = fmaf(T, inv_hi, fmaf(T, inv_lo, off));
+        const float below_hi = __uint_as_float(__float_as_uint((float)hi) - 1u);
+        const float uc = __builtin_amdgcn_fmed3f(u, (float)lo, below_hi);
+        n = (int)uc;
+        a = uc - (float)n;
+        return uc == u;
+    }
     // Window-relative, branch-free decoding for an LDS window that starts at
     // sample an: idx = floor(u) - an and a = frac(u) with u' = u - an computed
     // directly (the anchor folds into the offset, so u' keeps more fraction
@@ -75,6 +90,12 @@ struct DelayQ16 {
         n = last ? N - 2 : n0;
         a = last ? 1.0f : (float)(q & 0xFFFFu) * (1.0f / 65536.0f);
         return ok;
+    }
+    __device__ __forceinline__ bool decode_in(uint32_t q, int lo, int hi, int &n, float &a) const {
+        const int n0 = (int)(q >> 16);  // the sentinel gives 65535 >= hi
+        n = min(max(n0, lo), hi - 1);
+        a = (float)(q & 0xFFFFu) * (1.0f / 65536.0f);
+        return (uint32_t)(n0 - lo) < (uint32_t)(hi - lo);
     }
     struct Win { int an; };
     __device__ __forceinline__ Win window(int an) const { return Win{ an }; }

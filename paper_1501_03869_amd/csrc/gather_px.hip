@@ -38,7 +38,10 @@ struct PxShape {
 int px_sps(int S, int W) {
     const int S1 = std::max(S, 1);
     W = std::max(1, std::min(W, (S1 + 1) / 2));
-    return (S1 + 2 * W - 1) / (2 * W);
+    const int sps = (S1 + 2 * W - 1) / (2 * W);
+    // whole pipeline steps: only a wave's last step can have empty slots,
+    // and only in the last wave
+    return (sps + PX_U - 1) / PX_U * PX_U;
 }
 
 // Waves per workgroup: as many as keep every workgroup of the launch resident
@@ -105,12 +108,13 @@ struct PxJob {
     float h, x0, y0, inv_c;
 };
 
-// One pipeline stage: the delays of U sensors of this lane's slot, decoded,
-// and their samples.
+// One pipeline stage: the delays of U sensors of this lane's slot as loaded
+// (d, overwritten by the loads two steps ahead) and as decoded for the sum
+// (raw bits e for the general path, interpolation weight a and filter factor
+// k for the fast path), and their samples.
 struct Stage {
-    uint32_t d[PX_U];
-    int n[PX_U];
-    float k[PX_U], a[PX_U], w[PX_U], q[PX_U][4];
+    uint32_t d[PX_U], e[PX_U];
+    float k[PX_U], a[PX_U], q[PX_U][4];
 };
 
 // The sensors of wave wv for pixel tile*32 + lane%32: the wave owns sensors
@@ -247,67 +251,98 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             for (int j = 0; j < PX_U; ++j) st.d[j] = __builtin_amdgcn_raw_buffer_load_b32(rt, toff, 2 * j * P * 4, 0);
         }
     };
-    // decode the delays of step i and issue its sample loads; returns whether
-    // a decodable delay of the step sits at an end of its record (n = 0 or
-    // N-2).  Whether a slot position holds a sensor at all is decided per
-    // half-wave with scalar arithmetic and folded into the weight.
+    // Decode the delays of step i and issue its sample loads.  Returns whether
+    // this lane needs the general path for the step: a slot of the step holds
+    // no sensor, or a delay lies outside the fast range, where the filter's
+    // taps p[n-1 .. n+2] (raw input) or the two samples b[n], b[n+1]
+    // (filtered input) are inside the record and the delay contributes.  The
+    // sample index is clamped into the fast range for every lane, which makes
+    // the first tap n-1 (or n) clipped to [0, N-4] (or [0, N-2]), the start
+    // the general path expects, so both paths read the same loads.
     const float t0h = 0.5f * t0dt;
+    constexpr int LO = FILTERED ? 0 : 1;
+    const int HI = FILTERED ? N - 1 : N - 2;
     auto samples = [&](int i, Stage &st) -> bool {
-        const int s0 = sw + 2 * i * PX_U;
         const SigRsrc g = sig_rsrc(step_s0(i));
-        bool end = false;
+        bool fast = sw + 2 * (i + 1) * PX_U <= se;
 #pragma unroll
         for (int j = 0; j < PX_U; ++j) {
-            int n = 1;
-            float a = 0.0f;
-            const bool dok = dec.decode_bf(st.d[j], N, n, a);
-            float ws0 = s0 + 2 * j < se ? 1.0f : 0.0f;
-            float ws1 = s0 + 2 * j + 1 < se ? 1.0f : 0.0f;
-            if constexpr (HAS_W) {
-                ws0 *= J.w[min(s0 + 2 * j, S - 1)];
-                ws1 *= J.w[min(s0 + 2 * j + 1, S - 1)];
-            }
-            st.w[j] = dok ? (half ? ws1 : ws0) : 0.0f;
-            st.a[j] = a;  // 0 when the delay does not contribute
-            st.n[j] = n;
+            int n;
+            float a;
+            fast &= dec.decode_in(st.d[j], LO, HI, n, a);
+            st.e[j] = st.d[j];
+            st.a[j] = a;
             st.k[j] = fmaf((float)n, 0.5f, t0h);  // (n + t0/dt) / 2
+            // lo <= n <= hi-1: the first tap n-1 (raw) or n (filtered) is the
+            // same clipped start the general path assumes
             if constexpr (FILTERED) {
-                load2(g, j, min(max(n, 0), N - 2), st.q[j]);
+                load2(g, j, n, st.q[j]);
             } else {
-                end |= dok & ((n == 0) | (n == N - 2));
-                load4(g, j, min(max(n - 1, 0), N - 4), st.q[j]);
+                load4(g, j, n - 1, st.q[j]);
             }
         }
-        return end;
+        return !fast;
     };
     float acc = 0.0f;
-    auto sum = [&](const Stage &st, bool any_end) {
+    auto sum = [&](const Stage &st, int i, bool general) {
+        const int s0 = sw + 2 * i * PX_U;
+        if (!general) {
+            // every slot holds a sensor and every delay is in the fast range:
+            // q = p[n-1 .. n+2] and both samples take central differences,
+            // b[m] = p[m] - (m + t0/dt) * (p[m+1] - p[m-1]) / 2
+#pragma unroll
+            for (int j = 0; j < PX_U; ++j) {
+                float b0, b1;
+                if constexpr (FILTERED) {
+                    pair(st.q[j], b0, b1);
+                } else {
+                    float q[4];
+                    taps(st.q[j], q);
+                    b0 = fmaf(-st.k[j], q[2] - q[0], q[1]);
+                    b1 = fmaf(-(st.k[j] + 0.5f), q[3] - q[1], q[2]);
+                }
+                const float v = fmaf(st.a[j], b1 - b0, b0);
+                if constexpr (HAS_W) {
+                    acc = fmaf(half ? J.w[s0 + 2 * j + 1] : J.w[s0 + 2 * j], v, acc);
+                } else {
+                    acc += v;
+                }
+            }
+            return;
+        }
+        // general path: empty slots and non-contributing delays weigh 0; the
+        // filter is one-sided at both ends of the record
 #pragma unroll
         for (int j = 0; j < PX_U; ++j) {
+            int n = 0;
+            float a = 0.0f;
+            const bool dok = dec.decode_bf(st.e[j], N, n, a);  // 0 <= n <= N-2
+            const int sa = s0 + 2 * j, sb = sa + 1;
+            float w0 = sa < se ? 1.0f : 0.0f, w1 = sb < se ? 1.0f : 0.0f;
+            if constexpr (HAS_W) {
+                w0 *= J.w[min(sa, S - 1)];
+                w1 *= J.w[min(sb, S - 1)];
+            }
+            const float w = dok ? (half ? w1 : w0) : 0.0f;
             float b0, b1;
             if constexpr (FILTERED) {
                 pair(st.q[j], b0, b1);
             } else {
                 float q[4];
                 taps(st.q[j], q);
-                if (!any_end) {
-                    // every contributing lane has 1 <= n <= N-3, so q = p[n-1 .. n+2]
-                    // and both samples take central differences:
-                    // b[m] = p[m] - (m + t0/dt) * (p[m+1] - p[m-1]) / 2
-                    b0 = fmaf(-st.k[j], q[2] - q[0], q[1]);
-                    b1 = fmaf(-(st.k[j] + 0.5f), q[3] - q[1], q[2]);
-                } else {  // q = p[c .. c+3] with c = n-1 clipped to [0, N-4]
-                    const int n = min(max(st.n[j], 0), N - 2);
-                    const int sh = (n - 1) - min(max(n - 1, 0), N - 4);  // -1 at n = 0, +1 at n = N-2
-                    const float pm = sh == 1 ? q[1] : q[0];
-                    const float p0 = sh < 0 ? q[0] : (sh == 0 ? q[1] : q[2]);
-                    const float p1 = sh < 0 ? q[1] : (sh == 0 ? q[2] : q[3]);
-                    const float p2 = sh < 0 ? q[2] : q[3];
-                    b0 = ubp(pm, p0, p1, n, N, t0dt);
-                    b1 = ubp(p0, p1, p2, n + 1, N, t0dt);
-                }
+                // q = p[c .. c+3] with c = n-1 clipped to [0, N-4]
+                const int sh = (n - 1) - min(max(n - 1, 0), N - 4);  // -1 at n = 0, +1 at n = N-2
+                const float pm = sh == 1 ? q[1] : q[0];
+                const float p0 = sh < 0 ? q[0] : (sh == 0 ? q[1] : q[2]);
+                const float p1 = sh < 0 ? q[1] : (sh == 0 ? q[2] : q[3]);
+                const float p2 = sh < 0 ? q[2] : q[3];
+                const float k = fmaf((float)n, 0.5f, t0h);
+                const float d0 = n == 0 ? 2.0f * (p1 - p0) : p1 - pm;
+                const float d1 = n + 1 == N - 1 ? 2.0f * (p1 - p0) : p2 - p0;
+                b0 = fmaf(-k, d0, p0);
+                b1 = fmaf(-(k + 0.5f), d1, p1);
             }
-            acc = fmaf(st.w[j], fmaf(st.a[j], b1 - b0, b0), acc);
+            acc = fmaf(w, fmaf(a, b1 - b0, b0), acc);
         }
     };
 
@@ -320,20 +355,20 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     delays(0, A);
     delays(1, B);
     __builtin_amdgcn_sched_barrier(0);
-    bool endA = samples(0, A), endB = false;
+    bool genA = samples(0, A), genB = false;
     __builtin_amdgcn_sched_barrier(0);
     for (int i = 0; i < nstep; i += 2) {
         delays(i + 2, A);
         __builtin_amdgcn_sched_barrier(0);
-        endB = samples(i + 1, B);
+        genB = samples(i + 1, B);
         __builtin_amdgcn_sched_barrier(0);
-        sum(A, __any(endA));
+        sum(A, i, __any(genA));
         if (i + 1 >= nstep) break;
         delays(i + 3, B);
         __builtin_amdgcn_sched_barrier(0);
-        endA = samples(i + 2, A);
+        genA = samples(i + 2, A);
         __builtin_amdgcn_sched_barrier(0);
-        sum(B, __any(endB));
+        sum(B, i + 1, __any(genB));
     }
     return acc * sc;  // the FP16 frame scale (1 otherwise); filter and interpolation are linear
 }
