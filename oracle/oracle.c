@@ -26,6 +26,9 @@
  *      stored as a 16.16 fixed-point fractional sample index.
  *   6. orc_seed3 / orc_fmm3 / orc_tables3: steps 1-2 on a 3-D grid with the
  *      6-neighbour Godunov update (3-D reconstruction, Section IV).
+ *   7. orc_table_to_r16 / orc_r16_to_q16: the 16.16 table of item 5 stored as
+ *      16-bit offsets from a base per sensor and tile of 32 ROI positions
+ *      (a compressed storage form; not in the paper).
  *
  * Readings where the paper is silent (all FP64):
  *   - nodes carry the speed; missing neighbours beyond the grid edge are +inf;
@@ -588,6 +591,65 @@ void orc_gather_q16(const uint32_t *q, const double *b, const double *w, int S, 
             img[(long)f * P + p] = acc;
         }
     }
+}
+
+/* Tile-relative 16-bit delays.  The entries of sensor s are cut into tiles of
+ * 32 consecutive ROI positions (the last tile may be shorter).  A delay is
+ * valid when T is finite and u = (T - t0)/dt lies in [0, N-1].  For a tile with
+ * a valid delay: b = floor(smallest valid u), k = the largest integer in
+ * [0, 16] with (largest valid u - b) * 2^k <= 65534, every valid entry stores
+ * off = round-half-even((u - b) * 2^k) and every other one 0xFFFF, and the
+ * header is (b << 16) | (16 - k).  A tile without valid delays has header 0
+ * and only 0xFFFF entries.  off <= 65534 always, and the decoded value
+ * u' = b + off / 2^k satisfies |u' - u| <= 2^-(k+1) and u' <= N-1.
+ * off: [S][P] uint16; hdr: [S][ceil(P/32)] uint32. */
+void orc_table_to_r16(const float *T, int S, long P, double t0, double dt, int N, uint16_t *off, uint32_t *hdr) {
+    int old = fegetround();
+    fesetround(FE_TONEAREST);
+    long tiles = (P + 31) / 32;
+    for (int s = 0; s < S; ++s) {
+        for (long t = 0; t < tiles; ++t) {
+            long p0 = t * 32, p1 = p0 + 32 < P ? p0 + 32 : P;
+            double lo = INFINITY, hi = -INFINITY;
+            double u[32];
+            int ok[32];
+            for (long p = p0; p < p1; ++p) {
+                double tv = (double)T[(long)s * P + p];
+                double uu = (tv - t0) / dt;
+                int v = isfinite(tv) && uu >= 0.0 && uu <= (double)(N - 1);
+                u[p - p0] = uu;
+                ok[p - p0] = v;
+                if (v) {
+                    if (uu < lo) lo = uu;
+                    if (uu > hi) hi = uu;
+                }
+            }
+            if (!(lo <= hi)) {  /* no valid delay */
+                hdr[(long)s * tiles + t] = 0u;
+                for (long p = p0; p < p1; ++p) off[(long)s * P + p] = 0xFFFFu;
+                continue;
+            }
+            double b = floor(lo);
+            int k = 16;
+            while (k > 0 && ldexp(hi - b, k) > 65534.0) --k;
+            hdr[(long)s * tiles + t] = ((uint32_t)b << 16) | (uint32_t)(16 - k);
+            for (long p = p0; p < p1; ++p)
+                off[(long)s * P + p] = ok[p - p0] ? (uint16_t)nearbyint(ldexp(u[p - p0] - b, k)) : (uint16_t)0xFFFFu;
+        }
+    }
+    fesetround(old);
+}
+
+/* The 16.16 value of every entry: (b << 16) + (off << (16 - k)), or the
+ * 16.16 sentinel 0xFFFFFFFF for off = 0xFFFF. */
+void orc_r16_to_q16(const uint16_t *off, const uint32_t *hdr, int S, long P, uint32_t *q) {
+    long tiles = (P + 31) / 32;
+    for (int s = 0; s < S; ++s)
+        for (long p = 0; p < P; ++p) {
+            uint16_t o = off[(long)s * P + p];
+            uint32_t h = hdr[(long)s * tiles + p / 32];
+            q[(long)s * P + p] = o == 0xFFFFu ? 0xFFFFFFFFu : (h & 0xFFFF0000u) + ((uint32_t)o << (h & 31u));
+        }
 }
 
 int orc_max_threads(void) {

@@ -26,6 +26,7 @@ _fp = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
 _u8 = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
 _i32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _u32 = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_u16 = np.ctypeslib.ndpointer(dtype=np.uint16, flags="C_CONTIGUOUS")
 
 
 def build(force: bool = True) -> str:
@@ -61,6 +62,10 @@ def lib():
         L.orc_table_to_q16.restype = None
         L.orc_gather_q16.argtypes = [_u32, _dp, C.c_void_p, C.c_int, C.c_long, C.c_int, C.c_int, _dp, C.c_int]
         L.orc_gather_q16.restype = None
+        L.orc_table_to_r16.argtypes = [_fp, C.c_int, C.c_long, C.c_double, C.c_double, C.c_int, _u16, _u32]
+        L.orc_table_to_r16.restype = None
+        L.orc_r16_to_q16.argtypes = [_u16, _u32, C.c_int, C.c_long, _u32]
+        L.orc_r16_to_q16.restype = None
         L.orc_fmm3.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, _dp, _u8, _dp, C.POINTER(C.c_long)]
         L.orc_fmm3.restype = C.c_int
         L.orc_seed3.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, _dp, C.c_double, C.c_double, C.c_double,
@@ -177,6 +182,28 @@ def table_to_q16(T: np.ndarray, dt: float, N: int, t0: float = 0.0) -> np.ndarra
     T = np.ascontiguousarray(T, dtype=np.float32)
     q = np.empty(T.shape, dtype=np.uint32)
     lib().orc_table_to_q16(T, T.size, float(t0), float(dt), int(N), q)
+    return q
+
+
+def table_to_r16(T: np.ndarray, dt: float, N: int, t0: float = 0.0):
+    """Tile-relative 16-bit form of a float32 delay table: (off uint16 [S][P],
+    hdr uint32 [S][ceil(P/32)])."""
+    T = np.ascontiguousarray(T, dtype=np.float32)
+    S, P = T.shape
+    off = np.empty((S, P), dtype=np.uint16)
+    hdr = np.empty((S, (P + 31) // 32), dtype=np.uint32)
+    lib().orc_table_to_r16(T, S, P, float(t0), float(dt), int(N), off, hdr)
+    return off, hdr
+
+
+def r16_to_q16(off: np.ndarray, hdr: np.ndarray) -> np.ndarray:
+    """The 16.16 table a tile-relative 16-bit table stands for."""
+    off = np.ascontiguousarray(off, dtype=np.uint16)
+    hdr = np.ascontiguousarray(hdr, dtype=np.uint32)
+    S, P = off.shape
+    assert hdr.shape == (S, (P + 31) // 32)
+    q = np.empty((S, P), dtype=np.uint32)
+    lib().orc_r16_to_q16(off, hdr, S, P, q)
     return q
 
 
