@@ -116,10 +116,13 @@ def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
                      "timing_note": "eager single-frame launches (wall time); device_ms_*: HIP events around each",
                      "device_ms_p50": percentile(ms, 50), "device_ms_p99": percentile(ms, 99)}
 
+    r16 = ctx.table_to_r16(table, geo.dt, N, geo.t0)
     single("v0_f32_table_f32_signal", table, frames, None)
     single("v1_q16_table_f32_signal", q16, frames, None)
     single("v2_f32_table_f16_signal", table, half, scale_d)
     single("v3_q16_table_f16_signal", q16, half, scale_d)
+    single("v4_r16_table_f16_signal", r16, half, scale_d)
+    single("v4a_r16_table_f32_signal", r16, frames, None)
 
     # batched: F frames per launch, table read once; replayed from a HIP graph
     F = 64
@@ -127,7 +130,8 @@ def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
     sigs = {"f32": frames[torch.from_numpy(idx).to(dev)].contiguous(), "f16": half[torch.from_numpy(idx).to(dev)].contiguous()}
     scl = scale_d[torch.from_numpy(idx).to(dev)].contiguous()
     outF = torch.empty((F, P), dtype=torch.float32, device=dev)
-    for name, tab, sk in (("batch64_v0_f32", table, "f32"), ("batch64_v3_q16_f16", q16, "f16")):
+    for name, tab, sk in (("batch64_v0_f32", table, "f32"), ("batch64_v3_q16_f16", q16, "f16"),
+                          ("batch64_v4_r16_f16", r16, "f16")):
         sig = sigs[sk]
         sc = scl if sk == "f16" else None
         ctx.reserve(S, P, F)

@@ -58,8 +58,11 @@ typedef enum pat_status {
 /* Delay-table formats accepted by pat_backproject. */
 enum {
     PAT_TABLE_F32 = 0,   /* float32 seconds; non-finite = no contribution */
-    PAT_TABLE_Q16 = 1    /* uint32 16.16 fractional sample index,
+    PAT_TABLE_Q16 = 1,   /* uint32 16.16 fractional sample index,
                             0xFFFFFFFF = no contribution */
+    PAT_TABLE_R16 = 2    /* 16-bit offsets from a base per sensor and 32-entry
+                            tile (pat_table_to_r16): a 16.16 table in about
+                            half the bytes */
 };
 
 /* Signal formats accepted by pat_backproject. */
@@ -170,6 +173,33 @@ int pat_table_to_q16(pat_ctx *ctx, const float *d_table, int64_t n, double t0, d
                      uint32_t *d_q, void *stream);
 
 /*
+ * Delay table -> tile-relative 16-bit form (PAT_TABLE_R16), a compressed
+ * 16.16 table for the gather's bandwidth-bound shapes and for resident
+ * tables (not in the paper).  The entries of sensor s are cut into tiles of
+ * 32 consecutive ROI positions (the last one may be shorter).  With
+ * u = (T - t0)/dt in FP64, a delay is valid when T is finite and
+ * 0 <= u <= N-1.  For a tile with a valid delay, b = floor(smallest valid u)
+ * and k = the largest integer in [0, 16] with (largest valid u - b) * 2^k <=
+ * 65534; each valid entry stores off = round-half-even((u - b) * 2^k), each
+ * other one 0xFFFF, and the tile's header is (b << 16) | (16 - k).  A tile
+ * without valid delays has header 0.  The entry stands for the 16.16 value
+ * (b << 16) + (off << (16 - k)), i.e. u' = b + off / 2^k with
+ * |u' - u| <= 2^-(k+1) and u' <= N-1; keeping tiles compact (pat_tile_order)
+ * keeps k large (11 for compact blocks of the paper geometry, 8 where a run
+ * of 32 ROI entries skips nodes outside the ROI).
+ *
+ *   d_table   float32 [S][P] seconds.  2 <= N <= 65535.
+ *   d_out     pat_table_r16_bytes(S, P) bytes: uint16 offsets [S][P] at byte
+ *             0, then uint32 headers [S][ceil(P/32)] at byte
+ *             2*S*P rounded up to a multiple of 256.
+ * Stream-ordered; PAT_EINVAL for bad sizes or parameters.
+ */
+int pat_table_to_r16(pat_ctx *ctx, const float *d_table, int S, int P, double t0, double dt, int N,
+                     void *d_out, void *stream);
+/* Bytes of a PAT_TABLE_R16 table of S sensors and P ROI positions.  Host only. */
+size_t pat_table_r16_bytes(int S, int P);
+
+/*
  * Host helper: reorder ROI node indices tile-major (tiles of tile_w x tile_h
  * nodes; tile rows alternately left to right and right to left, so that
  * consecutive tiles are neighbours; Z-order (Morton) inside a tile), so that every
@@ -206,8 +236,9 @@ int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, doubl
  * with linear interpolation between samples floor(u) and floor(u)+1 (the last
  * interval at u = N-1); delays with u < 0, u > N-1 or non-finite contribute 0.
  *
- *   d_table   [S][P], format table_fmt (PAT_TABLE_F32 seconds or
- *             PAT_TABLE_Q16 from pat_table_to_q16 with the same t0, dt, N).
+ *   d_table   [S][P], format table_fmt (PAT_TABLE_F32 seconds,
+ *             PAT_TABLE_Q16 from pat_table_to_q16 or PAT_TABLE_R16 from
+ *             pat_table_to_r16, both with the same t0, dt, N).
  *   d_sig     [F][S][N] signals, format sig_fmt.  If sig_is_filtered is 0 the
  *             signals are raw pressures p and the filter above is applied
  *             inside the kernel; otherwise they are already b.
@@ -225,7 +256,8 @@ int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, doubl
  * are split inside one workgroup (no scratch) for several frames or for a
  * frame too small to fill the GPU otherwise; the remaining shapes use
  * LDS-windowed workgroups over sensor groups, which add their partial sums
- * in scratch.
+ * in scratch.  PAT_TABLE_R16 tables always take the split-sensor kernel and
+ * need N >= 4 and an aligned d_sig (else PAT_EINVAL).
  */
 int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
@@ -261,7 +293,8 @@ typedef struct pat_server pat_server;
 typedef struct pat_server_config {
     size_t hbm_budget_bytes;  /* device bytes for tables, frames and build working
                                  memory; 0 = 80% of the free memory at creation */
-    int table_fmt;            /* PAT_TABLE_F32 or PAT_TABLE_Q16, all maps */
+    int table_fmt;            /* PAT_TABLE_F32, PAT_TABLE_Q16 or PAT_TABLE_R16, all maps
+                                 (R16: pass the ROI in pat_tile_order order) */
     int sig_fmt;              /* PAT_SIG_F32 or PAT_SIG_F16, all frames (raw p) */
     int max_batch;            /* frames per launch (0 = 64) */
     int max_inflight;         /* batches on the device at once (0 = 2, <= 8) */

@@ -214,6 +214,23 @@ extern "C" int pat_table_to_q16(pat_ctx *ctx, const float *d_table, int64_t n, d
     return pat_launch_table_to_q16(d_table, n, t0, dt, N, d_q, (hipStream_t)stream);
 }
 
+extern "C" size_t pat_table_r16_bytes(int S, int P) {
+    if (S <= 0 || P <= 0) return 0;
+    return pat_r16_bytes(S, P);
+}
+
+extern "C" int pat_table_to_r16(pat_ctx *ctx, const float *d_table, int S, int P, double t0, double dt, int N,
+                                void *d_out, void *stream) {
+    int rc = pat_make_current(ctx);
+    if (rc) return rc;
+    if (S < 0 || P < 0) return pat_fail(PAT_EINVAL, "negative size (S=%d P=%d)", S, P);
+    if (N < 2 || N > 65535) return pat_fail(PAT_EINVAL, "16-bit tables need 2 <= N <= 65535 (N=%d)", N);
+    if (!finite_pos(dt) || !std::isfinite(t0)) return pat_fail(PAT_EINVAL, "need finite t0 and dt > 0");
+    if (S == 0 || P == 0) return PAT_OK;
+    if (!d_table || !d_out) return pat_fail(PAT_EINVAL, "null table pointer");
+    return pat_launch_table_to_r16(d_table, S, P, t0, dt, N, d_out, (hipStream_t)stream);
+}
+
 extern "C" int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
                                int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
                                int N, int F, double t0, double dt, float *d_img, void *stream) {
@@ -221,10 +238,10 @@ extern "C" int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt,
     if (rc) return rc;
     if (S < 0 || P < 0 || F < 0) return pat_fail(PAT_EINVAL, "negative size (S=%d P=%d F=%d)", S, P, F);
     if (N < 2) return pat_fail(PAT_EINVAL, "need N >= 2 samples (N=%d)", N);
-    if (table_fmt != PAT_TABLE_F32 && table_fmt != PAT_TABLE_Q16)
+    if (table_fmt != PAT_TABLE_F32 && table_fmt != PAT_TABLE_Q16 && table_fmt != PAT_TABLE_R16)
         return pat_fail(PAT_EINVAL, "unknown table format %d", table_fmt);
     if (sig_fmt != PAT_SIG_F32 && sig_fmt != PAT_SIG_F16) return pat_fail(PAT_EINVAL, "unknown signal format %d", sig_fmt);
-    if (table_fmt == PAT_TABLE_Q16 && N > 65535) return pat_fail(PAT_EINVAL, "16.16 tables need N <= 65535");
+    if (table_fmt != PAT_TABLE_F32 && N > 65535) return pat_fail(PAT_EINVAL, "16.16 and 16-bit tables need N <= 65535");
     if (!finite_pos(dt) || !std::isfinite(t0)) return pat_fail(PAT_EINVAL, "need finite t0 and dt > 0");
     if ((long long)S * N > INT32_MAX || (long long)S * P > ((long long)1 << 40))
         return pat_fail(PAT_EINVAL, "sizes too large");

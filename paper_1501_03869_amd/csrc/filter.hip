@@ -2,6 +2,8 @@
 // HBM-streaming kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "pat_internal.h"
 
 // b[n] = p[n] - t_n D[n], t_n = t0 + n dt, D the central difference inside and
@@ -48,5 +50,63 @@ int pat_launch_table_to_q16(const float *T, int64_t n, double t0, double dt, int
     const int64_t grid = (n + blk - 1) / blk;
     k_table_to_q16<<<dim3((unsigned)grid), dim3(blk), 0, st>>>(T, q, n, t0, dt, (double)(N - 1));
     PAT_HIP(hipGetLastError());
+    return PAT_OK;
+}
+
+// Tile-relative 16-bit delays: 32 lanes per (sensor, 32-entry tile).  The
+// tile's smallest and largest valid u come from a butterfly over the 32
+// lanes; then b = floor(smallest), k = the largest shift in [0, 16] with
+// (largest - b) * 2^k <= 65534, and each valid entry stores
+// round-half-even((u - b) * 2^k).  All in FP64 with exact steps (the
+// subtraction of b and the scaling by 2^k are exact), so the encoding is
+// bit for bit the definition's.
+__global__ void __launch_bounds__(256) k_table_to_r16(const float *__restrict__ T, uint16_t *__restrict__ off,
+                                                      uint32_t *__restrict__ hdr, int S, int P, int tiles,
+                                                      double t0, double dt, double umax) {
+    const long pair = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+    const int l = threadIdx.x & 31;
+    const bool live = pair < (long)S * tiles;
+    const int s = live ? (int)(pair / tiles) : 0, t = live ? (int)(pair % tiles) : 0;
+    const long p = (long)t * 32 + l;
+    const bool in = live && p < P;
+    double u = 0.0;
+    bool ok = false;
+    if (in) {
+        const double tv = (double)T[(long)s * P + p];
+        u = (tv - t0) / dt;
+        ok = isfinite(tv) && u >= 0.0 && u <= umax;
+    }
+    double lo = ok ? u : INFINITY, hi = ok ? u : -INFINITY;
+    for (int m = 16; m >= 1; m >>= 1) {  // every lane of the wave takes part
+        lo = fmin(lo, __shfl_xor(lo, m, 32));
+        hi = fmax(hi, __shfl_xor(hi, m, 32));
+    }
+    if (!in) return;
+    const long e = (long)s * P + p;
+    if (!(lo <= hi)) {
+        if (l == 0) hdr[(long)s * tiles + t] = 0u;
+        off[e] = 0xFFFFu;
+        return;
+    }
+    const double b = floor(lo);
+    int k = 16;
+    while (k > 0 && ldexp(hi - b, k) > 65534.0) --k;
+    if (l == 0) hdr[(long)s * tiles + t] = ((uint32_t)b << 16) | (uint32_t)(16 - k);
+    off[e] = ok ? (uint16_t)rint(ldexp(u - b, k)) : (uint16_t)0xFFFFu;
+}
+
+int pat_launch_table_to_r16(const float *T, int S, int P, double t0, double dt, int N, void *out, hipStream_t st) {
+    const int tiles = (P + 31) / 32;
+    uint16_t *off = static_cast<uint16_t *>(out);
+    uint32_t *hdr = reinterpret_cast<uint32_t *>(static_cast<char *>(out) + pat_r16_hdr_offset(S, P));
+    // sensors in chunks of fewer than 2^30 lanes, so the grid stays in range
+    const int chunk = (int)std::max<long>(1, std::min<long>(S, (1L << 30) / ((long)tiles * 32)));
+    for (int s0 = 0; s0 < S; s0 += chunk) {
+        const int n = std::min(chunk, S - s0);
+        const long lanes = (long)n * tiles * 32;
+        k_table_to_r16<<<dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st>>>(
+            T + (long)s0 * P, off + (long)s0 * P, hdr + (long)s0 * tiles, n, P, tiles, t0, dt, (double)(N - 1));
+        PAT_HIP(hipGetLastError());
+    }
     return PAT_OK;
 }

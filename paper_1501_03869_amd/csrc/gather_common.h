@@ -11,6 +11,7 @@
 namespace pat_gather {
 
 struct DelayF32 {
+    static constexpr bool kR16 = false;
     float inv_hi, inv_lo, off;  // u = T * (inv_hi + inv_lo) + off
     float umax;                 // N - 1
     __device__ __forceinline__ bool decode(float T, int N, int &n, float &a) const {
@@ -73,6 +74,7 @@ struct DelayF32 {
 };
 
 struct DelayQ16 {
+    static constexpr bool kR16 = false;
     __device__ __forceinline__ bool decode(uint32_t q, int N, int &n, float &a) const {
         if (q == 0xFFFFFFFFu) return false;
         n = (int)(q >> 16);
@@ -104,6 +106,17 @@ struct DelayQ16 {
         idx = ok ? (int)(q >> 16) - w.an : 0;
         a = ok ? (float)(q & 0xFFFFu) * (1.0f / 65536.0f) : 0.0f;
         return ok;
+    }
+};
+
+// Tile-relative 16-bit delays: an offset per entry and a header
+// (b << 16) | (16 - k) per sensor and 32-entry tile stand for the 16.16 value
+// (b << 16) + (off << (16 - k)); offset 0xFFFF is the sentinel.  Decoding
+// then proceeds as for 16.16 tables.
+struct DelayR16 : DelayQ16 {
+    static constexpr bool kR16 = true;
+    __device__ __forceinline__ static uint32_t to_q16(uint32_t off, uint32_t hdr) {
+        return off == 0xFFFFu ? 0xFFFFFFFFu : (hdr & 0xFFFF0000u) + (off << (hdr & 31u));
     }
 };
 

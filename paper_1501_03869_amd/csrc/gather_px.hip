@@ -113,7 +113,7 @@ struct PxJob {
 // (raw bits e for the general path, interpolation weight a and filter factor
 // k for the fast path), and their samples.
 struct Stage {
-    uint32_t d[PX_U], e[PX_U];
+    uint32_t d[PX_U], h[PX_U], e[PX_U];  // h: 16-bit tables' tile headers
     float k[PX_U], a[PX_U], q[PX_U][4];
 };
 
@@ -145,6 +145,14 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     auto tab_rsrc = [&](int s0) {
         return rsrc(J.tab + (size_t)s0 * P, (uint32_t)min(2 * PX_U, S - s0) * (uint32_t)P * 4u);
     };
+    // 16-bit tables: offsets [S][P] and tile headers [S][tiles] (one header
+    // per half-wave and sensor, read by all its lanes)
+    const int tiles = (P + PX_T - 1) / PX_T;
+    const uint16_t *off16 = reinterpret_cast<const uint16_t *>(J.tab);
+    const uint32_t *hdr32 =
+        reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(J.tab) + pat_r16_hdr_offset(S, P));
+    const uint32_t ooff = ((uint32_t)(half * P) + (uint32_t)pc) * 2u;
+    const uint32_t hoff = ((uint32_t)(half * tiles) + (uint32_t)tile) * 4u;
     struct SigRsrc {
         __amdgpu_buffer_rsrc_t r;
         uint32_t res;
@@ -245,6 +253,16 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
                 const float dx = pxx - sx, dy = pxy - sy;
                 st.d[j] = __float_as_uint(__builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy)) * J.inv_c);
             }
+        } else if constexpr (Delay::kR16) {
+            const int s0 = step_s0(i);
+            const uint32_t rows = (uint32_t)min(2 * PX_U, S - s0);
+            const __amdgpu_buffer_rsrc_t ro = rsrc(off16 + (size_t)s0 * P, rows * (uint32_t)P * 2u);
+            const __amdgpu_buffer_rsrc_t rh = rsrc(hdr32 + (size_t)s0 * tiles, rows * (uint32_t)tiles * 4u);
+#pragma unroll
+            for (int j = 0; j < PX_U; ++j) {
+                st.d[j] = __builtin_amdgcn_raw_buffer_load_b16(ro, ooff, 2 * j * P * 2, 0);
+                st.h[j] = __builtin_amdgcn_raw_buffer_load_b32(rh, hoff, 2 * j * tiles * 4, 0);
+            }
         } else {
             const __amdgpu_buffer_rsrc_t rt = tab_rsrc(step_s0(i));
 #pragma unroll
@@ -269,8 +287,10 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         for (int j = 0; j < PX_U; ++j) {
             int n;
             float a;
-            fast &= dec.decode_in(st.d[j], LO, HI, n, a);
-            st.e[j] = st.d[j];
+            uint32_t dq = st.d[j];
+            if constexpr (Delay::kR16) dq = DelayR16::to_q16(st.d[j], st.h[j]);
+            fast &= dec.decode_in(dq, LO, HI, n, a);
+            st.e[j] = dq;
             st.a[j] = a;
             st.k[j] = fmaf((float)n, 0.5f, t0h);  // (n + t0/dt) / 2
             // lo <= n <= hi-1: the first tap n-1 (raw) or n (filtered) is the
@@ -451,10 +471,14 @@ __global__ void __launch_bounds__(64 * PX_MULTI_WAVES) k_bp_px_multi(const pat_b
         dec.inv_hi = D.inv_hi; dec.inv_lo = D.inv_lo; dec.off = D.off; dec.umax = D.umax;
         if (D.w) px_block<DelayF32, SFMT, false, true>(J, dec, tile, wv, PX_MULTI_WAVES);
         else px_block<DelayF32, SFMT, false, false>(J, dec, tile, wv, PX_MULTI_WAVES);
-    } else {
+    } else if constexpr (TFMT == PAT_TABLE_Q16) {
         DelayQ16 dec;
         if (D.w) px_block<DelayQ16, SFMT, false, true>(J, dec, tile, wv, PX_MULTI_WAVES);
         else px_block<DelayQ16, SFMT, false, false>(J, dec, tile, wv, PX_MULTI_WAVES);
+    } else {
+        DelayR16 dec;
+        if (D.w) px_block<DelayR16, SFMT, false, true>(J, dec, tile, wv, PX_MULTI_WAVES);
+        else px_block<DelayR16, SFMT, false, false>(J, dec, tile, wv, PX_MULTI_WAVES);
     }
 }
 
@@ -557,6 +581,12 @@ int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig,
                    ? launch_px<DelayF32, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
                    : launch_px<DelayF32, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
     }
+    if (table_fmt == PAT_TABLE_R16) {
+        DelayR16 d;
+        return sig_fmt == PAT_SIG_F32
+                   ? launch_px<DelayR16, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
+                   : launch_px<DelayR16, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
+    }
     DelayQ16 d;
     return sig_fmt == PAT_SIG_F32
                ? launch_px<DelayQ16, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
@@ -591,9 +621,12 @@ int pat_launch_px_multi(const pat_bp_desc *d_descs, int nd, int total_blocks, in
     if (table_fmt == PAT_TABLE_F32) {
         if (sig_fmt == PAT_SIG_F32) k_bp_px_multi<PAT_TABLE_F32, PAT_SIG_F32><<<grid, block, 0, st>>>(d_descs, nd);
         else k_bp_px_multi<PAT_TABLE_F32, PAT_SIG_F16><<<grid, block, 0, st>>>(d_descs, nd);
-    } else {
+    } else if (table_fmt == PAT_TABLE_Q16) {
         if (sig_fmt == PAT_SIG_F32) k_bp_px_multi<PAT_TABLE_Q16, PAT_SIG_F32><<<grid, block, 0, st>>>(d_descs, nd);
         else k_bp_px_multi<PAT_TABLE_Q16, PAT_SIG_F16><<<grid, block, 0, st>>>(d_descs, nd);
+    } else {
+        if (sig_fmt == PAT_SIG_F32) k_bp_px_multi<PAT_TABLE_R16, PAT_SIG_F32><<<grid, block, 0, st>>>(d_descs, nd);
+        else k_bp_px_multi<PAT_TABLE_R16, PAT_SIG_F16><<<grid, block, 0, st>>>(d_descs, nd);
     }
     PAT_HIP(hipGetLastError());
     return PAT_OK;

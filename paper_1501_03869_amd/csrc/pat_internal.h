@@ -67,10 +67,16 @@ int pat_px_frame_shape(pat_bp_desc *d, int S, int P, int N, double t0, double dt
 int pat_launch_px_multi(const pat_bp_desc *d_descs, int nd, int total_blocks, int table_fmt, int sig_fmt,
                         hipStream_t st);
 
+// PAT_TABLE_R16 layout: uint16 offsets [S][P] at byte 0, uint32 headers
+// [S][ceil(P/32)] from this byte offset.
+__host__ __device__ inline size_t pat_r16_hdr_offset(long long S, long long P) { return ((size_t)(2 * S * P) + 255) & ~(size_t)255; }
+__host__ __device__ inline size_t pat_r16_bytes(long long S, long long P) { return pat_r16_hdr_offset(S, P) + (size_t)(4 * S * ((P + 31) / 32)); }
+
 // Launchers (stream-ordered; arguments validated by the callers).
 int pat_launch_filter(const float *p, long rows, int N, double t0, double dt, float *b, hipStream_t st);
 int pat_launch_table_to_q16(const float *T, int64_t n, double t0, double dt, int N, uint32_t *q,
                             hipStream_t st);
+int pat_launch_table_to_r16(const float *T, int S, int P, double t0, double dt, int N, void *out, hipStream_t st);
 // Gather scratch shared by the single-frame and batched kernels.
 size_t pat_gather_counter_bytes(int P, int F);
 // Tables up to this size are taken to stay cached between frames (half of

@@ -224,9 +224,13 @@ struct pat_server {
     }
     // bytes a build also allocates through the pool: speed map, pixels, table(s)
     size_t map_pool_bytes(const Map &m) const {
-        size_t b = (size_t)m.nx * m.ny * 4 + (size_t)m.P * 4 + (size_t)m.S * m.P * 4;
-        if (cfg.table_fmt == PAT_TABLE_Q16) b += (size_t)m.S * m.P * 4;
+        size_t b = (size_t)m.nx * m.ny * 4 + (size_t)m.P * 4 + table_bytes(m);
+        if (cfg.table_fmt != PAT_TABLE_F32) b += (size_t)m.S * m.P * 4;  // the float32 table it is made from
         return b;
+    }
+    // bytes of a map's resident table in the configured format
+    size_t table_bytes(const Map &m) const {
+        return cfg.table_fmt == PAT_TABLE_R16 ? pat_r16_bytes(m.S, m.P) : (size_t)m.S * m.P * 4;
     }
     // queue a (re)build of an evicted map if its memory can be found
     void ensure_building(Map *m) {
@@ -277,17 +281,19 @@ void pat_server::builder() {
         int rc = PAT_OK;
         const size_t n = (size_t)m->nx * m->ny;
         void *d_speed = nullptr, *d_pix = nullptr, *d_f32 = nullptr, *d_out = nullptr;
-        const size_t tb = (size_t)m->S * m->P * 4;
+        const size_t t32 = (size_t)m->S * m->P * 4;  // float32 table
+        const size_t tb = table_bytes(*m);           // resident table
+        const bool convert = cfg.table_fmt != PAT_TABLE_F32;
         {
             std::lock_guard<std::mutex> lk(mu);
             d_speed = dev_alloc(n * 4);
             d_pix = dev_alloc((size_t)m->P * 4);
             d_out = dev_alloc(tb);
-            if (cfg.table_fmt == PAT_TABLE_Q16) d_f32 = dev_alloc(tb);
-            if (!d_speed || !d_pix || !d_out || (cfg.table_fmt == PAT_TABLE_Q16 && !d_f32)) rc = PAT_ENOMEM;
+            if (convert) d_f32 = dev_alloc(t32);
+            if (!d_speed || !d_pix || !d_out || (convert && !d_f32)) rc = PAT_ENOMEM;
         }
         if (rc == PAT_OK) {
-            float *table32 = static_cast<float *>(cfg.table_fmt == PAT_TABLE_Q16 ? d_f32 : d_out);
+            float *table32 = static_cast<float *>(convert ? d_f32 : d_out);
             if (hipMemcpyAsync(d_speed, m->speed.data(), n * 4, hipMemcpyHostToDevice, build_stream) != hipSuccess ||
                 hipMemcpyAsync(d_pix, m->pix.data(), (size_t)m->P * 4, hipMemcpyHostToDevice, build_stream) != hipSuccess)
                 rc = PAT_EDEVICE;
@@ -297,6 +303,8 @@ void pat_server::builder() {
             if (rc == PAT_OK && cfg.table_fmt == PAT_TABLE_Q16)
                 rc = pat_table_to_q16(build_ctx, table32, (int64_t)m->S * m->P, m->t0, m->dt, m->N,
                                       static_cast<uint32_t *>(d_out), build_stream);
+            if (rc == PAT_OK && cfg.table_fmt == PAT_TABLE_R16)
+                rc = pat_table_to_r16(build_ctx, table32, m->S, m->P, m->t0, m->dt, m->N, d_out, build_stream);
             if (rc == PAT_OK && hipStreamSynchronize(build_stream) != hipSuccess) rc = PAT_EDEVICE;
         }
         size_t scratch = build_ctx->eik_tq.bytes + build_ctx->eik_f.bytes + build_ctx->eik_flags.bytes +
@@ -305,7 +313,7 @@ void pat_server::builder() {
             std::lock_guard<std::mutex> lk(mu);
             dev_free(d_speed, n * 4);
             dev_free(d_pix, (size_t)m->P * 4);
-            if (d_f32) dev_free(d_f32, tb);
+            if (d_f32) dev_free(d_f32, t32);
             // the builder's context keeps its working maps for the next build
             if (scratch > build_scratch) {
                 used += scratch - build_scratch;
@@ -518,7 +526,8 @@ extern "C" int pat_server_create(pat_ctx *ctx, const pat_server_config *cfg, pat
     *out = nullptr;
     pat_server_config c{};
     if (cfg) c = *cfg;
-    if (c.table_fmt != PAT_TABLE_F32 && c.table_fmt != PAT_TABLE_Q16) return pat_fail(PAT_EINVAL, "bad table format");
+    if (c.table_fmt != PAT_TABLE_F32 && c.table_fmt != PAT_TABLE_Q16 && c.table_fmt != PAT_TABLE_R16)
+        return pat_fail(PAT_EINVAL, "bad table format");
     if (c.sig_fmt != PAT_SIG_F32 && c.sig_fmt != PAT_SIG_F16) return pat_fail(PAT_EINVAL, "bad signal format");
     if (c.max_batch <= 0) c.max_batch = 64;
     if (c.max_inflight <= 0) c.max_inflight = 2;
@@ -619,7 +628,8 @@ extern "C" int pat_server_add_map(pat_server *s, const float *h_speed, int nx, i
     if (!pat_px_multi_eligible(s->cfg.sig_fmt, S, P, N))
         return pat_fail(PAT_EINVAL, "map too large for the frame server (S*P or S*N beyond 32-bit offsets)");
     if (!h_speed || !h_sensor_xy || !h_pix) return pat_fail(PAT_EINVAL, "null map data");
-    if (s->cfg.table_fmt == PAT_TABLE_Q16 && N > 65535) return pat_fail(PAT_EINVAL, "16.16 tables need N <= 65535");
+    if (s->cfg.table_fmt != PAT_TABLE_F32 && N > 65535)
+        return pat_fail(PAT_EINVAL, "16.16 and 16-bit tables need N <= 65535");
     const size_t n = (size_t)nx * ny;
     for (size_t k = 0; k < n; ++k)
         if (!(std::isfinite(h_speed[k]) && h_speed[k] > 0)) return pat_fail(PAT_EINVAL, "speed must be finite and > 0");

@@ -17,12 +17,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpat.so")
 
 PAT_OK, PAT_EINVAL, PAT_ENOMEM, PAT_EDEVICE, PAT_EBUSY, PAT_ENOTFOUND, PAT_ETIMEOUT, PAT_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
-TABLE_F32, TABLE_Q16 = 0, 1
+TABLE_F32, TABLE_Q16, TABLE_R16 = 0, 1, 2
 SIG_F32, SIG_F16 = 0, 1
 
 EXPORTED = [
     "pat_last_error", "pat_version", "pat_ctx_create", "pat_ctx_destroy", "pat_ctx_reserve",
-    "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_3d", "pat_eikonal_last_stats", "pat_table_to_q16",
+    "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_3d", "pat_eikonal_last_stats", "pat_table_to_q16", "pat_table_to_r16", "pat_table_r16_bytes",
     "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_const",
     "pat_server_create", "pat_server_destroy", "pat_server_add_map", "pat_server_map_state",
     "pat_server_remove_map", "pat_server_submit", "pat_server_wait", "pat_server_get_stats",
@@ -81,6 +81,9 @@ def lib() -> C.CDLL:
         L.pat_eikonal_tables_3d.argtypes = [vp, vp, i32, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
         L.pat_eikonal_last_stats.argtypes = [vp, C.POINTER(EikonalStats)]
         L.pat_table_to_q16.argtypes = [vp, vp, i64, dbl, dbl, i32, vp, vp]
+        L.pat_table_to_r16.argtypes = [vp, vp, i32, i32, dbl, dbl, i32, vp, vp]
+        L.pat_table_r16_bytes.argtypes = [i32, i32]
+        L.pat_table_r16_bytes.restype = sz
         L.pat_tile_order.argtypes = [i32, i32, vp, i32, i32, i32, vp]
         L.pat_tile_order_3d.argtypes = [i32, i32, i32, vp, i32, i32, i32, i32, vp]
         L.pat_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp]
@@ -203,6 +206,16 @@ class Context:
                                      _stream(stream)))
         return out
 
+    def table_to_r16(self, table, dt: float, N: int, t0: float = 0.0, stream=None) -> "R16Table":
+        """Tile-relative 16-bit form of a float32 [S][P] table (see pat_table_to_r16)."""
+        import torch
+        _need(table, torch.float32, "table")
+        S, P = table.shape
+        buf = torch.empty(int(lib().pat_table_r16_bytes(S, P)), dtype=torch.uint8, device=table.device)
+        check(lib().pat_table_to_r16(self.h, _ptr(table), S, P, float(t0), float(dt), int(N), _ptr(buf),
+                                     _stream(stream)))
+        return R16Table(buf, S, P)
+
     # ------------------------------------------------------------------ frames
     def filter(self, p, dt: float, t0: float = 0.0, out=None, stream=None):
         import torch
@@ -220,8 +233,12 @@ class Context:
         """table: [S][P] float32 seconds or int32 (16.16 bits); sig: [S][N] or [F][S][N] float32/float16."""
         import torch
         S, P = table.shape
-        tfmt = TABLE_Q16 if table.dtype == torch.int32 else TABLE_F32
-        _need(table, torch.int32 if tfmt == TABLE_Q16 else torch.float32, "table")
+        if isinstance(table, R16Table):
+            tfmt = TABLE_R16
+            _need(table.buf, torch.uint8, "table")
+        else:
+            tfmt = TABLE_Q16 if table.dtype == torch.int32 else TABLE_F32
+            _need(table, torch.int32 if tfmt == TABLE_Q16 else torch.float32, "table")
         single = sig.dim() == 2
         F = 1 if single else sig.shape[0]
         N = sig.shape[-1]
@@ -262,6 +279,38 @@ class Context:
                                           _ptr(pix), P, _ptr(sig), sfmt, 1 if filtered else 0, _ptr(frame_scale),
                                           _ptr(w), N, F, float(t0), float(dt), _ptr(out), _stream(stream)))
         return out
+
+
+class R16Table:
+    """A PAT_TABLE_R16 table: the device buffer and its S x P shape.  offsets()
+    and headers() view the two arrays the buffer holds."""
+
+    def __init__(self, buf, S: int, P: int):
+        self.buf, self.shape = buf, (int(S), int(P))
+
+    @property
+    def device(self):
+        return self.buf.device
+
+    def data_ptr(self) -> int:
+        return self.buf.data_ptr()
+
+    def is_contiguous(self) -> bool:
+        return True
+
+    def offsets(self):
+        S, P = self.shape
+        return self.buf[: 2 * S * P].view(_torch().int16).view(S, P)
+
+    def headers(self):
+        S, P = self.shape
+        off = (2 * S * P + 255) // 256 * 256
+        return self.buf[off: off + 4 * S * ((P + 31) // 32)].view(_torch().int32).view(S, (P + 31) // 32)
+
+
+def _torch():
+    import torch
+    return torch
 
 
 def tile_order(nx: int, ny: int, pix: np.ndarray, tile_w: int = 16, tile_h: int = 16) -> np.ndarray:

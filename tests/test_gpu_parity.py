@@ -236,7 +236,7 @@ def test_backproject_q16_matches_oracle(ctx, orc):
     q = ctx.table_to_q16(dev(T), dt, N)
     p = inputs.random_signals(9, S, N)
     got = ctx.backproject(q, dev(p), dt).cpu().numpy()
-    ref = orc.gather_q16(q.cpu().numpy().view(np.uint32), p)
+    ref = orc.gather_q16(orc.table_to_q16(T, dt, N), p)
     assert rel_l2(got, ref) <= 1e-5
 
 
@@ -313,7 +313,7 @@ def test_backproject_batched_matches_oracle(ctx, orc, F, sig, filtered, q16):
         got = got.cpu().numpy()
         b = vals if filtered else orc.filt(vals, geo.dt)
         if q16:
-            ref = orc.gather_q16(tab.cpu().numpy().view(np.uint32), b, w.astype(np.float64))
+            ref = orc.gather_q16(orc.table_to_q16(T, geo.dt, geo.n_samples), b, w.astype(np.float64))
         else:
             ref = orc.gather(T.astype(np.float64), b, geo.dt, 0.0, w.astype(np.float64))
         err = rel_l2(got, ref)
@@ -346,7 +346,7 @@ def test_backproject_batched_large_table(ctx, orc, F, sig, filtered, q16):
     got = got.cpu().numpy()
     b = vals if filtered else orc.filt(vals, dt)
     if q16:
-        ref = orc.gather_q16(tab.cpu().numpy().view(np.uint32), b, w.astype(np.float64))
+        ref = orc.gather_q16(orc.table_to_q16(T, dt, N), b, w.astype(np.float64))
     else:
         ref = orc.gather(T.astype(np.float64), b, dt, 0.0, w.astype(np.float64))
     err = rel_l2(got, ref)
@@ -402,7 +402,8 @@ def test_batched_v3_within_bound(ctx, orc):
     w = np.ones(geo.S)
     for f in (0, 7, 15):
         ref = orc.backproject(T32.astype(np.float64), p[f], geo.dt)
-        bound = _v3_error_bound(q.cpu().numpy().view(np.uint32), T32.astype(np.float64), p[f].astype(np.float64),
+        bound = _v3_error_bound(orc.table_to_q16(T32, geo.dt, geo.n_samples), T32.astype(np.float64),
+                                p[f].astype(np.float64),
                                 float(scale[f]), geo.dt, w)
         err = np.abs(got[f] - ref)
         print(f"[v3] frame {f}: rel L2 {rel_l2(got[f], ref):.3e}, bound rel L2 "
@@ -455,7 +456,7 @@ def test_q16_at_the_sample_limit(ctx, orc):
     assert got[0, 1] == (N - 1) << 16 and got[0, 3] == 0xFFFFFFFF
     b = np.random.default_rng(3).normal(size=(1, N)).astype(np.float32)
     img = ctx.backproject(dev(got.view(np.int32)), dev(b), dt).cpu().numpy()
-    ref = orc.gather_q16(got, b)
+    ref = orc.gather_q16(orc.table_to_q16(T, dt, N), b)
     np.testing.assert_allclose(img, ref, rtol=1e-6, atol=1e-6)
 
 
