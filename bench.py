@@ -49,11 +49,12 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 of the files below; any change makes the field null until the
 # counters are taken again.  Summaries: profiles/k_bp_px_*_hbm_counters.md.
 TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_common.h")
-TRAFFIC_SHA = "7aeaa9eddf56ac600813067e99c5297130f3658e7c2f97ed343d0925d911135b:" \
-              "929644709dbf60bb072c43dfc23c2ee332cfcd7183960112783b1274ca458d26"
-FETCH_FACTOR = 250000.0 / 125012.36
+TRAFFIC_SHA = "95087522a9f5ad778647d8288221cab345cdc3c54c34df3eb94a204f85858c40:" \
+              "b759672c62a06a02c3815c3b0e7c34da647c831a9640bff5695d9272284e1fed"
+FETCH_FACTOR = 250000.0 / 125012.32
 WRITE_FACTOR = 1.0
-TRAFFIC_KIB = {"paper": (25566.98, 83.38), "large": (1914208.27, 3311.77), "head3": (24928.29, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+TRAFFIC_KIB = {"paper": (25210.72, 83.51), "large": (1836692.48, 3286.97),
+               "head3": (24703.05, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 
 
 def measured_traffic(config: str):
