@@ -428,6 +428,20 @@ int launch(bool filtered, bool vec4, dim3 grid, const uint32_t *tab, const void 
     return PAT_OK;
 }
 
+// Zero an image with a kernel rather than a memset node, so that a call with
+// no sensors can be captured into a HIP graph like any other.
+__global__ void __launch_bounds__(256) k_zero(float *__restrict__ img, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) img[i] = 0.0f;
+}
+
+int launch_zero(float *img, long n, hipStream_t st) {
+    if (n <= 0) return PAT_OK;
+    const long blocks = std::min<long>((n + 255) / 256, 4096);
+    k_zero<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(img, n);
+    PAT_HIP(hipGetLastError());
+    return PAT_OK;
+}
+
 }  // namespace
 
 // Gather scratch: the partial sums live in the context's gather buffer; the
@@ -467,8 +481,7 @@ int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const
                            int sig_is_filtered, const float *frame_scale, const float *w, int S, int P, int N,
                            int F, double t0, double dt, float *img, hipStream_t st) {
     if (S == 0) {
-        PAT_HIP(hipMemsetAsync(img, 0, (size_t)P * F * sizeof(float), st));
-        return PAT_OK;
+        return launch_zero(img, (long)P * F, st);
     }
     // Kernel choice.  Several frames whose table stays in the 256 MB Infinity
     // Cache between frames are fastest with the split-sensor kernel, one
@@ -527,8 +540,7 @@ int pat_launch_backproject_const(pat_ctx *ctx, int nx, int ny, double h, double 
                                  const float *frame_scale, const float *w, int N, int F, double t0, double dt,
                                  float *img, hipStream_t st) {
     if (S == 0) {
-        PAT_HIP(hipMemsetAsync(img, 0, (size_t)P * F * sizeof(float), st));
-        return PAT_OK;
+        return launch_zero(img, (long)P * F, st);
     }
     const BpShape sh = bp_shape(S, P, F);
     if ((sh.groups > 1 || F >= 2) && pat_px_eligible(sig_fmt, S, P, N, F, sig))

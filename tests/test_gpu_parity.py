@@ -212,7 +212,8 @@ def test_backproject_split_sensor_edges(ctx, orc, sig, N, filtered, F):
 
 def test_backproject_empty_and_deterministic(ctx, orc):
     z = torch.zeros((0, 10), dtype=torch.float32, device="cuda")
-    img = ctx.backproject(z, torch.zeros((0, 8), device="cuda"), 1e-8)
+    out = torch.full((10,), float("nan"), device="cuda")
+    img = ctx.backproject(z, torch.zeros((0, 8), device="cuda"), 1e-8, out=out)
     assert torch.count_nonzero(img).item() == 0 and img.shape == (10,)
     T = dev(inputs.random_table(3, 96, 3001, 800, 4e-8))
     p = dev(inputs.random_signals(4, 96, 800))
@@ -562,3 +563,42 @@ def test_large_gather_full_size_sampled(ctx, orc):
     err = rel_l2(got[sample], ref)
     print(f"[gather] large full size, 3000 sampled pixels: rel L2 {err:.3e}", flush=True)
     assert err <= IMG_TOL
+
+
+def test_graph_replay_matches_eager(ctx, orc):
+    # single-frame launches (split-sensor kernel, FP32 and 16-bit tables) and a
+    # no-sensor call captured into one HIP graph; every replay, with eager work
+    # and synchronisations in between, must reproduce the eager images bit for
+    # bit (the split-sensor kernel's sum order is fixed)
+    from paper_1501_03869_amd import pat
+    geo = inputs.config("paper")
+    pix = pat.tile_order(geo.nx, geo.ny, geo.pix, 32, 32)
+    T = dev(orc.tables(geo.speed, geo.h, geo.sensors, pix).astype(np.float32))
+    r16 = ctx.table_to_r16(T, geo.dt, geo.n_samples)
+    p = dev(inputs.random_signals(61, geo.S, geo.n_samples))
+    z = torch.zeros((0, 7), dtype=torch.float32, device="cuda")
+    outs = [torch.empty(geo.P, device="cuda"), torch.empty(geo.P, device="cuda"),
+            torch.full((7,), float("nan"), device="cuda")]
+
+    def run(st=None):
+        ctx.backproject(T, p, geo.dt, filtered=False, out=outs[0], stream=st)
+        ctx.backproject(r16, p, geo.dt, filtered=False, out=outs[1], stream=st)
+        ctx.backproject(z, torch.zeros((0, 8), device="cuda"), geo.dt, out=outs[2], stream=st)
+
+    run()
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in outs]
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(g, stream=cap):
+        run(cap)
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float("nan"))
+        ctx.backproject(T, p, geo.dt, filtered=True, out=torch.empty(geo.P, device="cuda"))  # eager work between
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), rep
