@@ -35,6 +35,21 @@ struct DelayF32 {
         a = uc - (float)n;
         return ok;
     }
+    // The split-sensor kernel's decoding computes u with one FMA,
+    // u = T * (1/dt)_f32 - t0/dt: the dropped term T * inv_lo is at most
+    // u * 2^-25, about half an ulp of u, so u stays within about 1 ulp.
+    __device__ __forceinline__ float u1(float T) const { return fmaf(T, inv_hi, off); }
+    // The same decoding without branches (split-sensor kernel, general
+    // path): n and a are computed for every lane (from u clamped to 0 when
+    // the delay does not contribute).
+    __device__ __forceinline__ bool decode_bf1(uint32_t bits, int N, int &n, float &a) const {
+        const float u = u1(__uint_as_float(bits));
+        const bool ok = u >= 0.0f && u <= umax;  // also rejects NaN and inf
+        const float uc = ok ? u : 0.0f;
+        n = min((int)uc, N - 2);
+        a = uc - (float)n;
+        return ok;
+    }
     // Fast-path decoding for an integer range lo <= u < hi (lo >= 0): u is
     // clamped to [lo, hi) (median of three against lo and the float just
     // below hi), n = floor and a = fraction of the clamped value, so
@@ -42,8 +57,7 @@ struct DelayF32 {
     // range.  Returns whether it does (the clamp changed nothing; never for
     // NaN or inf).
     __device__ __forceinline__ bool decode_in(uint32_t bits, int lo, int hi, int &n, float &a) const {
-        const float T = __uint_as_float(bits);
-        const float u = fmaf(T, inv_hi, fmaf(T, inv_lo, off));
+        const float u = u1(__uint_as_float(bits));
         const float below_hi = __uint_as_float(__float_as_uint((float)hi) - 1u);
         const float uc = __builtin_amdgcn_fmed3f(u, (float)lo, below_hi);
         n = (int)uc;
@@ -92,6 +106,9 @@ struct DelayQ16 {
         n = last ? N - 2 : n0;
         a = last ? 1.0f : (float)(q & 0xFFFFu) * (1.0f / 65536.0f);
         return ok;
+    }
+    __device__ __forceinline__ bool decode_bf1(uint32_t q, int N, int &n, float &a) const {
+        return decode_bf(q, N, n, a);
     }
     __device__ __forceinline__ bool decode_in(uint32_t q, int lo, int hi, int &n, float &a) const {
         const int n0 = (int)(q >> 16);  // the sentinel gives 65535 >= hi

@@ -17,6 +17,7 @@
 // one or two vector instructions; the descriptor's range also bounds every
 // access.
 #include <mutex>
+#include <type_traits>
 
 #include "gather_common.h"
 #include "pat_internal.h"
@@ -270,7 +271,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         }
     };
     // Decode the delays of step i and issue its sample loads.  Returns whether
-    // this lane needs the general path for the step: a slot of the step holds
+    // a lane of the wave needs the general path for the step: a slot of the step holds
     // no sensor, or a delay lies outside the fast range, where the filter's
     // taps p[n-1 .. n+2] (raw input) or the two samples b[n], b[n+1]
     // (filtered input) are inside the record and the delay contributes.  The
@@ -280,16 +281,24 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     const float t0h = 0.5f * t0dt;
     constexpr int LO = FILTERED ? 0 : 1;
     const int HI = FILTERED ? N - 1 : N - 2;
+    // F32 decoding: the offset -t0/dt in a vector register, so the decode's
+    // FMA reads only one scalar operand
+    Delay dv = dec;
+    if constexpr (std::is_same<Delay, DelayF32>::value) {
+        float offv;
+        asm("v_mov_b32 %0, %1" : "=v"(offv) : "s"(dec.off));
+        dv.off = offv;
+    }
     auto samples = [&](int i, Stage &st) -> bool {
         const SigRsrc g = sig_rsrc(step_s0(i));
-        bool fast = sw + 2 * (i + 1) * PX_U <= se;
+        uint64_t slow = sw + 2 * (i + 1) * PX_U <= se ? 0ull : ~0ull;
 #pragma unroll
         for (int j = 0; j < PX_U; ++j) {
             int n;
             float a;
             uint32_t dq = st.d[j];
             if constexpr (Delay::kR16) dq = DelayR16::to_q16(st.d[j], st.h[j]);
-            fast &= dec.decode_in(dq, LO, HI, n, a);
+            slow |= __builtin_amdgcn_ballot_w64(!dv.decode_in(dq, LO, HI, n, a));
             st.e[j] = dq;
             st.a[j] = a;
             st.k[j] = fmaf((float)n, 0.5f, t0h);  // (n + t0/dt) / 2
@@ -301,7 +310,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
                 load4(g, j, n - 1, st.q[j]);
             }
         }
-        return !fast;
+        return slow != 0;  // wave-uniform
     };
     float acc = 0.0f;
     auto sum = [&](const Stage &st, int i, bool general) {
@@ -336,7 +345,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         for (int j = 0; j < PX_U; ++j) {
             int n = 0;
             float a = 0.0f;
-            const bool dok = dec.decode_bf(st.e[j], N, n, a);  // 0 <= n <= N-2
+            const bool dok = dv.decode_bf1(st.e[j], N, n, a);  // 0 <= n <= N-2
             const int sa = s0 + 2 * j, sb = sa + 1;
             float w0 = sa < se ? 1.0f : 0.0f, w1 = sb < se ? 1.0f : 0.0f;
             if constexpr (HAS_W) {
@@ -382,13 +391,13 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         __builtin_amdgcn_sched_barrier(0);
         genB = samples(i + 1, B);
         __builtin_amdgcn_sched_barrier(0);
-        sum(A, i, __any(genA));
+        sum(A, i, genA);
         if (i + 1 >= nstep) break;
         delays(i + 3, B);
         __builtin_amdgcn_sched_barrier(0);
         genA = samples(i + 2, A);
         __builtin_amdgcn_sched_barrier(0);
-        sum(B, i + 1, __any(genB));
+        sum(B, i + 1, genB);
     }
     return acc * sc;  // the FP16 frame scale (1 otherwise); filter and interpolation are linear
 }
