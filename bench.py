@@ -72,11 +72,20 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")
 
 
-def cpu_baseline(geo, table, frames, budget_s=12.0):
+def cpu_baseline(geo, vol, budget_s=12.0):
     """The FP64 oracle (filter + gather) on the host cores, timed on a bounded
-    sample of the same workload: whole frames, repeated for about budget_s."""
+    sample of the same workload: whole frames, repeated for about budget_s.
+    Its inputs are its own: the oracle's delay table of the geometry (built
+    before the timed region) and frames synthesised from it."""
+    from paper_1501_03869_amd import inputs
     from oracle import oracle as orc
-    T = np.ascontiguousarray(np.asarray(table, dtype=np.float64))
+    if vol:
+        T = orc.tables3(geo.speed, geo.h, geo.sensors, geo.pix)
+        frames = [inputs.frame_for3(geo, T, f) for f in range(2)]
+    else:
+        T = orc.tables(geo.speed, geo.h, geo.sensors, geo.pix)
+        phantom = "points" if geo.nx * geo.ny > 512 * 512 else "segments"
+        frames = [inputs.frame_for(geo, T, f, phantom=phantom) for f in range(2)]
     n = 0
     t0 = time.perf_counter()
     while True:
@@ -87,9 +96,8 @@ def cpu_baseline(geo, table, frames, budget_s=12.0):
             break
     gathers = n * geo.S * geo.P
     return {"value": gathers / el, "unit": "gathers/s", "cores": orc.max_threads(), "kind": "oracle",
-            "sample": f"{n} whole frames ({geo.S} sensors x {geo.P} {'voxels' if hasattr(geo, 'nz') else 'pixels'}) "
-                      f"of the same workload, FP64 filter + "
-                      f"gather, {el:.1f} s"}
+            "sample": f"{n} whole frames ({geo.S} sensors x {geo.P} {'voxels' if vol else 'pixels'}) of the same "
+                      f"workload (the oracle's own table and frames), FP64 filter + gather, {el:.1f} s"}
 
 
 def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
@@ -475,7 +483,7 @@ def main():
     if args.serve > 0 and not vol:
         out["serving"] = [run_serving(ctx, args.serve, v) for v in ("v0", "v3")]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(geo, table_h, frames_h)
+        out["cpu_baseline"] = cpu_baseline(geo, vol)
     print(json.dumps(out), flush=True)
     ctx.close()
 
