@@ -49,12 +49,12 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 of the files below; any change makes the field null until the
 # counters are taken again.  Summaries: profiles/k_bp_px_*_hbm_counters.md.
 TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_common.h")
-TRAFFIC_SHA = "95087522a9f5ad778647d8288221cab345cdc3c54c34df3eb94a204f85858c40:" \
-              "b759672c62a06a02c3815c3b0e7c34da647c831a9640bff5695d9272284e1fed"
+TRAFFIC_SHA = "de32106d2a780f9d6d2b13f5916874d47d57f31a8f4bdbbf6edec8226baf8f22:" \
+              "046afad2d9d976f56fb21100e0e5c9f9620cda616a8d09c45b88ba79e760cfe7"
 FETCH_FACTOR = 250000.0 / 125012.32
 WRITE_FACTOR = 1.0
-TRAFFIC_KIB = {"paper": (25210.72, 83.51), "large": (1836692.48, 3286.97),
-               "head3": (24703.05, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+TRAFFIC_KIB = {"paper": (25166.14, 83.44), "large": (1822671.10, 3268.67),
+               "head3": (24509.75, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 
 
 def measured_traffic(config: str):
