@@ -25,7 +25,9 @@
  *   5. orc_table_to_q16 / orc_gather_q16: the same gather from a delay table
  *      stored as a 16.16 fixed-point fractional sample index.
  *   6. orc_seed3 / orc_fmm3 / orc_tables3: steps 1-2 on a 3-D grid with the
- *      6-neighbour Godunov update (3-D reconstruction, Section IV).
+ *      6-neighbour Godunov update (3-D reconstruction, Section IV);
+ *      orc_tables_const3: the straight-ray table of the conventional back
+ *      projection on the same grid (orc_tables_const is its 2-D form).
  *   7. orc_table_to_r16 / orc_r16_to_q16: the 16.16 table of item 5 stored as
  *      16-bit offsets from a base per sensor and tile of 32 ROI positions
  *      (a compressed storage form; not in the paper).
@@ -299,6 +301,27 @@ int orc_tables_const(int nx, int ny, double h, double c, const double *sxy, int 
 }
 
 /* ---------------------------------------------------------- 3-D eikonal */
+
+/* Straight-ray delays |x_k - s| / c on a 3-D grid (the conventional back
+ * projection's table in 3-D): node k = (l ny + j) nx + i at the grid-centred
+ * position of the 3-D convention below; sxyz [S][3]. */
+int orc_tables_const3(int nx, int ny, int nz, double h, double c, const double *sxyz, int S, const int32_t *vox,
+                      long P, double *table) {
+    long n = (long)nx * ny * nz;
+    if (!(c > 0.0)) return -1;
+    for (long p = 0; p < P; ++p)
+        if (vox[p] < 0 || vox[p] >= n) return -1;
+    double x0 = -0.5 * (nx - 1) * h, y0 = -0.5 * (ny - 1) * h, z0 = -0.5 * (nz - 1) * h;
+    for (int s = 0; s < S; ++s) {
+        for (long p = 0; p < P; ++p) {
+            int i = vox[p] % nx, j = (vox[p] / nx) % ny, l = vox[p] / (nx * ny);
+            double dx = (x0 + i * h) - sxyz[3 * s], dy = (y0 + j * h) - sxyz[3 * s + 1],
+                   dz = (z0 + l * h) - sxyz[3 * s + 2];
+            table[(long)s * P + p] = sqrt(dx * dx + dy * dy + dz * dz) / c;
+        }
+    }
+    return 0;
+}
 /*
  * The same method on a 3-D grid, the extension the paper anticipates for 3-D
  * reconstruction (Section IV): node (i, j, l) with index k = (l ny + j) nx + i

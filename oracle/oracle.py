@@ -53,6 +53,9 @@ def lib():
         L.orc_tables.restype = C.c_int
         L.orc_tables_const.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, C.c_int, _i32, C.c_long, _dp]
         L.orc_tables_const.restype = C.c_int
+        L.orc_tables_const3.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, _dp, C.c_int, _i32,
+                                        C.c_long, _dp]
+        L.orc_tables_const3.restype = C.c_int
         L.orc_filter.argtypes = [_dp, C.c_long, C.c_int, C.c_double, C.c_double, _dp]
         L.orc_filter.restype = None
         L.orc_gather.argtypes = [_dp, _dp, C.c_void_p, C.c_int, C.c_long, C.c_int, C.c_int, C.c_double,
@@ -141,6 +144,17 @@ def tables_const(nx: int, ny: int, h: float, c: float, sensors: np.ndarray, pix:
     out = np.empty((sxy.shape[0], pix.shape[0]), dtype=np.float64)
     if lib().orc_tables_const(int(nx), int(ny), float(h), float(c), sxy, sxy.shape[0], pix, pix.shape[0], out):
         raise ValueError("orc_tables_const: invalid input")
+    return out
+
+
+def tables_const3(nx: int, ny: int, nz: int, h: float, c: float, sensors: np.ndarray, vox: np.ndarray) -> np.ndarray:
+    """Straight-ray delays |x - s| / c on a 3-D grid; sensors [S][3]."""
+    sxyz = np.ascontiguousarray(sensors, dtype=np.float64)
+    vox = np.ascontiguousarray(vox, dtype=np.int32)
+    out = np.empty((sxyz.shape[0], vox.shape[0]), dtype=np.float64)
+    if lib().orc_tables_const3(int(nx), int(ny), int(nz), float(h), float(c), sxyz, sxyz.shape[0], vox,
+                               vox.shape[0], out):
+        raise ValueError("orc_tables_const3: invalid input")
     return out
 
 

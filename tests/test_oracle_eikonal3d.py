@@ -158,3 +158,39 @@ def test_tables3_match_maps_and_reject(orc):
         orc.tables3(geo.speed, geo.h, np.array([[1.0, 0.0, 0.0]]), geo.pix)
     with pytest.raises(ValueError):
         orc.tables3(geo.speed, geo.h, geo.sensors, np.array([geo.speed.size], np.int32))
+
+
+def test_const3_straight_rays(orc):
+    # the conventional back projection's 3-D straight-ray table: a one-layer
+    # grid gives the (pinned) 2-D straight-ray table bit for bit, exchanging
+    # axes permutes it, and the fast-marching table of a homogeneous cube lies
+    # above it within the first-order scheme's error
+    n, h, c = 21, 0.3e-3, 1500.0
+    x, y, z = inputs.node_coords3(n, n, n, h)
+    rng = np.random.default_rng(12)
+    sens = np.stack([rng.uniform(x[0], x[-1], 3), rng.uniform(y[0], y[-1], 3), rng.uniform(z[0], z[-1], 3)], 1)
+    vox = rng.permutation(n ** 3)[:2000].astype(np.int32)
+    T = orc.tables_const3(n, n, n, h, c, sens, vox)
+    # one layer
+    x2, y2 = inputs.node_coords(n, 17, h)
+    s2 = np.stack([rng.uniform(x2[0], x2[-1], 4), rng.uniform(y2[0], y2[-1], 4)], 1)
+    pix = np.arange(n * 17, dtype=np.int32)
+    T2 = orc.tables_const(n, 17, h, c, s2, pix)
+    T1 = orc.tables_const3(n, 17, 1, h, c, np.concatenate([s2, np.zeros((4, 1))], 1), pix)
+    assert np.array_equal(T1, T2)
+    # axis exchange x <-> z: node (i, j, l) -> (l, j, i), sensor (sx, sy, sz) -> (sz, sy, sx)
+    i, j, l = vox % n, (vox // n) % n, vox // (n * n)
+    Tp = orc.tables_const3(n, n, n, h, c, sens[:, ::-1].copy(), (i * n + j) * n + l)
+    np.testing.assert_allclose(Tp, T, rtol=1e-15, atol=0)
+    # homogeneous fast marching from nodes (sensors snapped to nodes)
+    snap = np.stack([x[np.abs(x[:, None] - sens[:, 0]).argmin(0)], y[np.abs(y[:, None] - sens[:, 1]).argmin(0)],
+                     z[np.abs(z[:, None] - sens[:, 2]).argmin(0)]], 1)
+    Ts = orc.tables_const3(n, n, n, h, c, snap, vox)
+    Fm = orc.tables3(np.full((n, n, n), c, np.float32), h, snap, vox)
+    far = Ts > 5 * h / c
+    assert np.all(Fm >= Ts * (1 - 1e-12))
+    assert ((Fm - Ts)[far] / Ts[far]).max() < 0.15
+    with pytest.raises(ValueError):
+        orc.tables_const3(n, n, n, h, -1.0, sens, vox)
+    with pytest.raises(ValueError):
+        orc.tables_const3(n, n, n, h, c, sens, np.array([n ** 3], np.int32))
