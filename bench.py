@@ -133,6 +133,25 @@ def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
     single("v4_r16_table_f16_signal", r16, half, scale_d)
     single("v4a_r16_table_f32_signal", r16, frames, None)
 
+    # the conventional back projection (straight rays at 1540 m/s computed per
+    # gather, no table) on the same frames
+    pix_d = torch.from_numpy(np.ascontiguousarray(geo.pix)).to(dev)
+
+    def conv(i):
+        r = i % R
+        if hasattr(geo, "nz"):
+            ctx.backproject_const_3d(geo.nx, geo.ny, geo.nz, geo.h, 1540.0, geo.sensors, pix_d, frames[r], geo.dt,
+                                     geo.t0, filtered=False, out=img[r], stream=stream)
+        else:
+            ctx.backproject_const(geo.nx, geo.ny, geo.h, 1540.0, geo.sensors, pix_d, frames[r], geo.dt, geo.t0,
+                                  filtered=False, out=img[r], stream=stream)
+    wall, ms = timed(conv, args.steps, args.warmup)
+    res["conventional_bp_straight_rays"] = {
+        "frames_per_launch": 1, "gathers_per_s": args.steps * S * P / wall, "frames_per_s": args.steps / wall,
+        "timing_note": "eager single-frame launches (wall time, including the per-call sensor upload); "
+                       "device_ms_*: HIP events around each", "device_ms_p50": percentile(ms, 50),
+        "device_ms_p99": percentile(ms, 99)}
+
     # batched: F frames per launch, table read once; replayed from a HIP graph
     F = 64
     idx = np.arange(F) % R

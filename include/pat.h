@@ -278,6 +278,22 @@ int pat_backproject_const(pat_ctx *ctx, int nx, int ny, double h, double c, cons
                           const float *d_frame_scale, const float *d_w, int N, int F, double t0, double dt,
                           float *d_img, void *stream);
 
+/*
+ * The conventional back projection on a 3-D grid (the 3-D counterpart of
+ * pat_backproject_const, for the 3-D reconstruction anticipated in
+ * Section IV): straight-ray delays |x_vox[p] - s| / c computed per gather in
+ * FP32.  d_vox are node indices k = (l*ny + j)*nx + i on the grid convention
+ * of pat_eikonal_tables_3d, each in [0, nx*ny*nz) (used only as
+ * coordinates); h_sensor_xyz is host float64 [S][3] metres (copied
+ * stream-ordered into context memory).  Runs the split-sensor kernel only:
+ * PAT_EINVAL unless N >= 4 and d_sig is aligned to its sample size.  Other
+ * arguments as pat_backproject; uses no scratch.
+ */
+int pat_backproject_const_3d(pat_ctx *ctx, int nx, int ny, int nz, double h, double c, const double *h_sensor_xyz,
+                             int S, const int32_t *d_vox, int P, const void *d_sig, int sig_fmt, int sig_is_filtered,
+                             const float *d_frame_scale, const float *d_w, int N, int F, double t0, double dt,
+                             float *d_img, void *stream);
+
 /* ------------------------------------------------------------------ serving
  *
  * A frame server keeps each speed map's delay table resident in HBM (the

@@ -252,6 +252,40 @@ extern "C" int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt,
                                   N, F, t0, dt, d_img, (hipStream_t)stream);
 }
 
+extern "C" int pat_backproject_const_3d(pat_ctx *ctx, int nx, int ny, int nz, double h, double c,
+                                        const double *h_sensor_xyz, int S, const int32_t *d_vox, int P,
+                                        const void *d_sig, int sig_fmt, int sig_is_filtered, const float *d_frame_scale,
+                                        const float *d_w, int N, int F, double t0, double dt, float *d_img,
+                                        void *stream) {
+    int rc = pat_make_current(ctx);
+    if (rc) return rc;
+    if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz > INT32_MAX || !finite_pos(h) || !finite_pos(c))
+        return pat_fail(PAT_EINVAL, "need a grid of at most 2^31-1 nodes, h > 0 and c > 0");
+    if (S < 0 || P < 0 || F < 0) return pat_fail(PAT_EINVAL, "negative size");
+    if (N < 2 || !finite_pos(dt) || !std::isfinite(t0)) return pat_fail(PAT_EINVAL, "need N >= 2, finite t0, dt > 0");
+    if (sig_fmt != PAT_SIG_F32 && sig_fmt != PAT_SIG_F16) return pat_fail(PAT_EINVAL, "unknown signal format %d", sig_fmt);
+    if ((long long)S * N > INT32_MAX) return pat_fail(PAT_EINVAL, "sizes too large");
+    if (P == 0 || F == 0) return PAT_OK;
+    if (!d_img || !d_vox || (S > 0 && (!d_sig || !h_sensor_xyz))) return pat_fail(PAT_EINVAL, "null pointer");
+    if (S == 0)
+        return pat_launch_backproject_const(ctx, nx, ny, h, c, nullptr, 0, d_vox, P, d_sig, sig_fmt, sig_is_filtered,
+                                            d_frame_scale, d_w, N, F, t0, dt, d_img, (hipStream_t)stream);
+    if (!pat_px_eligible(sig_fmt, S, P, N, F, d_sig))
+        return pat_fail(PAT_EINVAL, "3-D straight-ray back projection needs N >= 4, a signal pointer aligned to its "
+                                    "sample size and per-step offsets below 2^31 (N=%d)", N);
+    std::vector<float> sxyz((size_t)3 * S);
+    for (int i = 0; i < 3 * S; ++i) {
+        if (!std::isfinite(h_sensor_xyz[i])) return pat_fail(PAT_EINVAL, "non-finite sensor position");
+        sxyz[(size_t)i] = (float)h_sensor_xyz[i];
+    }
+    if ((rc = ctx->sensors.grow(sxyz.size() * sizeof(float)))) return rc;
+    PAT_HIP(hipMemcpyAsync(ctx->sensors.ptr, sxyz.data(), sxyz.size() * sizeof(float), hipMemcpyHostToDevice,
+                           (hipStream_t)stream));
+    return pat_launch_backproject_px_const(nx, h, c, static_cast<const float *>(ctx->sensors.ptr), S, d_vox, P, d_sig,
+                                           sig_fmt, sig_is_filtered, d_frame_scale, d_w, N, F, t0, dt, d_img, ny,
+                                           (hipStream_t)stream, nz);
+}
+
 extern "C" int pat_backproject_const(pat_ctx *ctx, int nx, int ny, double h, double c, const double *h_sensor_xy,
                                      int S, const int32_t *d_pix, int P, const void *d_sig, int sig_fmt,
                                      int sig_is_filtered, const float *d_frame_scale, const float *d_w, int N, int F,

@@ -104,9 +104,9 @@ struct PxJob {
     // straight-ray delays |x - s| / c instead of a table (conventional back
     // projection): pixel node indices, sensor positions, grid
     const int32_t *pix;
-    const float *sxy;     // [S][2] metres
-    int nx;
-    float h, x0, y0, inv_c;
+    const float *sxy;     // [S][2] metres (2-D) or [S][3] (3-D)
+    int nx, ny;
+    float h, x0, y0, z0, inv_c;
 };
 
 // One pipeline stage: the delays of U sensors of this lane's slot as loaded
@@ -122,7 +122,7 @@ struct Stage {
 // sw .. sw+2*sps-1 (sw = wv*2*sps, clipped to S); lanes 0-31 take the even
 // ones, lanes 32-63 the odd ones.  wv must be wave-uniform (a scalar) and
 // sw < S.
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W, bool CONSTC = false>
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC = 0>
 __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, int tile, int wv) {
     const int S = J.S, P = J.P, N = J.N, sps = J.sps;
     const float t0dt = J.t0dt, sc = J.scale;
@@ -237,14 +237,19 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     // static: a step past the last re-reads the wave's last records, and a
     // sensor past the wave's end reads zeros (outside the descriptor) and
     // contributes nothing.
-    float pxx = 0.0f, pxy = 0.0f;  // this lane's pixel position (straight-ray delays)
-    if constexpr (CONSTC) {
+    float pxx = 0.0f, pxy = 0.0f, pxz = 0.0f;  // this lane's node position (straight-ray delays)
+    if constexpr (CONSTC == 2) {
         const int k = J.pix[pc];
         pxx = J.x0 + (float)(k % J.nx) * J.h;
         pxy = J.y0 + (float)(k / J.nx) * J.h;
+    } else if constexpr (CONSTC == 3) {
+        const int k = J.pix[pc];
+        pxx = J.x0 + (float)(k % J.nx) * J.h;
+        pxy = J.y0 + (float)((k / J.nx) % J.ny) * J.h;
+        pxz = J.z0 + (float)(k / (J.nx * J.ny)) * J.h;
     }
     auto delays = [&](int i, Stage &st) {
-        if constexpr (CONSTC) {
+        if constexpr (CONSTC == 2) {
             const int s0 = step_s0(i);
 #pragma unroll
             for (int j = 0; j < PX_U; ++j) {
@@ -253,6 +258,15 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
                 const float sy = half ? J.sxy[2 * sb + 1] : J.sxy[2 * sa + 1];
                 const float dx = pxx - sx, dy = pxy - sy;
                 st.d[j] = __float_as_uint(__builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy)) * J.inv_c);
+            }
+        } else if constexpr (CONSTC == 3) {
+            const int s0 = step_s0(i);
+#pragma unroll
+            for (int j = 0; j < PX_U; ++j) {
+                const int sa = min(s0 + 2 * j, S - 1), sb = min(s0 + 2 * j + 1, S - 1);
+                const int sr = half ? sb : sa;
+                const float dx = pxx - J.sxy[3 * sr], dy = pxy - J.sxy[3 * sr + 1], dz = pxz - J.sxy[3 * sr + 2];
+                st.d[j] = __float_as_uint(__builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) * J.inv_c);
             }
         } else if constexpr (Delay::kR16) {
             const int s0 = step_s0(i);
@@ -404,7 +418,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
 
 // One tile of one frame: every wave sums its slots, then the slot sums are
 // added in slot order.  Waves whose slots start past S add zero.
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W, bool CONSTC = false>
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC = 0>
 __device__ __forceinline__ void px_block(const PxJob &J, const Delay &dec, int tile, int wv, int nw) {
     __shared__ float red[2 * PX_MAX_WAVES][PX_T];
     const int lane = threadIdx.x & 63;
@@ -426,11 +440,11 @@ __device__ __forceinline__ void px_block(const PxJob &J, const Delay &dec, int t
 struct PxGeom {
     const int32_t *pix;
     const float *sxy;
-    int nx;
-    float h, x0, y0, inv_c;
+    int nx, ny;
+    float h, x0, y0, z0, inv_c;
 };
 
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W, bool CONSTC>
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC>
 __global__ void __launch_bounds__(64 * PX_MAX_WAVES)
     k_bp_px(const uint32_t *__restrict__ tab, const void *__restrict__ sig, const float *__restrict__ scale,
             const float *__restrict__ w, int S, int P, int N, int sps, Delay dec, float t0dt,
@@ -445,8 +459,8 @@ __global__ void __launch_bounds__(64 * PX_MAX_WAVES)
     J.S = S; J.P = P; J.N = N; J.sps = sps;
     J.t0dt = t0dt;
     J.scale = (SFMT == PAT_SIG_F16 && scale) ? scale[f] : 1.0f;
-    J.pix = geo.pix; J.sxy = geo.sxy; J.nx = geo.nx;
-    J.h = geo.h; J.x0 = geo.x0; J.y0 = geo.y0; J.inv_c = geo.inv_c;
+    J.pix = geo.pix; J.sxy = geo.sxy; J.nx = geo.nx; J.ny = geo.ny;
+    J.h = geo.h; J.x0 = geo.x0; J.y0 = geo.y0; J.z0 = geo.z0; J.inv_c = geo.inv_c;
     // a wave-uniform wave index keeps the descriptors in scalar registers
     const int tile = xcd_tile(blockIdx.x, (P + PX_T - 1) / PX_T);
     if (tile < 0) return;
@@ -491,7 +505,7 @@ __global__ void __launch_bounds__(64 * PX_MULTI_WAVES) k_bp_px_multi(const pat_b
     }
 }
 
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W, bool CONSTC = false>
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC = 0>
 int launch_one(int S, int P, int F, const uint32_t *tab, const void *sig, const float *scale, const float *w, int N,
                Delay dec, float t0dt, float *img, hipStream_t st, const PxGeom &geo = PxGeom{}) {
     // occupancy per block size, computed once per kernel and device
@@ -528,16 +542,16 @@ int launch_px(bool filtered, int S, int P, int F, const uint32_t *tab, const voi
                     : launch_one<Delay, SFMT, false, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
 }
 
-template <int SFMT>
+template <int SFMT, int DIM>
 int launch_px_const(bool filtered, int S, int P, int F, const void *sig, const float *scale, const float *w, int N,
                     DelayF32 dec, float t0dt, float *img, hipStream_t st, const PxGeom &geo) {
     if (w)
         return filtered
-                   ? launch_one<DelayF32, SFMT, true, true, true>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo)
-                   : launch_one<DelayF32, SFMT, false, true, true>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo);
+                   ? launch_one<DelayF32, SFMT, true, true, DIM>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo)
+                   : launch_one<DelayF32, SFMT, false, true, DIM>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo);
     return filtered
-               ? launch_one<DelayF32, SFMT, true, false, true>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo)
-               : launch_one<DelayF32, SFMT, false, false, true>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo);
+               ? launch_one<DelayF32, SFMT, true, false, DIM>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo)
+               : launch_one<DelayF32, SFMT, false, false, DIM>(S, P, F, nullptr, sig, scale, w, N, dec, t0dt, img, st, geo);
 }
 
 }  // namespace
@@ -545,7 +559,7 @@ int launch_px_const(bool filtered, int S, int P, int F, const void *sig, const f
 int pat_launch_backproject_px_const(int nx, double h, double c, const float *d_sxy, int S, const int32_t *d_pix,
                                     int P, const void *sig, int sig_fmt, int sig_is_filtered, const float *frame_scale,
                                     const float *w, int N, int F, double t0, double dt, float *img, int ny,
-                                    hipStream_t st) {
+                                    hipStream_t st, int nz) {
     DelayF32 d;
     const double inv = 1.0 / dt;
     d.inv_hi = (float)inv;
@@ -556,15 +570,21 @@ int pat_launch_backproject_px_const(int nx, double h, double c, const float *d_s
     g.pix = d_pix;
     g.sxy = d_sxy;
     g.nx = nx;
+    g.ny = ny;
     g.h = (float)h;
     g.x0 = (float)(-0.5 * (nx - 1) * h);
     g.y0 = (float)(-0.5 * (ny - 1) * h);
+    g.z0 = (float)(-0.5 * (nz - 1) * h);
     g.inv_c = (float)(1.0 / c);
     const float t0dt = (float)(t0 / dt);
     const bool filt = sig_is_filtered != 0;
+    if (nz > 0)
+        return sig_fmt == PAT_SIG_F32
+                   ? launch_px_const<PAT_SIG_F32, 3>(filt, S, P, F, sig, frame_scale, w, N, d, t0dt, img, st, g)
+                   : launch_px_const<PAT_SIG_F16, 3>(filt, S, P, F, sig, frame_scale, w, N, d, t0dt, img, st, g);
     return sig_fmt == PAT_SIG_F32
-               ? launch_px_const<PAT_SIG_F32>(filt, S, P, F, sig, frame_scale, w, N, d, t0dt, img, st, g)
-               : launch_px_const<PAT_SIG_F16>(filt, S, P, F, sig, frame_scale, w, N, d, t0dt, img, st, g);
+               ? launch_px_const<PAT_SIG_F32, 2>(filt, S, P, F, sig, frame_scale, w, N, d, t0dt, img, st, g)
+               : launch_px_const<PAT_SIG_F16, 2>(filt, S, P, F, sig, frame_scale, w, N, d, t0dt, img, st, g);
 }
 
 bool pat_px_eligible(int sig_fmt, int S, int P, int N, int F, const void *sig) {

@@ -84,11 +84,12 @@ size_t pat_gather_counter_bytes(int P, int F);
 constexpr size_t PAT_CACHED_TABLE_BYTES = 128ull << 20;
 // one-pixel-per-lane gather (no LDS windows, no partial sums in global memory)
 bool pat_px_eligible(int sig_fmt, int S, int P, int N, int F, const void *sig);
-// the same with straight-ray delays |x - s| / c computed per gather (d_sxy: float32 [S][2] metres)
+// the same with straight-ray delays |x - s| / c computed per gather (d_sxy: float32 metres)
+// nz = 0: 2-D grid, d_sxy [S][2]; nz >= 1: 3-D grid, d_sxy [S][3]
 int pat_launch_backproject_px_const(int nx, double h, double c, const float *d_sxy, int S, const int32_t *d_pix,
                                     int P, const void *sig, int sig_fmt, int sig_is_filtered, const float *frame_scale,
                                     const float *w, int N, int F, double t0, double dt, float *img, int ny,
-                                    hipStream_t st);
+                                    hipStream_t st, int nz = 0);
 int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig, int sig_fmt, int sig_is_filtered,
                               const float *frame_scale, const float *w, int S, int P, int N, int F, double t0,
                               double dt, float *img, hipStream_t st);

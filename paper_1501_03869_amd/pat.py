@@ -23,7 +23,7 @@ SIG_F32, SIG_F16 = 0, 1
 EXPORTED = [
     "pat_last_error", "pat_version", "pat_ctx_create", "pat_ctx_destroy", "pat_ctx_reserve",
     "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_3d", "pat_eikonal_last_stats", "pat_table_to_q16", "pat_table_to_r16", "pat_table_r16_bytes",
-    "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_const",
+    "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_const", "pat_backproject_const_3d",
     "pat_server_create", "pat_server_destroy", "pat_server_add_map", "pat_server_map_state",
     "pat_server_remove_map", "pat_server_submit", "pat_server_wait", "pat_server_get_stats",
     "pat_server_reset_stats",
@@ -90,6 +90,8 @@ def lib() -> C.CDLL:
         L.pat_backproject.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp, i32, i32, i32, i32, dbl, dbl, vp, vp]
         L.pat_backproject_const.argtypes = [vp, i32, i32, dbl, dbl, vp, i32, vp, i32, vp, i32, i32, vp, vp, i32, i32,
                                             dbl, dbl, vp, vp]
+        L.pat_backproject_const_3d.argtypes = [vp, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, vp, i32, i32, vp, vp,
+                                               i32, i32, dbl, dbl, vp, vp]
         L.pat_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
         L.pat_server_destroy.argtypes = [vp]
         L.pat_server_add_map.argtypes = [vp, vp, i32, i32, dbl, vp, i32, vp, i32, dbl, dbl, i32, C.POINTER(i32)]
@@ -254,6 +256,34 @@ class Context:
         check(lib().pat_backproject(self.h, _ptr(table), tfmt, _ptr(sig), sfmt, 1 if filtered else 0,
                                     _ptr(frame_scale), _ptr(w), S, P, N, F, float(t0), float(dt), _ptr(out),
                                     _stream(stream)))
+        return out
+
+    def backproject_const_3d(self, nx: int, ny: int, nz: int, h: float, c: float, sensors: np.ndarray, vox, sig,
+                             dt: float, t0: float = 0.0, *, filtered: bool = True, w=None, frame_scale=None, out=None,
+                             stream=None):
+        """Conventional back projection on a 3-D grid (straight-ray delays |x - s| / c)."""
+        import torch
+        _need(vox, torch.int32, "vox")
+        sxyz = np.ascontiguousarray(sensors, dtype=np.float64)
+        if sxyz.ndim != 2 or sxyz.shape[1] != 3:
+            raise ValueError("sensors must be [S][3]")
+        S, P = sxyz.shape[0], vox.shape[0]
+        single = sig.dim() == 2
+        F = 1 if single else sig.shape[0]
+        N = sig.shape[-1]
+        if sig.shape[-2] != S:
+            raise ValueError("signal and sensor counts differ")
+        sfmt = SIG_F16 if sig.dtype == torch.float16 else SIG_F32
+        _need(sig, torch.float16 if sfmt == SIG_F16 else torch.float32, "sig")
+        _need(w, torch.float32, "w")
+        _need(frame_scale, torch.float32, "frame_scale")
+        if out is None:
+            out = torch.empty((P,) if single else (F, P), dtype=torch.float32, device=sig.device)
+        _need(out, torch.float32, "out")
+        check(lib().pat_backproject_const_3d(self.h, int(nx), int(ny), int(nz), float(h), float(c), sxyz.ctypes.data,
+                                             S, _ptr(vox), P, _ptr(sig), sfmt, 1 if filtered else 0,
+                                             _ptr(frame_scale), _ptr(w), N, F, float(t0), float(dt), _ptr(out),
+                                             _stream(stream)))
         return out
 
     def backproject_const(self, nx: int, ny: int, h: float, c: float, sensors: np.ndarray, pix, sig, dt: float,

@@ -1,8 +1,8 @@
 """3-D delay tables (6-neighbour first-order Godunov, brick-parallel
-relaxation) against the 3-D fast-marching oracle, and a 3-D end-to-end
+relaxation) against the 3-D fast-marching oracle, a 3-D end-to-end
 reconstruction (GPU tables, GPU fused filter and gather) against the
-all-oracle pipeline.  The gather kernels are the 2-D ones with voxels as
-pixels, so only the tables are new here."""
+all-oracle pipeline, and the 3-D conventional (straight-ray) back projection.
+The table-based gather is the 2-D kernel with voxels as pixels."""
 import numpy as np
 import pytest
 import torch
@@ -181,3 +181,52 @@ def test_rejects_bad_input(ctx):
     # S = 0 or P = 0: nothing to do, no error
     t = ctx.eikonal_tables_3d(dev(geo.speed), geo.h, np.zeros((0, 3)), dev(geo.pix))
     assert t.shape == (0, geo.P)
+
+
+@pytest.mark.parametrize("F,sig,filtered,weights", [(1, "f32", False, False), (2, "f32", True, True),
+                                                    (1, "f16", False, True)])
+def test_const3_backprojection(ctx, orc, F, sig, filtered, weights):
+    # the conventional back projection on the 3-D head grid (straight rays at
+    # 1540 m/s computed per gather) against the oracle's straight-ray table
+    # and FP64 filter and gather; a quarter of the sensors, the ROI in tile order
+    from paper_1501_03869_amd import pat
+    geo = inputs.config3("head3")
+    sens = geo.sensors[::4]
+    vox = pat.tile_order_3d(geo.nx, geo.ny, geo.nz, geo.pix, 4, 4, 2)
+    S, N = sens.shape[0], geo.n_samples
+    T = orc.tables_const3(geo.nx, geo.ny, geo.nz, geo.h, 1540.0, sens, vox)
+    rng = np.random.default_rng(F + 10)
+    p = inputs.random_signals(70 + F, S, N, F).reshape(F, S, N)
+    w = rng.uniform(0.5, 1.5, S).astype(np.float32) if weights else None
+    if sig == "f16":
+        scale = (np.abs(p).reshape(F, -1).max(1) / 2.0 ** 14).astype(np.float32)
+        h = (p / scale[:, None, None]).astype(np.float16)
+        vals = h.astype(np.float64) * scale.astype(np.float64)[:, None, None]
+        x = dev(h if F > 1 else h[0])
+        fs = dev(scale)
+    else:
+        vals, x, fs = p.astype(np.float64), dev(p if F > 1 else p[0]), None
+    got = ctx.backproject_const_3d(geo.nx, geo.ny, geo.nz, geo.h, 1540.0, sens, dev(vox), x, geo.dt,
+                                   filtered=filtered, w=None if w is None else dev(w),
+                                   frame_scale=fs).cpu().numpy().reshape(F, -1)
+    for f in range(F):
+        b = vals[f] if filtered else orc.filt(vals[f], geo.dt)
+        ref = orc.gather(T, b, geo.dt, 0.0, None if w is None else w.astype(np.float64))
+        err = float(np.linalg.norm(got[f] - ref) / np.linalg.norm(ref))
+        print(f"[const3] F={F} {sig} filtered={filtered} frame {f}: rel L2 {err:.3e}", flush=True)
+        assert err <= 1e-4
+
+
+def test_const3_rejects_and_empty(ctx):
+    from paper_1501_03869_amd import pat
+    geo = inputs.config3("tiny3")
+    p = dev(inputs.random_signals(3, geo.S, 3))
+    with pytest.raises(pat.PatError):  # N < 4: no split-sensor kernel
+        ctx.backproject_const_3d(geo.nx, geo.ny, geo.nz, geo.h, 1500.0, geo.sensors, dev(geo.pix), p, geo.dt)
+    with pytest.raises(pat.PatError):
+        ctx.backproject_const_3d(geo.nx, geo.ny, geo.nz, geo.h, -1.0, geo.sensors,
+                                 dev(geo.pix), dev(inputs.random_signals(3, geo.S, 16)), geo.dt)
+    out = torch.full((geo.P,), float("nan"), device="cuda")
+    img = ctx.backproject_const_3d(geo.nx, geo.ny, geo.nz, geo.h, 1500.0, np.zeros((0, 3)), dev(geo.pix),
+                                   torch.zeros((0, 16), device="cuda"), geo.dt, out=out)
+    assert torch.count_nonzero(img).item() == 0
