@@ -210,6 +210,39 @@ def test_backproject_split_sensor_edges(ctx, orc, sig, N, filtered, F):
     assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("sig,filtered", [("f32", False), ("f32", True), ("f16", False)])
+def test_backproject_fast_range_boundaries(ctx, orc, sig, filtered):
+    # Mostly interior delays, so most pipeline steps take the split-sensor
+    # kernel's fast path, with a few columns exactly on the edges of its
+    # range: u = 1 and the float below it, the float below N-2 and N-2
+    # itself, u = N-1 (valid, last interval) and 0.  dt = 2^-24 makes
+    # u = T/dt exact.  Tiles holding such a column take the general path;
+    # both must agree with the oracle.
+    dt, S, P, N = 2.0 ** -24, 64, 2048, 64
+    rng = np.random.default_rng(31)
+    u = rng.uniform(2.0, N - 3.0, size=(S, P))
+    below1 = np.nextafter(np.float32(1.0), np.float32(0.0))
+    below_hi = np.nextafter(np.float32(N - 2), np.float32(0.0))
+    edge = [1.0, below1, below_hi, N - 2.0, N - 1.0, 0.0]
+    for s in range(S):
+        for k, e in enumerate(edge):
+            u[s, (k * 331 + 7 * s) % P] = e
+    T = (u * dt).astype(np.float32)
+    assert np.all(T.astype(np.float64) / dt == u.astype(np.float32))
+    p = inputs.random_signals(32, S, N)
+    if sig == "f16":
+        scale, h, vals = _fp16_frames(p[None])
+        got = ctx.backproject(dev(T), dev(h[0]), dt, filtered=filtered, frame_scale=dev(scale)).cpu().numpy()
+        vals = vals[0]
+    else:
+        vals = p.astype(np.float64)
+        got = ctx.backproject(dev(T), dev(p), dt, filtered=filtered).cpu().numpy()
+    b = vals if filtered else orc.filt(vals, dt)
+    ref = orc.gather(T.astype(np.float64), b, dt)
+    assert rel_l2(got, ref) <= IMG_TOL
+    assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
 def test_backproject_empty_and_deterministic(ctx, orc):
     z = torch.zeros((0, 10), dtype=torch.float32, device="cuda")
     out = torch.full((10,), float("nan"), device="cuda")
