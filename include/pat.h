@@ -346,6 +346,12 @@ int pat_server_destroy(pat_server *s);
 int pat_server_add_map(pat_server *s, const float *h_speed, int nx, int ny, double h,
                        const double *h_sensor_xy, int S, const int32_t *h_pix, int P,
                        double t0, double dt, int N, int *map_id);
+/* The same for a 3-D map (pat_eikonal_tables_3d conventions: speed
+ * [nz][ny][nx], sensors [S][3], voxel indices (l*ny + j)*nx + i); its frames
+ * are submitted and gathered like any other map's. */
+int pat_server_add_map_3d(pat_server *s, const float *h_speed, int nx, int ny, int nz, double h,
+                          const double *h_sensor_xyz, int S, const int32_t *h_vox, int P,
+                          double t0, double dt, int N, int *map_id);
 int pat_server_map_state(pat_server *s, int map_id, int *state);
 /* Unregister an idle map (PAT_EBUSY while it has frames or a build). */
 int pat_server_remove_map(pat_server *s, int map_id);

@@ -49,10 +49,10 @@ enum FrameState { FR_QUEUED = 0, FR_INFLIGHT = 1, FR_DONE = 2, FR_FAILED = 3 };
 struct Map {
     int id = 0;
     int state = MAP_QUEUED;
-    int nx = 0, ny = 0;
+    int nx = 0, ny = 0, nz = 0;  // nz = 0: a 2-D map
     double h = 0;
     std::vector<float> speed;
-    std::vector<double> sxy;
+    std::vector<double> sxy;     // [S][2], or [S][3] for a 3-D map
     std::vector<int32_t> pix;
     int S = 0, P = 0, N = 0;
     double t0 = 0, dt = 0;
@@ -216,15 +216,16 @@ struct pat_server {
     // working memory pat_eikonal_tables will allocate in the builder's context
     // beyond what it already holds (its buffers only grow)
     size_t map_build_bytes(const Map &m) const {
-        const size_t n = (size_t)m.nx * m.ny;
-        const size_t tiles = (size_t)((m.nx + 31) / 32) * ((m.ny + 31) / 32);
+        const size_t n = (size_t)m.nx * m.ny * std::max(m.nz, 1);
+        const size_t tiles = m.nz > 0 ? (size_t)((m.nx + 7) / 8) * ((m.ny + 7) / 8) * ((m.nz + 7) / 8)
+                                      : (size_t)((m.nx + 31) / 32) * ((m.ny + 31) / 32);
         const size_t maps_per_chunk = std::min<size_t>(m.S, std::max<size_t>(1, (8ull << 30) / (n * 4)));
-        const size_t est = maps_per_chunk * n * 4 + n * 4 + 4 * tiles * maps_per_chunk * 4 + maps_per_chunk * 128 + 4096;
+        const size_t est = maps_per_chunk * n * 4 + n * 4 + 4 * tiles * maps_per_chunk * 4 + maps_per_chunk * 512 + 4096;
         return est > build_scratch ? est - build_scratch : 0;
     }
     // bytes a build also allocates through the pool: speed map, pixels, table(s)
     size_t map_pool_bytes(const Map &m) const {
-        size_t b = (size_t)m.nx * m.ny * 4 + (size_t)m.P * 4 + table_bytes(m);
+        size_t b = (size_t)m.nx * m.ny * std::max(m.nz, 1) * 4 + (size_t)m.P * 4 + table_bytes(m);
         if (cfg.table_fmt != PAT_TABLE_F32) b += (size_t)m.S * m.P * 4;  // the float32 table it is made from
         return b;
     }
@@ -279,7 +280,7 @@ void pat_server::builder() {
             m->state = MAP_BUILDING;
         }
         int rc = PAT_OK;
-        const size_t n = (size_t)m->nx * m->ny;
+        const size_t n = (size_t)m->nx * m->ny * std::max(m->nz, 1);
         void *d_speed = nullptr, *d_pix = nullptr, *d_f32 = nullptr, *d_out = nullptr;
         const size_t t32 = (size_t)m->S * m->P * 4;  // float32 table
         const size_t tb = table_bytes(*m);           // resident table
@@ -298,8 +299,12 @@ void pat_server::builder() {
                 hipMemcpyAsync(d_pix, m->pix.data(), (size_t)m->P * 4, hipMemcpyHostToDevice, build_stream) != hipSuccess)
                 rc = PAT_EDEVICE;
             if (rc == PAT_OK)
-                rc = pat_eikonal_tables(build_ctx, static_cast<float *>(d_speed), m->nx, m->ny, m->h, m->sxy.data(),
-                                        m->S, static_cast<int32_t *>(d_pix), m->P, table32, build_stream);
+                rc = m->nz > 0 ? pat_eikonal_tables_3d(build_ctx, static_cast<float *>(d_speed), m->nx, m->ny, m->nz, m->h,
+                                                       m->sxy.data(), m->S, static_cast<int32_t *>(d_pix), m->P,
+                                                       table32, build_stream)
+                               : pat_eikonal_tables(build_ctx, static_cast<float *>(d_speed), m->nx, m->ny, m->h,
+                                                    m->sxy.data(), m->S, static_cast<int32_t *>(d_pix), m->P, table32,
+                                                    build_stream);
             if (rc == PAT_OK && cfg.table_fmt == PAT_TABLE_Q16)
                 rc = pat_table_to_q16(build_ctx, table32, (int64_t)m->S * m->P, m->t0, m->dt, m->N,
                                       static_cast<uint32_t *>(d_out), build_stream);
@@ -619,31 +624,36 @@ extern "C" int pat_server_destroy(pat_server *s) {
     return PAT_OK;
 }
 
-extern "C" int pat_server_add_map(pat_server *s, const float *h_speed, int nx, int ny, double h,
-                                  const double *h_sensor_xy, int S, const int32_t *h_pix, int P, double t0, double dt,
-                                  int N, int *map_id) {
+// A 2-D map (nz = 0, sensors [S][2]) or a 3-D map (nz >= 1, sensors [S][3]).
+static int add_map(pat_server *s, const float *h_speed, int nx, int ny, int nz, double h, const double *h_sensor,
+                   int S, const int32_t *h_pix, int P, double t0, double dt, int N, int *map_id) {
     if (!s || !map_id) return pat_fail(PAT_EINVAL, "null argument");
-    if (nx < 2 || ny < 2 || !(h > 0) || S <= 0 || P <= 0 || N < 4 || !(dt > 0) || !std::isfinite(t0))
+    const bool vol = nz > 0;
+    const bool grid_ok = vol ? nx >= 1 && ny >= 1 && (long long)nx * ny * nz >= 2 && (long long)nx * ny * nz <= (1LL << 30)
+                             : nx >= 2 && ny >= 2;
+    if (!grid_ok || !(h > 0) || S <= 0 || P <= 0 || N < 4 || !(dt > 0) || !std::isfinite(t0))
         return pat_fail(PAT_EINVAL, "bad map geometry");
     if (!pat_px_multi_eligible(s->cfg.sig_fmt, S, P, N))
         return pat_fail(PAT_EINVAL, "map too large for the frame server (S*P or S*N beyond 32-bit offsets)");
-    if (!h_speed || !h_sensor_xy || !h_pix) return pat_fail(PAT_EINVAL, "null map data");
+    if (!h_speed || !h_sensor || !h_pix) return pat_fail(PAT_EINVAL, "null map data");
     if (s->cfg.table_fmt != PAT_TABLE_F32 && N > 65535)
         return pat_fail(PAT_EINVAL, "16.16 and 16-bit tables need N <= 65535");
-    const size_t n = (size_t)nx * ny;
+    const size_t n = (size_t)nx * ny * (vol ? nz : 1);
     for (size_t k = 0; k < n; ++k)
         if (!(std::isfinite(h_speed[k]) && h_speed[k] > 0)) return pat_fail(PAT_EINVAL, "speed must be finite and > 0");
     for (int p = 0; p < P; ++p)
         if (h_pix[p] < 0 || (size_t)h_pix[p] >= n) return pat_fail(PAT_EINVAL, "pixel index out of range");
-    const double x0 = -0.5 * (nx - 1) * h, y0 = -0.5 * (ny - 1) * h;
-    for (int i = 0; i < S; ++i) {
-        const double gi = (h_sensor_xy[2 * i] - x0) / h, gj = (h_sensor_xy[2 * i + 1] - y0) / h;
-        if (!(gi >= 0 && gi <= nx - 1 && gj >= 0 && gj <= ny - 1)) return pat_fail(PAT_EINVAL, "sensor outside the grid");
-    }
+    const int dim = vol ? 3 : 2;
+    const int ext[3] = { nx, ny, vol ? nz : 1 };
+    for (int i = 0; i < S; ++i)
+        for (int a = 0; a < dim; ++a) {
+            const double g = (h_sensor[dim * i + a] + 0.5 * (ext[a] - 1) * h) / h;
+            if (!(g >= 0 && g <= ext[a] - 1)) return pat_fail(PAT_EINVAL, "sensor outside the grid");
+        }
     auto m = std::make_unique<Map>();
-    m->nx = nx; m->ny = ny; m->h = h; m->S = S; m->P = P; m->N = N; m->t0 = t0; m->dt = dt;
+    m->nx = nx; m->ny = ny; m->nz = vol ? nz : 0; m->h = h; m->S = S; m->P = P; m->N = N; m->t0 = t0; m->dt = dt;
     m->speed.assign(h_speed, h_speed + n);
-    m->sxy.assign(h_sensor_xy, h_sensor_xy + 2 * (size_t)S);
+    m->sxy.assign(h_sensor, h_sensor + (size_t)dim * S);
     m->pix.assign(h_pix, h_pix + P);
     std::lock_guard<std::mutex> lk(s->mu);
     const size_t resv = s->map_build_bytes(*m);
@@ -659,6 +669,19 @@ extern "C" int pat_server_add_map(pat_server *s, const float *h_speed, int nx, i
     s->maps[m->id] = std::move(m);
     s->cv_build.notify_all();
     return PAT_OK;
+}
+
+extern "C" int pat_server_add_map(pat_server *s, const float *h_speed, int nx, int ny, double h,
+                                  const double *h_sensor_xy, int S, const int32_t *h_pix, int P, double t0, double dt,
+                                  int N, int *map_id) {
+    return add_map(s, h_speed, nx, ny, 0, h, h_sensor_xy, S, h_pix, P, t0, dt, N, map_id);
+}
+
+extern "C" int pat_server_add_map_3d(pat_server *s, const float *h_speed, int nx, int ny, int nz, double h,
+                                     const double *h_sensor_xyz, int S, const int32_t *h_vox, int P, double t0,
+                                     double dt, int N, int *map_id) {
+    if (nz < 1) return pat_fail(PAT_EINVAL, "bad map geometry");
+    return add_map(s, h_speed, nx, ny, nz, h, h_sensor_xyz, S, h_vox, P, t0, dt, N, map_id);
 }
 
 extern "C" int pat_server_map_state(pat_server *s, int map_id, int *state) {

@@ -24,7 +24,7 @@ EXPORTED = [
     "pat_last_error", "pat_version", "pat_ctx_create", "pat_ctx_destroy", "pat_ctx_reserve",
     "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_3d", "pat_eikonal_last_stats", "pat_table_to_q16", "pat_table_to_r16", "pat_table_r16_bytes",
     "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_const", "pat_backproject_const_3d",
-    "pat_server_create", "pat_server_destroy", "pat_server_add_map", "pat_server_map_state",
+    "pat_server_create", "pat_server_destroy", "pat_server_add_map", "pat_server_add_map_3d", "pat_server_map_state",
     "pat_server_remove_map", "pat_server_submit", "pat_server_wait", "pat_server_get_stats",
     "pat_server_reset_stats",
     "pat_server_hold",
@@ -95,6 +95,7 @@ def lib() -> C.CDLL:
         L.pat_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
         L.pat_server_destroy.argtypes = [vp]
         L.pat_server_add_map.argtypes = [vp, vp, i32, i32, dbl, vp, i32, vp, i32, dbl, dbl, i32, C.POINTER(i32)]
+        L.pat_server_add_map_3d.argtypes = [vp, vp, i32, i32, i32, dbl, vp, i32, vp, i32, dbl, dbl, i32, C.POINTER(i32)]
         L.pat_server_map_state.argtypes = [vp, i32, C.POINTER(i32)]
         L.pat_server_remove_map.argtypes = [vp, i32]
         L.pat_server_submit.argtypes = [vp, i32, vp, C.c_float, i32, C.POINTER(C.c_uint64)]
@@ -400,6 +401,21 @@ class Server:
                                        px.ctypes.data, px.shape[0], float(t0), float(dt), int(n_samples),
                                        C.byref(mid)))
         self._geo[mid.value] = (sxy.shape[0], px.shape[0], int(n_samples))
+        return mid.value
+
+    def add_map_3d(self, speed: np.ndarray, h: float, sensors: np.ndarray, vox: np.ndarray, n_samples: int,
+                   dt: float, t0: float = 0.0) -> int:
+        c = np.ascontiguousarray(speed, dtype=np.float32)
+        nz, ny, nx = c.shape
+        sxyz = np.ascontiguousarray(sensors, dtype=np.float64)
+        if sxyz.ndim != 2 or sxyz.shape[1] != 3:
+            raise ValueError("sensors must be [S][3]")
+        px = np.ascontiguousarray(vox, dtype=np.int32)
+        mid = C.c_int()
+        check(lib().pat_server_add_map_3d(self.h, c.ctypes.data, nx, ny, nz, float(h), sxyz.ctypes.data, sxyz.shape[0],
+                                          px.ctypes.data, px.shape[0], float(t0), float(dt), int(n_samples),
+                                          C.byref(mid)))
+        self._geo[mid.value] = (sxyz.shape[0], px.shape[0], int(n_samples))
         return mid.value
 
     def map_state(self, map_id: int) -> int:

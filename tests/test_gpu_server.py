@@ -205,3 +205,37 @@ def test_build_overlaps_frames(ctx, orc):
         srv.remove_map(12345)
     srv.remove_map(a)
     srv.close()
+
+
+def test_server_3d_map(ctx, orc):
+    # a 3-D map in the frame server beside a 2-D one: its table is built by
+    # the 3-D eikonal solver on the build stream, and its frames match the
+    # single-frame launch on the same (GPU) table and the all-oracle pipeline
+    from paper_1501_03869_amd import pat
+    g3 = inputs.config3("head3")
+    sens = g3.sensors[::4]
+    vox = pat.tile_order_3d(g3.nx, g3.ny, g3.nz, g3.pix, 4, 4, 2)
+    g = inputs.Geometry3(g3.name, g3.nx, g3.ny, g3.nz, g3.h, g3.speed, sens, vox, g3.n_samples, g3.dt)
+    T64 = orc.tables3(g3.speed, g3.h, sens, vox)
+    frames = [inputs.frame_for3(g, T64, f) for f in range(3)]
+    g2 = inputs.config("small")
+    srv = pat.Server(ctx, max_batch=8)
+    try:
+        m2 = srv.add_map(g2.speed, g2.h, g2.sensors, g2.pix, g2.n_samples, g2.dt)
+        m3 = srv.add_map_3d(g3.speed, g3.h, sens, vox, g3.n_samples, g3.dt)
+        t2 = srv.submit(m2, inputs.random_signals(5, g2.S, g2.n_samples))
+        imgs = [srv.wait(srv.submit(m3, f), m3, timeout_ms=WAIT_MS) for f in frames]
+        srv.wait(t2, m2, timeout_ms=WAIT_MS)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["builds"] >= 2
+    Tg = ctx.eikonal_tables_3d(torch.from_numpy(g3.speed).cuda(), g3.h, sens, torch.from_numpy(vox).cuda())
+    for f, img in zip(frames, imgs):
+        single = ctx.backproject(Tg, torch.from_numpy(f).cuda(), g3.dt, filtered=False).cpu().numpy()
+        ref = orc.backproject(T64, f, g3.dt)
+        e1 = float(np.linalg.norm(img - single) / np.linalg.norm(single))
+        e2 = float(np.linalg.norm(img - ref) / np.linalg.norm(ref))
+        print(f"[server 3d] rel L2 vs single launch {e1:.3e}, vs oracle pipeline {e2:.3e}", flush=True)
+        assert e1 <= 1e-5
+        assert e2 <= 2e-3
