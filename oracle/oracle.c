@@ -28,6 +28,8 @@
  *      6-neighbour Godunov update (3-D reconstruction, Section IV);
  *      orc_tables_const3: the straight-ray table of the conventional back
  *      projection on the same grid (orc_tables_const is its 2-D form).
+ *   8. orc_fmm2 / orc_tables2: steps 1-2 with the paper's second-order
+ *      one-sided differences (Section II-B), same heap order.
  *   7. orc_table_to_r16 / orc_r16_to_q16: the 16.16 table of item 5 stored as
  *      16-bit offsets from a base per sensor and tile of 32 ROI positions
  *      (a compressed storage form; not in the paper).
@@ -186,6 +188,128 @@ int orc_fmm(int nx, int ny, double h, const double *slow, const unsigned char *f
     return rc;
 }
 
+/* ------------------------------------------------- second-order marching */
+/*
+ * The paper's scheme (Section II-B, after Sethian): the same fast marching,
+ * with the one-sided derivative along an axis taken to second order,
+ * (3 T - 4 T1 + T2) / (2h), where the two upwind nodes T1 (the smaller
+ * accepted neighbour on the axis) and T2 (the node beyond it on the same
+ * side) are both accepted and T2 <= T1; otherwise the first-order (T - T1)/h.
+ * Each axis then contributes c (T - b)^2 to sum = (f h)^2, with c = 9/4,
+ * b = (4 T1 - T2) / 3 (second order) or c = 1, b = T1 (first order).
+ */
+
+/* Upwind term of node m along one axis: neighbours at m - st and m + st
+ * exist when lo / hi; the nodes two away at m -/+ 2 st exist when lo2 / hi2. */
+static int axis_term(const double *T, const unsigned char *state, long m, long st, int lo, int hi, int lo2,
+                     int hi2, int order, double *c, double *b) {
+    double t1 = INFINITY;
+    int side = 0;
+    if (lo && state[m - st] == ORC_KNOWN) { t1 = T[m - st]; side = -1; }
+    if (hi && state[m + st] == ORC_KNOWN && T[m + st] < t1) { t1 = T[m + st]; side = 1; }
+    if (side == 0) return 0;
+    *c = 1.0;
+    *b = t1;
+    if (order == 2) {
+        int ok2 = side < 0 ? lo2 : hi2;
+        long m2 = m + 2 * side * st;
+        if (ok2 && state[m2] == ORC_KNOWN && T[m2] <= t1) {
+            *c = 2.25;
+            *b = (4.0 * t1 - T[m2]) / 3.0;
+        }
+    }
+    return 1;
+}
+
+/* Root of sum over the available axes of c_k (T - b_k)^2 = fh^2: both axes
+ * when the root lies at or above both b_k, else the smaller one-axis root
+ * b_k + fh / sqrt(c_k).  With first-order terms on both axes this is the
+ * first-order update above (computed by it). */
+static double update2(int hx, double cx, double bx, int hy, double cy, double by, double fh) {
+    if (!hx && !hy) return INFINITY;
+    double ix = cx == 1.0 ? fh : fh / 1.5, iy = cy == 1.0 ? fh : fh / 1.5;
+    if (!hy) return bx + ix;
+    if (!hx) return by + iy;
+    if (cx == 1.0 && cy == 1.0) return godunov(bx, by, fh);
+    double m = bx < by ? bx : by;
+    double ex = bx - m, ey = by - m;
+    double A = cx + cy, B = cx * ex + cy * ey, C = cx * ex * ex + cy * ey * ey - fh * fh;
+    double disc = B * B - A * C;
+    if (disc >= 0.0) {
+        double t = (B + sqrt(disc)) / A;
+        if (t >= ex && t >= ey) return m + t;
+    }
+    double tx = bx + ix, ty = by + iy;
+    return tx < ty ? tx : ty;
+}
+
+static double node_update2(const double *T, const unsigned char *state, int nx, int ny, long m, double fh,
+                           int order) {
+    int i = (int)(m % nx), j = (int)(m / nx);
+    double cx = 0, bx = 0, cy = 0, by = 0;
+    int hx = axis_term(T, state, m, 1, i > 0, i < nx - 1, i > 1, i < nx - 2, order, &cx, &bx);
+    int hy = axis_term(T, state, m, nx, j > 0, j < ny - 1, j > 1, j < ny - 2, order, &cy, &by);
+    return update2(hx, cx, bx, hy, cy, by, fh);
+}
+
+/* Fast marching with the update of the given order (1 or 2); otherwise as
+ * orc_fmm (same heap order: the smallest trial time first, ties by index;
+ * a trial value is replaced when a newly accepted neighbour lowers it). */
+int orc_fmm2(int nx, int ny, double h, const double *slow, const unsigned char *frozen, double *T, long *npop,
+             int order) {
+    long n = (long)nx * ny;
+    unsigned char *state = (unsigned char *)calloc((size_t)n, 1);
+    orc_heap hp = { 0, 0, 0 };
+    if (!state) return -1;
+    for (long k = 0; k < n; ++k) {
+        if (frozen[k]) state[k] = ORC_KNOWN;
+        else T[k] = INFINITY;
+    }
+    long pops = 0;
+    int rc = 0;
+    for (long k = 0; k < n; ++k) {
+        if (!frozen[k]) continue;
+        int i = (int)(k % nx), j = (int)(k / nx);
+        const int di[4] = { -1, 1, 0, 0 }, dj[4] = { 0, 0, -1, 1 };
+        for (int q = 0; q < 4; ++q) {
+            int ii = i + di[q], jj = j + dj[q];
+            if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+            long m = (long)jj * nx + ii;
+            if (state[m] != ORC_KNOWN) state[m] = ORC_TRIAL;
+        }
+    }
+    for (long m = 0; m < n && rc == 0; ++m) {
+        if (state[m] != ORC_TRIAL) continue;
+        T[m] = node_update2(T, state, nx, ny, m, slow[m] * h, order);
+        if (heap_push(&hp, T[m], (int32_t)m)) rc = -1;
+    }
+    while (rc == 0 && hp.n > 0) {
+        orc_item it = heap_pop(&hp);
+        long k = it.idx;
+        if (state[k] == ORC_KNOWN || it.key != T[k]) continue; /* stale entry */
+        state[k] = ORC_KNOWN;
+        ++pops;
+        int i = (int)(k % nx), j = (int)(k / nx);
+        const int di[4] = { -1, 1, 0, 0 }, dj[4] = { 0, 0, -1, 1 };
+        for (int q = 0; q < 4; ++q) {
+            int ii = i + di[q], jj = j + dj[q];
+            if (ii < 0 || ii >= nx || jj < 0 || jj >= ny) continue;
+            long m = (long)jj * nx + ii;
+            if (state[m] == ORC_KNOWN) continue;
+            double t = node_update2(T, state, nx, ny, m, slow[m] * h, order);
+            if (t < T[m]) {
+                T[m] = t;
+                state[m] = ORC_TRIAL;
+                if (heap_push(&hp, t, (int32_t)m)) { rc = -1; break; }
+            }
+        }
+    }
+    free(hp.a);
+    free(state);
+    if (npop) *npop = pops;
+    return rc;
+}
+
 /* Point-source initial condition: every node within r0 of the source (sx, sy)
  * is frozen at the straight-ray time |x_k - s| * slow(n*), where n* is the node
  * nearest the source.  Coordinates are grid-centred (node i at
@@ -265,6 +389,62 @@ int orc_tables(int nx, int ny, double h, const float *speed, const double *sxy, 
                 continue;
             }
             if (orc_fmm(nx, ny, h, slow, fr, T, 0)) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+                rc = -2;
+                continue;
+            }
+            for (long p = 0; p < P; ++p) table[(long)s * P + p] = T[pix[p]];
+        }
+        free(T);
+        free(fr);
+    }
+    free(slow);
+    return rc;
+}
+
+/* orc_tables with the second-order marching of orc_fmm2. */
+int orc_tables2(int nx, int ny, double h, const float *speed, const double *sxy, int S,
+               const int32_t *pix, long P, double *table, int nthreads) {
+    long n = (long)nx * ny;
+    for (long p = 0; p < P; ++p)
+        if (pix[p] < 0 || pix[p] >= n) return -1;
+    double *slow = (double *)malloc((size_t)n * sizeof(double));
+    if (!slow) return -2;
+    for (long k = 0; k < n; ++k) {
+        double c = (double)speed[k];
+        if (!(c > 0.0) || isinf(c)) { free(slow); return -1; }
+        slow[k] = 1.0 / c;
+    }
+    int rc = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+    {
+        double *T = (double *)malloc((size_t)n * sizeof(double));
+        unsigned char *fr = (unsigned char *)malloc((size_t)n);
+        if (!T || !fr) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+            rc = -2;
+        }
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int s = 0; s < S; ++s) {
+            if (!T || !fr) continue;
+            int c = orc_seed(nx, ny, h, slow, sxy[2 * s], sxy[2 * s + 1], 2.0 * h, fr, T);
+            if (c < 0) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+                rc = -1;
+                continue;
+            }
+            if (orc_fmm2(nx, ny, h, slow, fr, T, 0, 2)) {
 #ifdef _OPENMP
 #pragma omp atomic write
 #endif

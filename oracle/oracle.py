@@ -51,6 +51,10 @@ def lib():
         L.orc_seed.restype = C.c_int
         L.orc_tables.argtypes = [C.c_int, C.c_int, C.c_double, _fp, _dp, C.c_int, _i32, C.c_long, _dp, C.c_int]
         L.orc_tables.restype = C.c_int
+        L.orc_fmm2.argtypes = [C.c_int, C.c_int, C.c_double, _dp, _u8, _dp, C.POINTER(C.c_long), C.c_int]
+        L.orc_fmm2.restype = C.c_int
+        L.orc_tables2.argtypes = [C.c_int, C.c_int, C.c_double, _fp, _dp, C.c_int, _i32, C.c_long, _dp, C.c_int]
+        L.orc_tables2.restype = C.c_int
         L.orc_tables_const.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, _dp, C.c_int, _i32, C.c_long, _dp]
         L.orc_tables_const.restype = C.c_int
         L.orc_tables_const3.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, _dp, C.c_int, _i32,
@@ -101,6 +105,19 @@ def fmm(slow: np.ndarray, frozen: np.ndarray, T0: np.ndarray, h: float):
     return T, int(pops.value)
 
 
+def fmm2(slow: np.ndarray, frozen: np.ndarray, T0: np.ndarray, h: float, order: int = 2):
+    """Fast marching with the paper's second-order one-sided differences
+    (order=2) or the first-order update (order=1).  Returns (T, pops)."""
+    ny, nx = slow.shape
+    T = np.ascontiguousarray(T0, dtype=np.float64).copy()
+    pops = C.c_long(0)
+    rc = lib().orc_fmm2(nx, ny, float(h), np.ascontiguousarray(slow, dtype=np.float64),
+                        np.ascontiguousarray(frozen, dtype=np.uint8), T, C.byref(pops), int(order))
+    if rc:
+        raise MemoryError("orc_fmm2")
+    return T, int(pops.value)
+
+
 def seed(slow: np.ndarray, h: float, sx: float, sy: float, r0: float | None = None):
     """Point-source initial condition (frozen mask, T with frozen values set)."""
     ny, nx = slow.shape
@@ -134,6 +151,22 @@ def tables(speed: np.ndarray, h: float, sensors: np.ndarray, pix: np.ndarray, nt
         raise ValueError("orc_tables: invalid input")
     if rc:
         raise MemoryError("orc_tables")
+    return out
+
+
+def tables2(speed: np.ndarray, h: float, sensors: np.ndarray, pix: np.ndarray, nthreads: int = 0) -> np.ndarray:
+    """Delay table T[S][P] from the second-order fast marching (orc_fmm2)."""
+    speed = np.ascontiguousarray(speed, dtype=np.float32)
+    ny, nx = speed.shape
+    sxy = np.ascontiguousarray(sensors, dtype=np.float64)
+    pix = np.ascontiguousarray(pix, dtype=np.int32)
+    S, P = sxy.shape[0], pix.shape[0]
+    out = np.empty((S, P), dtype=np.float64)
+    rc = lib().orc_tables2(nx, ny, float(h), speed, sxy, S, pix, P, out, int(nthreads))
+    if rc == -1:
+        raise ValueError("orc_tables2: invalid input")
+    if rc:
+        raise MemoryError("orc_tables2")
     return out
 
 
