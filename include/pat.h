@@ -124,6 +124,25 @@ int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, int ny, doubl
                        float *d_table, void *stream);
 
 /*
+ * Delay tables with the paper's second-order scheme (Section II-B): the fast
+ * marching method itself, with the second-order one-sided difference
+ * (3T - 4T1 + T2)/(2h) along an axis where both upwind nodes are accepted and
+ * T2 <= T1 (else the first-order difference), the nodes accepted in heap
+ * order (smallest trial time first, ties by node index).  Each axis adds
+ * c (T - b)^2 to sum = (h/c_node)^2, c = 9/4 and b = (4 T1 - T2)/3 (second
+ * order) or c = 1 and b = T1; both axes are used when the root lies at or
+ * above both b, else the smaller one-axis root.  Computed in FP64 per map
+ * (one map per wave, the marching itself sequential), so the times equal the
+ * definition's; rounded once to float32 seconds.  Arguments, seeding and
+ * errors as pat_eikonal_tables (grid up to 2^28 nodes); memory
+ * about 69 bytes per node per map in flight (maps in chunks of 8 GiB).
+ * Synchronises `stream`.
+ */
+int pat_eikonal_tables_o2(pat_ctx *ctx, const float *d_speed, int nx, int ny, double h,
+                          const double *h_sensor_xy, int S, const int32_t *d_pix, int P,
+                          float *d_table, void *stream);
+
+/*
  * 3-D delay tables (3-D reconstruction, anticipated in Section IV): the same
  * first-order upwind scheme on a 6-neighbour grid, each node updated from the
  * upwind minima along x, y and z (one-, two- or three-sided root, whichever

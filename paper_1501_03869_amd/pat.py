@@ -22,7 +22,7 @@ SIG_F32, SIG_F16 = 0, 1
 
 EXPORTED = [
     "pat_last_error", "pat_version", "pat_ctx_create", "pat_ctx_destroy", "pat_ctx_reserve",
-    "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_3d", "pat_eikonal_last_stats", "pat_table_to_q16", "pat_table_to_r16", "pat_table_r16_bytes",
+    "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_o2", "pat_eikonal_tables_3d", "pat_eikonal_last_stats", "pat_table_to_q16", "pat_table_to_r16", "pat_table_r16_bytes",
     "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_const", "pat_backproject_const_3d",
     "pat_server_create", "pat_server_destroy", "pat_server_add_map", "pat_server_add_map_3d", "pat_server_map_state",
     "pat_server_remove_map", "pat_server_submit", "pat_server_wait", "pat_server_get_stats",
@@ -78,6 +78,7 @@ def lib() -> C.CDLL:
         L.pat_backproject_scratch_bytes.argtypes = [i32, i32, i32]
         L.pat_backproject_scratch_bytes.restype = sz
         L.pat_eikonal_tables.argtypes = [vp, vp, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
+        L.pat_eikonal_tables_o2.argtypes = [vp, vp, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
         L.pat_eikonal_tables_3d.argtypes = [vp, vp, i32, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
         L.pat_eikonal_last_stats.argtypes = [vp, C.POINTER(EikonalStats)]
         L.pat_table_to_q16.argtypes = [vp, vp, i64, dbl, dbl, i32, vp, vp]
@@ -175,6 +176,23 @@ class Context:
         _need(table, torch.float32, "table")
         check(lib().pat_eikonal_tables(self.h, _ptr(speed), nx, ny, float(h), sxy.ctypes.data, S, _ptr(pix), P,
                                        _ptr(table), _stream(stream)))
+        return table
+
+    def eikonal_tables_o2(self, speed, h: float, sensors: np.ndarray, pix, table=None, stream=None):
+        """Second-order fast-marching tables (the paper's scheme); arguments as eikonal_tables."""
+        import torch
+        _need(speed, torch.float32, "speed")
+        _need(pix, torch.int32, "pix")
+        ny, nx = speed.shape
+        sxy = np.ascontiguousarray(sensors, dtype=np.float64)
+        if sxy.ndim != 2 or sxy.shape[1] != 2:
+            raise ValueError("sensors must be [S][2]")
+        S, P = sxy.shape[0], pix.shape[0]
+        if table is None:
+            table = torch.empty((S, P), dtype=torch.float32, device=speed.device)
+        _need(table, torch.float32, "table")
+        check(lib().pat_eikonal_tables_o2(self.h, _ptr(speed), nx, ny, float(h), sxy.ctypes.data, S, _ptr(pix), P,
+                                          _ptr(table), _stream(stream)))
         return table
 
     def eikonal_tables_3d(self, speed, h: float, sensors: np.ndarray, vox, table=None, stream=None):
