@@ -319,7 +319,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               f"(frame-parallel sharding across GPUs needs no exchange and is described in the design notes).",
               file=sys.stderr)
         sys.exit(2)
