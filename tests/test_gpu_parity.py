@@ -126,12 +126,22 @@ def test_eikonal_rejects_bad_input(ctx):
 
 # ----------------------------------------------------------------------------- filter
 
-def test_filter_matches_oracle(ctx, orc):
-    rng = np.random.default_rng(1)
-    p = rng.normal(size=(37, 1001)).astype(np.float32)
+@pytest.mark.parametrize("rows,N,shift", [(37, 1001, 0), (64, 2048, 0), (5, 2500, 0), (3, 4, 0), (2, 2, 0),
+                                          (9, 1028, 1), (1, 4096, 0)])
+def test_filter_matches_oracle(ctx, orc, rows, N, shift):
+    # N % 4 == 0 on a 16-byte aligned buffer takes the vector loads; shift
+    # moves the rows off that alignment; N > 1024 spans several workgroups
+    # per row with a ragged last one
+    rng = np.random.default_rng(rows * N)
+    p = rng.normal(size=(rows, N)).astype(np.float32)
+    buf = torch.zeros(rows * N + shift, dtype=torch.float32, device="cuda")
+    buf[shift:] = dev(p.reshape(-1))
+    src = buf[shift:].view(rows, N)
+    out = torch.full((rows * N + shift,), float("nan"), device="cuda")
     for t0 in (0.0, 3.3e-7):
-        got = ctx.filter(dev(p), 4e-8, t0).cpu().numpy()
-        ref = orc.filt(p, 4e-8, t0)
+        got = ctx.filter(src, 4e-8, t0, out=out[shift:].view(rows, N)).cpu().numpy()
+        ref = orc.filt(p.astype(np.float64), 4e-8, t0)
+        assert np.isfinite(got).all()
         assert rel_l2(got, ref) < 1e-6
         assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
 
