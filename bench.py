@@ -49,12 +49,12 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 of the files below; any change makes the field null until the
 # counters are taken again.  Summaries: profiles/k_bp_px_*_hbm_counters.md.
 TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_common.h")
-TRAFFIC_SHA = "a7c5d8a4f11fada67cf232a267ec4831f38708223116ff39eb5ea759cc5cf140:" \
+TRAFFIC_SHA = "23acbfc72afce42308df583f7ad04c84839c7eef0206a267e00ed9699920bb43:" \
               "046afad2d9d976f56fb21100e0e5c9f9620cda616a8d09c45b88ba79e760cfe7"
 FETCH_FACTOR = 250000.0 / 125012.32
 WRITE_FACTOR = 1.0
-TRAFFIC_KIB = {"paper": (25130.78, 83.53), "large": (1823352.67, 3274.95),
-               "head3": (24634.96, 174.70)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+TRAFFIC_KIB = {"paper": (25125.24, 83.53), "large": (1822683.16, 3274.77),
+               "head3": (24621.56, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 
 
 def measured_traffic(config: str):

@@ -139,8 +139,8 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     // record the step may touch, so per-lane offsets stay below 2*U records
     // however large the table is.  Signal records start on a dword for FP32;
     // for FP16 the base is rounded down to a dword and sample offsets count
-    // from there (res = 0 or 1 sample).  Every load reads only dwords that
-    // hold at least one wanted value.
+    // from there (res = 0 or 1 sample), and the fast path's loads start on the
+    // dword holding the first wanted sample.
     const uint32_t toff = ((uint32_t)(half * P) + (uint32_t)pc) * 4u;
     auto step_s0 = [&](int i) { return min(sw + 2 * i * PX_U, se - 1); };
     auto tab_rsrc = [&](int s0) {
@@ -160,16 +160,19 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     };
     auto sig_rsrc = [&](int s0) {
         const uintptr_t a = reinterpret_cast<uintptr_t>(J.sig) + (size_t)s0 * N * esz;
+        const uint32_t n = (uint32_t)min(2 * PX_U, S - s0) * (uint32_t)N;
         SigRsrc g;
         g.res = (uint32_t)(a & 3u) / esz;
-        const uint32_t n = (uint32_t)min(2 * PX_U, S - s0) * (uint32_t)N;
         g.r = rsrc(reinterpret_cast<const void *>(a & ~(uintptr_t)3), ((g.res + n) * esz + 3u) & ~3u);
         return g;
     };
 
     // q[0..3] = x[c .. c+3] of record r = 2j + half of the step.  FP16: the
-    // raw dwords and the start's parity are kept, and the samples are cut out
-    // (unscaled) only when they are summed, so nothing waits for the load here.
+    // three dwords from the one holding c, and the byte shift of c inside the
+    // first (0 or 2) in q[3]; the samples are cut out (unscaled) only when
+    // they are summed, so nothing waits for the load here.  The third dword
+    // may hold no wanted sample: the fast range ends a sample early for FP16
+    // so that it still lies in the record.
     auto load4 = [&](const SigRsrc &g, int j, int c, float (&q)[4]) {
         if constexpr (SFMT == PAT_SIG_F32) {
             const auto v = __builtin_amdgcn_raw_buffer_load_b128(g.r, 4u * ((uint32_t)(half * N) + (uint32_t)c),
@@ -177,17 +180,12 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             q[0] = __uint_as_float(v[0]); q[1] = __uint_as_float(v[1]);
             q[2] = __uint_as_float(v[2]); q[3] = __uint_as_float(v[3]);
         } else {
-            // two dwords from the even sample at or below c, and for an odd
-            // start the dword holding c+3 (else the first one again)
             const uint32_t h = g.res + (uint32_t)((2 * j + half) * N + c);
-            const bool odd = h & 1u;
-            const uint32_t e = 2u * (h & ~1u);
-            const auto d = __builtin_amdgcn_raw_buffer_load_b64(g.r, e, 0, 0);
-            const uint32_t d2 = __builtin_amdgcn_raw_buffer_load_b32(g.r, odd ? e + 8u : e, 0, 0);
-            q[0] = __uint_as_float(d[0]);
-            q[1] = __uint_as_float(d[1]);
-            q[2] = __uint_as_float(d2);
-            q[3] = odd ? 1.0f : 0.0f;
+            const auto v = __builtin_amdgcn_raw_buffer_load_b96(g.r, 2u * (h & ~1u), 0, 0);
+            q[0] = __uint_as_float(v[0]);
+            q[1] = __uint_as_float(v[1]);
+            q[2] = __uint_as_float(v[2]);
+            q[3] = __uint_as_float((h & 1u) * 2u);
         }
     };
     // the four samples of a stage slot as floats (FP16: unscaled)
@@ -195,17 +193,16 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         if constexpr (SFMT == PAT_SIG_F32) {
             p[0] = q[0]; p[1] = q[1]; p[2] = q[2]; p[3] = q[3];
         } else {
-            const bool odd = q[3] != 0.0f;
             const uint32_t d0 = __float_as_uint(q[0]), d1 = __float_as_uint(q[1]), d2 = __float_as_uint(q[2]);
-            const uint32_t e0 = odd ? __builtin_amdgcn_alignbyte(d1, d0, 2) : d0;
-            const uint32_t e1 = odd ? __builtin_amdgcn_alignbyte(d2, d1, 2) : d1;
+            const uint32_t sh = __float_as_uint(q[3]);
+            const uint32_t e0 = __builtin_amdgcn_alignbyte(d1, d0, sh), e1 = __builtin_amdgcn_alignbyte(d2, d1, sh);
             p[0] = h2f(e0 & 0xFFFFu); p[1] = h2f(e0 >> 16);
             p[2] = h2f(e1 & 0xFFFFu); p[3] = h2f(e1 >> 16);
         }
     };
     // b[n], b[n+1] of record 2j + half of the step (filtered input; n <= N-2)
-    // into q[1], q[2]; FP16: the dword holding n, the one holding n+1 (for
-    // odd n) and the parity, cut out when summed
+    // into q[1], q[2]; FP16: the two dwords from the one holding n and the
+    // byte shift of n in q[3], cut out when summed
     auto load2 = [&](const SigRsrc &g, int j, int n, float (&q)[4]) {
         if constexpr (SFMT == PAT_SIG_F32) {
             const auto v = __builtin_amdgcn_raw_buffer_load_b64(g.r, 4u * ((uint32_t)(half * N) + (uint32_t)n),
@@ -214,11 +211,10 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             q[2] = __uint_as_float(v[1]);
         } else {
             const uint32_t h = g.res + (uint32_t)((2 * j + half) * N + n);
-            const bool odd = h & 1u;
-            const uint32_t e = 2u * (h & ~1u);
-            q[1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(g.r, e, 0, 0));
-            q[2] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(g.r, odd ? e + 4u : e, 0, 0));
-            q[3] = odd ? 1.0f : 0.0f;
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(g.r, 2u * (h & ~1u), 0, 0);
+            q[1] = __uint_as_float(v[0]);
+            q[2] = __uint_as_float(v[1]);
+            q[3] = __uint_as_float((h & 1u) * 2u);
         }
     };
     auto pair = [&](const float (&q)[4], float &b0, float &b1) {
@@ -226,8 +222,8 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             b0 = q[1];
             b1 = q[2];
         } else {
-            const uint32_t d0 = __float_as_uint(q[1]), d1 = __float_as_uint(q[2]);
-            const uint32_t e = q[3] != 0.0f ? __builtin_amdgcn_alignbyte(d1, d0, 2) : d0;
+            const uint32_t e = __builtin_amdgcn_alignbyte(__float_as_uint(q[2]), __float_as_uint(q[1]),
+                                                          __float_as_uint(q[3]));
             b0 = h2f(e & 0xFFFFu);
             b1 = h2f(e >> 16);
         }
@@ -291,10 +287,15 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     // (filtered input) are inside the record and the delay contributes.  The
     // sample index is clamped into the fast range for every lane, which makes
     // the first tap n-1 (or n) clipped to [0, N-4] (or [0, N-2]), the start
-    // the general path expects, so both paths read the same loads.
+    // the general path expects, so both paths read the same FP32 loads (FP16:
+    // the general path reads its samples again).
     const float t0h = 0.5f * t0dt;
     constexpr int LO = FILTERED ? 0 : 1;
-    const int HI = FILTERED ? N - 1 : N - 2;
+    // FP16 loads start on a dword and read up to two samples past the last
+    // tap: the fast range ends one sample earlier so that they stay in the
+    // record
+    constexpr bool F16 = SFMT == PAT_SIG_F16;
+    const int HI = (FILTERED ? N - 1 : N - 2) - (F16 ? 1 : 0);
     // F32 decoding: the offset -t0/dt in a vector register, so the decode's
     // FMA reads only one scalar operand
     Delay dv = dec;
@@ -367,12 +368,33 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
                 w1 *= J.w[min(sb, S - 1)];
             }
             const float w = dok ? (half ? w1 : w0) : 0.0f;
+            // FP16 loads were clamped to the shorter fast range: read the
+            // samples again at this path's own start (one unaligned load; buffer
+            // accesses take any byte address in the unaligned access mode the
+            // driver sets on this GPU)
+            float qs[4] = {st.q[j][0], st.q[j][1], st.q[j][2], st.q[j][3]};
+            if constexpr (F16) {
+                const SigRsrc g = sig_rsrc(step_s0(i));
+                const uint32_t r = g.res + (uint32_t)((2 * j + half) * N);
+                if constexpr (FILTERED) {
+                    qs[1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(g.r, 2u * (r + (uint32_t)n), 0, 0));
+                    qs[2] = 0.0f;
+                    qs[3] = 0.0f;
+                } else {
+                    const uint32_t c = (uint32_t)min(max(n - 1, 0), N - 4);
+                    const auto v = __builtin_amdgcn_raw_buffer_load_b64(g.r, 2u * (r + c), 0, 0);
+                    qs[0] = __uint_as_float(v[0]);
+                    qs[1] = __uint_as_float(v[1]);
+                    qs[2] = 0.0f;
+                    qs[3] = 0.0f;
+                }
+            }
             float b0, b1;
             if constexpr (FILTERED) {
-                pair(st.q[j], b0, b1);
+                pair(qs, b0, b1);
             } else {
                 float q[4];
-                taps(st.q[j], q);
+                taps(qs, q);
                 // q = p[c .. c+3] with c = n-1 clipped to [0, N-4]
                 const int sh = (n - 1) - min(max(n - 1, 0), N - 4);  // -1 at n = 0, +1 at n = N-2
                 const float pm = sh == 1 ? q[1] : q[0];

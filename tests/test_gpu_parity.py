@@ -253,6 +253,40 @@ def test_backproject_fast_range_boundaries(ctx, orc, sig, filtered):
     assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("filtered", [False, True])
+@pytest.mark.parametrize("shift", [0, 1])
+def test_backproject_f16_record_end(ctx, orc, filtered, shift):
+    # FP16 samples are read from the dword holding the first one, up to two
+    # samples past the last tap, so the fast range ends a sample early.  Here
+    # whole 32-pixel tiles of every sensor, the frame's last included, sit at
+    # the end of that range (u in [N-5, N-3)) or just past it (u in
+    # [N-3, N-1]), where the other path takes over, with both parities of the
+    # first sample; shift = 1 starts the frame half a dword into its buffer.
+    dt, S, P, N = 2.0 ** -24, 24, 32 * 40, 64
+    rng = np.random.default_rng(41 + shift)
+    u = rng.uniform(2.0, N - 6.0, size=(S, P))
+    for t, (lo, hi) in enumerate([(N - 5.0, N - 3.0), (N - 4.0, N - 3.0), (N - 3.0, N - 1.0), (N - 2.0, N - 1.0)]):
+        u[:, 32 * (2 * t + 1):32 * (2 * t + 2)] = rng.uniform(lo, hi, size=(S, 32))
+    u[:, 32 * 9] = N - 3.0
+    u[:, 32 * 9 + 1] = np.nextafter(np.float32(N - 3), np.float32(0.0))
+    u[:, 32 * 9 + 2] = N - 1.0
+    T = (u * dt).astype(np.float32)
+    p = inputs.random_signals(42, S, N, 2)  # two frames: the split-sensor kernel at this small shape
+    scale, h, vals = _fp16_frames(p)
+    buf = torch.zeros(2 * S * N + shift, dtype=torch.float16, device="cuda")
+    buf[shift:] = dev(h.reshape(-1))
+    src = buf[shift:].view(2, S, N)
+    assert src.data_ptr() % 4 == 2 * shift
+    got = ctx.backproject(dev(T), src, dt, filtered=filtered, frame_scale=dev(scale)).cpu().numpy()
+    for f in range(2):
+        b = vals[f] if filtered else orc.filt(vals[f], dt)
+        ref = orc.gather(T.astype(np.float64), b, dt)
+        print(f"[parity] f16 record end filtered={filtered} shift={shift} frame {f} rel L2 "
+              f"{rel_l2(got[f], ref):.2e}", flush=True)
+        assert rel_l2(got[f], ref) <= IMG_TOL
+        assert np.max(np.abs(got[f] - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
 def test_backproject_empty_and_deterministic(ctx, orc):
     z = torch.zeros((0, 10), dtype=torch.float32, device="cuda")
     out = torch.full((10,), float("nan"), device="cuda")
