@@ -49,12 +49,12 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 of the files below; any change makes the field null until the
 # counters are taken again.  Summaries: profiles/k_bp_px_*_hbm_counters.md.
 TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_common.h")
-TRAFFIC_SHA = "23acbfc72afce42308df583f7ad04c84839c7eef0206a267e00ed9699920bb43:" \
+TRAFFIC_SHA = "4552aa90f5f8ee786b732b2ae68615271ed06d22072a30149b1859a4c80804c6:" \
               "046afad2d9d976f56fb21100e0e5c9f9620cda616a8d09c45b88ba79e760cfe7"
 FETCH_FACTOR = 250000.0 / 125012.32
 WRITE_FACTOR = 1.0
-TRAFFIC_KIB = {"paper": (25125.24, 83.53), "large": (1822683.16, 3274.77),
-               "head3": (24621.56, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+TRAFFIC_KIB = {"paper": (25133.93, 83.46), "large": (1839643.75, 3275.14),
+               "head3": (24579.54, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 
 
 def measured_traffic(config: str):

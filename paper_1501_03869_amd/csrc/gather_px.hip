@@ -111,11 +111,14 @@ struct PxJob {
 
 // One pipeline stage: the delays of U sensors of this lane's slot as loaded
 // (d, overwritten by the loads two steps ahead) and as decoded for the sum
-// (raw bits e for the general path, interpolation weight a and filter factor
-// k for the fast path), and their samples.
+// (x: the sample position u for FP32 tables, as bits, or the 16.16 index;
+// nf: for FP32 tables the sample index n clamped into the fast range, as a
+// float), and their samples.  The fast path's interpolation weight and filter factor follow
+// from x and nf when the step is summed, and the general path decodes x
+// again; one register per slot less than keeping them.
 struct Stage {
-    uint32_t d[PX_U], h[PX_U], e[PX_U];  // h: 16-bit tables' tile headers
-    float k[PX_U], a[PX_U], q[PX_U][4];
+    uint32_t d[PX_U], h[PX_U], x[PX_U];  // h: 16-bit tables' tile headers
+    float nf[PX_U], q[PX_U][4];
 };
 
 // The sensors of wave wv for pixel tile*32 + lane%32: the wave owns sensors
@@ -132,7 +135,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     const int pc = min(p, P - 1);  // lanes past the end read a valid column and add nothing
     const int sw = wv * 2 * sps;
     const int se = min(S, sw + 2 * sps);  // end of this wave's sensors
-    const int nstep = (sps + PX_U - 1) / PX_U;
+    const int nstep = (se - sw + 2 * PX_U - 1) / (2 * PX_U);  // steps of this wave (the last may hold fewer sensors)
     constexpr uint32_t esz = SFMT == PAT_SIG_F16 ? 2 : 4;
     // Step i covers sensors s0 + 2j + half (j < U) with s0 = sw + 2*i*U.  Its
     // descriptors start at record s0 (scalar registers) and end at the last
@@ -299,7 +302,8 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     // F32 decoding: the offset -t0/dt in a vector register, so the decode's
     // FMA reads only one scalar operand
     Delay dv = dec;
-    if constexpr (std::is_same<Delay, DelayF32>::value) {
+    constexpr bool kF32T = std::is_same<Delay, DelayF32>::value;
+    if constexpr (kF32T) {
         float offv;
         asm("v_mov_b32 %0, %1" : "=v"(offv) : "s"(dec.off));
         dv.off = offv;
@@ -314,9 +318,12 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             uint32_t dq = st.d[j];
             if constexpr (Delay::kR16) dq = DelayR16::to_q16(st.d[j], st.h[j]);
             slow |= __builtin_amdgcn_ballot_w64(!dv.decode_in(dq, LO, HI, n, a));
-            st.e[j] = dq;
-            st.a[j] = a;
-            st.k[j] = fmaf((float)n, 0.5f, t0h);  // (n + t0/dt) / 2
+            if constexpr (kF32T) {
+                st.x[j] = __float_as_uint(dv.u1(__uint_as_float(dq)));
+                st.nf[j] = (float)n;
+            } else {
+                st.x[j] = dq;
+            }
             // lo <= n <= hi-1: the first tap n-1 (raw) or n (filtered) is the
             // same clipped start the general path assumes
             if constexpr (FILTERED) {
@@ -336,16 +343,22 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             // b[m] = p[m] - (m + t0/dt) * (p[m+1] - p[m-1]) / 2
 #pragma unroll
             for (int j = 0; j < PX_U; ++j) {
+                // in the fast range u is unclamped, so a = u - n
+                const float a = kF32T ? __uint_as_float(st.x[j]) - st.nf[j]
+                                      : (float)(st.x[j] & 0xFFFFu) * (1.0f / 65536.0f);
                 float b0, b1;
                 if constexpr (FILTERED) {
                     pair(st.q[j], b0, b1);
                 } else {
                     float q[4];
                     taps(st.q[j], q);
-                    b0 = fmaf(-st.k[j], q[2] - q[0], q[1]);
-                    b1 = fmaf(-(st.k[j] + 0.5f), q[3] - q[1], q[2]);
+                    // 16.16 index: n is its integer part in the fast range
+                    const float nf = kF32T ? st.nf[j] : (float)(st.x[j] >> 16);
+                    const float k = fmaf(nf, 0.5f, t0h);  // (n + t0/dt) / 2
+                    b0 = fmaf(-k, q[2] - q[0], q[1]);
+                    b1 = fmaf(-(k + 0.5f), q[3] - q[1], q[2]);
                 }
-                const float v = fmaf(st.a[j], b1 - b0, b0);
+                const float v = fmaf(a, b1 - b0, b0);
                 if constexpr (HAS_W) {
                     acc = fmaf(half ? J.w[s0 + 2 * j + 1] : J.w[s0 + 2 * j], v, acc);
                 } else {
@@ -360,7 +373,16 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
         for (int j = 0; j < PX_U; ++j) {
             int n = 0;
             float a = 0.0f;
-            const bool dok = dv.decode_bf1(st.e[j], N, n, a);  // 0 <= n <= N-2
+            bool dok;  // 0 <= n <= N-2
+            if constexpr (kF32T) {
+                const float u = __uint_as_float(st.x[j]);
+                dok = u >= 0.0f && u <= dv.umax;  // also rejects NaN and inf
+                const float uc = dok ? u : 0.0f;
+                n = min((int)uc, N - 2);
+                a = uc - (float)n;
+            } else {
+                dok = dv.decode_bf1(st.x[j], N, n, a);
+            }
             const int sa = s0 + 2 * j, sb = sa + 1;
             float w0 = sa < se ? 1.0f : 0.0f, w1 = sb < se ? 1.0f : 0.0f;
             if constexpr (HAS_W) {
