@@ -7,8 +7,9 @@
 // relaxation is guaranteed to reach the heap-ordered result; the order of
 // acceptance is part of the answer.  Each map therefore runs the marching
 // itself, in heap order (smallest trial time first, ties by node index),
-// on one wave: one lane pops, accepts and updates, with the map's times,
-// states and heap in device memory, and the maps of a chunk run side by side.
+// on one wave: one lane pops, accepts and updates, with the map's times and
+// states in device memory, the top of its heap in LDS and the rest of the
+// heap in device memory, and the maps of a chunk run side by side.
 // The arithmetic is the definition's, in FP64 without contraction, so the
 // times equal the oracle's.
 #include <hip/hip_runtime.h>
@@ -44,8 +45,9 @@ __device__ double godunov1(double a, double b, double fh) {
 }
 
 // Upwind term along one axis: c = 1, b = T1, or c = 9/4, b = (4 T1 - T2)/3.
-__device__ int axis_term(const double *T, const unsigned char *st, long m, long step, bool lo, bool hi, bool lo2,
-                         bool hi2, double &c, double &b) {
+template <class State>
+__device__ int axis_term(const double *T, const State *st, long m, long step, bool lo, bool hi, bool lo2, bool hi2,
+                         double &c, double &b) {
     double t1 = INFINITY;
     int side = 0;
     if (lo && st[m - step] == ST_KNOWN) { t1 = T[m - step]; side = -1; }
@@ -80,56 +82,103 @@ __device__ double update2(int hx, double cx, double bx, int hy, double cy, doubl
     return tx < ty ? tx : ty;
 }
 
-__device__ double node_update(const double *T, const unsigned char *st, const Map2 &g, long m, double fh) {
-    const int i = (int)(m % g.nx), j = (int)(m / g.nx);
+// The update of node (i, j), stored at m of arrays whose rows are `row`
+// apart (the map itself, or a snapshot of a neighbourhood).
+template <class State>
+__device__ double node_update_at(const double *T, const State *st, long m, long row, int i, int j, const Map2 &g,
+                                 double fh) {
     double cx = 0, bx = 0, cy = 0, by = 0;
     const int hx = axis_term(T, st, m, 1, i > 0, i < g.nx - 1, i > 1, i < g.nx - 2, cx, bx);
-    const int hy = axis_term(T, st, m, g.nx, j > 0, j < g.ny - 1, j > 1, j < g.ny - 2, cy, by);
+    const int hy = axis_term(T, st, m, row, j > 0, j < g.ny - 1, j > 1, j < g.ny - 2, cy, by);
     return update2(hx, cx, bx, hy, cy, by, fh);
 }
 
-// Binary min-heap of (key, index), ordered by key then index.
+__device__ double node_update(const double *T, const unsigned char *st, const Map2 &g, long m, double fh) {
+    return node_update_at(T, st, m, g.nx, (int)(m % g.nx), (int)(m / g.nx), g, fh);
+}
+
+// Binary min-heap of (key, index), ordered by key then index (a strict total
+// order: a node is pushed again only with a smaller key).  The first
+// FMM2_LDS_HEAP entries (the top levels, where every push and pop walks) live
+// in the workgroup's LDS and the rest in device memory.  Only lane 0 runs the
+// heap, so its positions are made wave-uniform and the choice between the
+// two memories is a scalar branch; pushes and pops move a hole and write the
+// moving entry once.
+constexpr int FMM2_LDS_HEAP = 4096;
+
 struct Heap {
-    double *key;
+    double *key;  // device memory, entries >= FMM2_LDS_HEAP
     int *idx;
-    long n, cap;
-    __device__ bool less(long a, long b) const {
-        return key[a] < key[b] || (key[a] == key[b] && idx[a] < idx[b]);
+    double *lkey;  // LDS, entries < FMM2_LDS_HEAP
+    int *lidx;
+    int n, cap;
+    __device__ static int u(int a) { return __builtin_amdgcn_readfirstlane(a); }
+    __device__ void get(int a, double &k, int &i) const {
+        a = u(a);
+        if (a < FMM2_LDS_HEAP) {
+            k = lkey[a];
+            i = lidx[a];
+        } else {
+            k = key[a];
+            i = idx[a];
+        }
     }
-    __device__ void swap(long a, long b) {
-        const double k = key[a]; key[a] = key[b]; key[b] = k;
-        const int t = idx[a]; idx[a] = idx[b]; idx[b] = t;
+    __device__ void set(int a, double k, int i) {
+        a = u(a);
+        if (a < FMM2_LDS_HEAP) {
+            lkey[a] = k;
+            lidx[a] = i;
+        } else {
+            key[a] = k;
+            idx[a] = i;
+        }
     }
+    __device__ static bool lt(double ka, int ia, double kb, int ib) { return ka < kb || (ka == kb && ia < ib); }
     __device__ bool push(double k, int i) {
         if (n >= cap) return false;
-        long c = n++;
-        key[c] = k;
-        idx[c] = i;
+        int c = u(n++);
         while (c > 0) {
-            const long p = (c - 1) / 2;
-            if (!less(c, p)) break;
-            swap(c, p);
+            const int p = (c - 1) / 2;
+            double kp;
+            int ip;
+            get(p, kp, ip);
+            if (!lt(k, i, kp, ip)) break;
+            set(c, kp, ip);
             c = p;
         }
+        set(c, k, i);
         return true;
     }
     __device__ void pop(double &k, int &i) {
-        k = key[0];
-        i = idx[0];
+        get(0, k, i);
         --n;
         if (n == 0) return;
-        key[0] = key[n];
-        idx[0] = idx[n];
-        long c = 0;
+        double kl;
+        int il;
+        get(n, kl, il);
+        int c = 0;
         for (;;) {
-            const long l = 2 * c + 1, r = l + 1;
-            long s = c;
-            if (l < n && less(l, s)) s = l;
-            if (r < n && less(r, s)) s = r;
-            if (s == c) break;
-            swap(c, s);
+            const int l = 2 * c + 1;
+            if (l >= n) break;
+            double ks;
+            int is;
+            get(l, ks, is);
+            int s = l;
+            if (l + 1 < n) {
+                double kr;
+                int ir;
+                get(l + 1, kr, ir);
+                if (lt(kr, ir, ks, is)) {
+                    s = l + 1;
+                    ks = kr;
+                    is = ir;
+                }
+            }
+            if (!lt(ks, is, kl, il)) break;
+            set(c, ks, is);
             c = s;
         }
+        set(c, kl, il);
     }
 };
 
@@ -143,6 +192,8 @@ __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Ma
                                              const double *__restrict__ frozen_val, const int *__restrict__ frozen_off,
                                              const int32_t *__restrict__ pix, int P, float *__restrict__ table,
                                              int *__restrict__ err) {
+    __shared__ double s_hkey[FMM2_LDS_HEAP];
+    __shared__ int s_hidx[FMM2_LDS_HEAP];
     const int m = blockIdx.x;
     double *T = T_all + (long)m * g.n;
     unsigned char *st = st_all + (long)m * g.n;
@@ -157,10 +208,10 @@ __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Ma
         st[frozen_idx[q]] = ST_KNOWN;
     }
     __syncthreads();
+    Heap hp{ hkey_all + (long)m * g.heap_cap, hidx_all + (long)m * g.heap_cap, s_hkey, s_hidx, 0, (int)g.heap_cap };
+    int bad = 0;  // lane 0's
+    const int di[4] = { -1, 1, 0, 0 }, dj[4] = { 0, 0, -1, 1 };
     if (threadIdx.x == 0) {
-        Heap hp{ hkey_all + (long)m * g.heap_cap, hidx_all + (long)m * g.heap_cap, 0, g.heap_cap };
-        int bad = 0;
-        const int di[4] = { -1, 1, 0, 0 }, dj[4] = { 0, 0, -1, 1 };
         // initial band: non-frozen neighbours of frozen nodes, valued in index order
         int band[256];
         int nb = 0;
@@ -187,32 +238,91 @@ __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Ma
             T[mm] = node_update(T, st, g, mm, fh);
             if (!hp.push(T[mm], (int)mm)) bad = 1;
         }
-        const long max_steps = 6 * g.n + 64;
-        long steps = 0;
-        while (!bad && hp.n > 0) {
-            if (++steps > max_steps) { bad = 2; break; }
-            double key;
-            int k;
-            hp.pop(key, k);
-            if (st[k] == ST_KNOWN || key != T[k]) continue;  // a stale entry
+    }
+    __threadfence_block();
+    __syncthreads();
+    // Marching.  Lane 0 pops; an update reads only accepted nodes, and none
+    // is accepted during a pop's four updates, so they all read one snapshot:
+    // the 7 x 7 neighbourhood of the popped node k (every node the four
+    // neighbours' stencils reach) taken after k is accepted.  49 lanes load
+    // it and 4 more the neighbours' slowness in one round trip, 4 lanes
+    // compute the updates, and lane 0 applies them in neighbour order.
+    __shared__ double s_T[49], s_key, s_t[4], s_fh[4];
+    __shared__ int s_S[49], s_k, s_go, s_ok[4];
+    const int lane = threadIdx.x;
+    const int sdx = lane % 7 - 3, sdy = lane / 7 - 3;  // snapshot offset of lanes 0 .. 48
+    const long max_steps = 6 * g.n + 64;
+    long steps = 0;
+    for (;;) {
+        if (lane == 0) {
+            int go = !bad && hp.n > 0;
+            if (go && ++steps > max_steps) {
+                bad = 2;
+                go = 0;
+            }
+            if (go) {
+                double key;
+                int k;
+                hp.pop(key, k);
+                s_key = key;
+                s_k = k;
+            }
+            s_go = go;
+        }
+        __syncthreads();
+        if (!s_go) break;
+        const int k = s_k;
+        const double key = s_key;
+        const int i = k % g.nx, j = k / g.nx;
+        if (lane < 49) {
+            const int ii = i + sdx, jj = j + sdy;
+            double tv = INFINITY;
+            int sv = ST_FAR;
+            if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny) {
+                const long q = (long)jj * g.nx + ii;
+                tv = T[q];
+                sv = st[q];
+            }
+            s_T[lane] = tv;
+            s_S[lane] = sv;
+        } else if (lane < 53) {
+            const int d = lane - 49, ii = i + di[d], jj = j + dj[d];
+            s_fh[d] = (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny) ? (1.0 / (double)speed[(long)jj * g.nx + ii]) * g.h
+                                                                      : 0.0;
+        }
+        __syncthreads();
+        if (s_S[24] == ST_KNOWN || key != s_T[24]) continue;  // a stale entry
+        if (lane == 0) s_S[24] = ST_KNOWN;
+        __syncthreads();
+        if (lane < 4) {
+            const int d = lane, ii = i + di[d], jj = j + dj[d];
+            const int qn = 24 + di[d] + 7 * dj[d];
+            const bool ok = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && s_S[qn] != ST_KNOWN;
+            s_t[d] = ok ? node_update_at(s_T, s_S, qn, 7, ii, jj, g, s_fh[d]) : 0.0;
+            s_ok[d] = ok;
+        }
+        __syncthreads();
+        if (lane == 0) {
             st[k] = ST_KNOWN;
-            const int i = k % g.nx, j = k / g.nx;
             for (int d = 0; d < 4; ++d) {
-                const int ii = i + di[d], jj = j + dj[d];
-                if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny) continue;
-                const long mm = (long)jj * g.nx + ii;
-                if (st[mm] == ST_KNOWN) continue;
-                const double fh = (1.0 / (double)speed[mm]) * g.h;
-                const double t = node_update(T, st, g, mm, fh);
-                if (t < T[mm]) {
+                if (!s_ok[d]) continue;
+                const int qn = 24 + di[d] + 7 * dj[d];
+                const double t = s_t[d];
+                if (t < s_T[qn]) {
+                    const long mm = (long)(j + dj[d]) * g.nx + (i + di[d]);
                     T[mm] = t;
                     st[mm] = ST_TRIAL;
-                    if (!hp.push(t, (int)mm)) { bad = 1; break; }
+                    if (!hp.push(t, (int)mm)) {
+                        bad = 1;
+                        break;
+                    }
                 }
             }
         }
-        err[m] = bad;
+        __threadfence_block();  // lane 0's stores land before the next snapshot is loaded
+        __syncthreads();
     }
+    if (lane == 0) err[m] = bad;
     __syncthreads();
     for (int p = threadIdx.x; p < P; p += blockDim.x) table[(long)m * P + p] = (float)T[pix[p]];
 }
