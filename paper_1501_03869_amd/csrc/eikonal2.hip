@@ -7,9 +7,9 @@
 // relaxation is guaranteed to reach the heap-ordered result; the order of
 // acceptance is part of the answer.  Each map therefore runs the marching
 // itself, in heap order (smallest trial time first, ties by node index),
-// on one wave: one lane pops, accepts and updates, with the map's times and
-// states in device memory, the top of its heap in LDS and the rest of the
-// heap in device memory, and the maps of a chunk run side by side.
+// on one wave: the wave pops, accepts and updates together, with the map's
+// times and states in device memory, its trial set in LDS (spilling to device
+// memory), and the maps of a chunk run side by side.
 // The arithmetic is the definition's, in FP64 without contraction, so the
 // times equal the oracle's.
 #include <hip/hip_runtime.h>
@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "pat_internal.h"
@@ -97,25 +98,25 @@ __device__ double node_update(const double *T, const unsigned char *st, const Ma
     return node_update_at(T, st, m, g.nx, (int)(m % g.nx), (int)(m / g.nx), g, fh);
 }
 
-// Binary min-heap of (key, index), ordered by key then index (a strict total
-// order: a node is pushed again only with a smaller key).  The first
-// FMM2_LDS_HEAP entries (the top levels, where every push and pop walks) live
-// in the workgroup's LDS and the rest in device memory.  Only lane 0 runs the
-// heap, so its positions are made wave-uniform and the choice between the
-// two memories is a scalar branch; pushes and pops move a hole and write the
-// moving entry once.
-constexpr int FMM2_LDS_HEAP = 4096;
+// The trial set: (key, index) pairs of trial nodes (with stale duplicates,
+// skipped when popped), unordered.  Every lane of the map's wave takes part:
+// a pop scans every 64th entry per lane and finds the smallest with a
+// butterfly over the lanes, then moves the last entry into its place; a push
+// appends.  (key, index) is a strict total order (a node is pushed again only
+// with a smaller key), so the smallest entry is unique and the pops come in
+// the order of a binary heap.  The first lcap <= FMM2_LDS_SET entries live
+// in the workgroup's LDS, the rest in device memory.  n is the same in every lane;
+// lane 0 writes.
+constexpr int FMM2_LDS_SET = 4096;
 
-struct Heap {
-    double *key;  // device memory, entries >= FMM2_LDS_HEAP
+struct TrialSet {
+    double *key;  // device memory, entries >= FMM2_LDS_SET
     int *idx;
-    double *lkey;  // LDS, entries < FMM2_LDS_HEAP
+    double *lkey;  // LDS, entries < lcap
     int *lidx;
-    int n, cap;
-    __device__ static int u(int a) { return __builtin_amdgcn_readfirstlane(a); }
+    int n, cap, lcap;
     __device__ void get(int a, double &k, int &i) const {
-        a = u(a);
-        if (a < FMM2_LDS_HEAP) {
+        if (a < lcap) {
             k = lkey[a];
             i = lidx[a];
         } else {
@@ -123,9 +124,8 @@ struct Heap {
             i = idx[a];
         }
     }
-    __device__ void set(int a, double k, int i) {
-        a = u(a);
-        if (a < FMM2_LDS_HEAP) {
+    __device__ void put(int a, double k, int i) {
+        if (a < lcap) {
             lkey[a] = k;
             lidx[a] = i;
         } else {
@@ -134,66 +134,60 @@ struct Heap {
         }
     }
     __device__ static bool lt(double ka, int ia, double kb, int ib) { return ka < kb || (ka == kb && ia < ib); }
-    __device__ bool push(double k, int i) {
+    __device__ bool push(double k, int i, int lane) {
         if (n >= cap) return false;
-        int c = u(n++);
-        while (c > 0) {
-            const int p = (c - 1) / 2;
-            double kp;
-            int ip;
-            get(p, kp, ip);
-            if (!lt(k, i, kp, ip)) break;
-            set(c, kp, ip);
-            c = p;
-        }
-        set(c, k, i);
+        if (lane == 0) put(n, k, i);
+        ++n;
         return true;
     }
-    __device__ void pop(double &k, int &i) {
-        get(0, k, i);
-        --n;
-        if (n == 0) return;
-        double kl;
-        int il;
-        get(n, kl, il);
-        int c = 0;
-        for (;;) {
-            const int l = 2 * c + 1;
-            if (l >= n) break;
-            double ks;
-            int is;
-            get(l, ks, is);
-            int s = l;
-            if (l + 1 < n) {
-                double kr;
-                int ir;
-                get(l + 1, kr, ir);
-                if (lt(kr, ir, ks, is)) {
-                    s = l + 1;
-                    ks = kr;
-                    is = ir;
-                }
+    // n > 0; every lane returns the smallest entry
+    __device__ void pop(double &k, int &i, int lane) {
+        double bk = INFINITY;  // keys are finite
+        int bi = 0x7FFFFFFF, bp = -1;
+        for (int a = lane; a < n; a += 64) {
+            double ka;
+            int ia;
+            get(a, ka, ia);
+            if (lt(ka, ia, bk, bi)) {
+                bk = ka;
+                bi = ia;
+                bp = a;
             }
-            if (!lt(ks, is, kl, il)) break;
-            set(c, ks, is);
-            c = s;
         }
-        set(c, kl, il);
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ok = __shfl_xor(bk, off);
+            const int oi = __shfl_xor(bi, off), op = __shfl_xor(bp, off);
+            if (lt(ok, oi, bk, bi)) {
+                bk = ok;
+                bi = oi;
+                bp = op;
+            }
+        }
+        k = bk;
+        i = bi;
+        --n;
+        if (lane == 0 && bp != n) {
+            double kl;
+            int il;
+            get(n, kl, il);
+            put(bp, kl, il);
+        }
+        if (n >= lcap) __threadfence_block();  // a move in device memory lands before the next scan
     }
 };
 
-// One map per wave; lane 0 marches.  frozen: this map's nf frozen node
-// indices (ascending) and their times.  err[m] != 0 reports a full heap or
-// an exceeded step count (neither expected: the heap holds 5n entries and a
-// map takes at most 5n pops).
+// One map per wave.  frozen: this map's nf frozen node indices (ascending)
+// and their times.  err[m] != 0 reports a full trial set or an exceeded step
+// count (neither expected: the set holds 5n + 64 entries and a map takes at
+// most 5n pops).
 __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Map2 g, double *__restrict__ T_all,
                                              unsigned char *__restrict__ st_all, double *__restrict__ hkey_all,
                                              int *__restrict__ hidx_all, const int *__restrict__ frozen_idx,
                                              const double *__restrict__ frozen_val, const int *__restrict__ frozen_off,
                                              const int32_t *__restrict__ pix, int P, float *__restrict__ table,
-                                             int *__restrict__ err) {
-    __shared__ double s_hkey[FMM2_LDS_HEAP];
-    __shared__ int s_hidx[FMM2_LDS_HEAP];
+                                             int *__restrict__ err, int lcap) {
+    __shared__ double s_hkey[FMM2_LDS_SET];
+    __shared__ int s_hidx[FMM2_LDS_SET];
     const int m = blockIdx.x;
     double *T = T_all + (long)m * g.n;
     unsigned char *st = st_all + (long)m * g.n;
@@ -208,10 +202,13 @@ __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Ma
         st[frozen_idx[q]] = ST_KNOWN;
     }
     __syncthreads();
-    Heap hp{ hkey_all + (long)m * g.heap_cap, hidx_all + (long)m * g.heap_cap, s_hkey, s_hidx, 0, (int)g.heap_cap };
-    int bad = 0;  // lane 0's
+    TrialSet ts{ hkey_all + (long)m * g.heap_cap, hidx_all + (long)m * g.heap_cap, s_hkey, s_hidx, 0, (int)g.heap_cap,
+                 lcap };
+    const int lane = threadIdx.x;
     const int di[4] = { -1, 1, 0, 0 }, dj[4] = { 0, 0, -1, 1 };
-    if (threadIdx.x == 0) {
+    __shared__ int s_n0, s_bad0;
+    if (lane == 0) {
+        int bad = 0;
         // initial band: non-frozen neighbours of frozen nodes, valued in index order
         int band[256];
         int nb = 0;
@@ -236,43 +233,35 @@ __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Ma
             const long mm = band[a];
             const double fh = (1.0 / (double)speed[mm]) * g.h;
             T[mm] = node_update(T, st, g, mm, fh);
-            if (!hp.push(T[mm], (int)mm)) bad = 1;
+            if (!ts.push(T[mm], (int)mm, 0)) bad = 1;
         }
+        s_n0 = ts.n;
+        s_bad0 = bad;
     }
     __threadfence_block();
     __syncthreads();
-    // Marching.  Lane 0 pops; an update reads only accepted nodes, and none
-    // is accepted during a pop's four updates, so they all read one snapshot:
-    // the 7 x 7 neighbourhood of the popped node k (every node the four
-    // neighbours' stencils reach) taken after k is accepted.  49 lanes load
-    // it and 4 more the neighbours' slowness in one round trip, 4 lanes
-    // compute the updates, and lane 0 applies them in neighbour order.
-    __shared__ double s_T[49], s_key, s_t[4], s_fh[4];
-    __shared__ int s_S[49], s_k, s_go, s_ok[4];
-    const int lane = threadIdx.x;
+    ts.n = s_n0;
+    int bad = s_bad0;  // the same in every lane from here on
+    // Marching.  An update reads only accepted nodes, and none is accepted
+    // during a pop's four updates, so they all read one snapshot: the 7 x 7
+    // neighbourhood of the popped node k (every node the four neighbours'
+    // stencils reach) taken after k is accepted.  49 lanes load it and 4
+    // more the neighbours' slowness in one round trip, 4 lanes compute the
+    // updates, and the wave applies them in neighbour order (lane 0 writes).
+    __shared__ double s_T[49], s_t[4], s_fh[4];
+    __shared__ int s_S[49], s_ok[4];
     const int sdx = lane % 7 - 3, sdy = lane / 7 - 3;  // snapshot offset of lanes 0 .. 48
     const long max_steps = 6 * g.n + 64;
     long steps = 0;
     for (;;) {
-        if (lane == 0) {
-            int go = !bad && hp.n > 0;
-            if (go && ++steps > max_steps) {
-                bad = 2;
-                go = 0;
-            }
-            if (go) {
-                double key;
-                int k;
-                hp.pop(key, k);
-                s_key = key;
-                s_k = k;
-            }
-            s_go = go;
+        if (bad || ts.n == 0) break;
+        if (++steps > max_steps) {
+            bad = 2;
+            break;
         }
-        __syncthreads();
-        if (!s_go) break;
-        const int k = s_k;
-        const double key = s_key;
+        double key;
+        int k;
+        ts.pop(key, k, lane);
         const int i = k % g.nx, j = k / g.nx;
         if (lane < 49) {
             const int ii = i + sdx, jj = j + sdy;
@@ -302,24 +291,24 @@ __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Ma
             s_ok[d] = ok;
         }
         __syncthreads();
-        if (lane == 0) {
-            st[k] = ST_KNOWN;
-            for (int d = 0; d < 4; ++d) {
-                if (!s_ok[d]) continue;
-                const int qn = 24 + di[d] + 7 * dj[d];
-                const double t = s_t[d];
-                if (t < s_T[qn]) {
-                    const long mm = (long)(j + dj[d]) * g.nx + (i + di[d]);
+        if (lane == 0) st[k] = ST_KNOWN;
+        for (int d = 0; d < 4; ++d) {
+            if (!s_ok[d]) continue;
+            const int qn = 24 + di[d] + 7 * dj[d];
+            const double t = s_t[d];
+            if (t < s_T[qn]) {
+                const long mm = (long)(j + dj[d]) * g.nx + (i + di[d]);
+                if (lane == 0) {
                     T[mm] = t;
                     st[mm] = ST_TRIAL;
-                    if (!hp.push(t, (int)mm)) {
-                        bad = 1;
-                        break;
-                    }
+                }
+                if (!ts.push(t, (int)mm, lane)) {
+                    bad = 1;
+                    break;
                 }
             }
         }
-        __threadfence_block();  // lane 0's stores land before the next snapshot is loaded
+        __threadfence_block();  // lane 0's stores land before the next pop and snapshot
         __syncthreads();
     }
     if (lane == 0) err[m] = bad;
@@ -369,6 +358,10 @@ extern "C" int pat_eikonal_tables_o2(pat_ctx *ctx, const float *d_speed, int nx,
     // per map: times (8 B), states (1 B) and a heap of 5n + 64 entries (12 B)
     Map2 g;
     g.nx = nx; g.ny = ny; g.h = h; g.n = n; g.heap_cap = 5 * n + 64;
+    // trial-set entries kept in LDS; PAT_FMM2_LDS_ENTRIES lowers it (tests of
+    // the part in device memory)
+    int lds_cap = FMM2_LDS_SET;
+    if (const char *e = std::getenv("PAT_FMM2_LDS_ENTRIES")) lds_cap = std::max(0, std::min(FMM2_LDS_SET, std::atoi(e)));
     const size_t per_map = (size_t)n * 9 + (size_t)g.heap_cap * 12;
     const int chunk = (int)std::max<long>(1, std::min<long>(S, (long)((8ull << 30) / per_map)));
     if ((rc = ctx->eik_tq.grow((size_t)chunk * per_map))) return rc;
@@ -420,7 +413,7 @@ extern "C" int pat_eikonal_tables_o2(pat_ctx *ctx, const float *d_speed, int nx,
         PAT_HIP(hipMemcpyAsync(d_fval, fval.data(), fval.size() * sizeof(double), hipMemcpyHostToDevice, st));
         PAT_HIP(hipMemcpyAsync(d_foff, foff.data(), foff.size() * sizeof(int), hipMemcpyHostToDevice, st));
         k_fmm2<<<dim3(maps), dim3(64), 0, st>>>(d_speed, g, T_all, st_all, hkey, hidx, d_fidx, d_fval, d_foff, d_pix,
-                                                P, d_table + (long)s0 * P, d_err);
+                                                P, d_table + (long)s0 * P, d_err, lds_cap);
         PAT_HIP(hipGetLastError());
         PAT_HIP(hipMemcpyAsync(errs.data(), d_err, (size_t)maps * sizeof(int), hipMemcpyDeviceToHost, st));
         PAT_HIP(hipStreamSynchronize(st));

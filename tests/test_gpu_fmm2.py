@@ -88,3 +88,15 @@ def test_tables_o2_rejects_bad_input(ctx):
         ctx.eikonal_tables_o2(dev(geo.speed), geo.h, geo.sensors * 10, dev(geo.pix))
     with pytest.raises(pat.PatError):
         ctx.eikonal_tables_o2(dev(geo.speed), geo.h, geo.sensors, dev(np.array([geo.speed.size], np.int32)))
+
+
+@pytest.mark.parametrize("entries,name", [(0, "tiny"), (8, "tiny"), (300, "small")])
+def test_trial_set_in_device_memory(ctx, orc, entries, name, monkeypatch):
+    # the trial set of a map lives in LDS up to a capacity and in device
+    # memory beyond it; the paper geometry's sets (a few hundred entries)
+    # stay in LDS, so lower the capacity to run the device-memory part (all
+    # of it, most of it, and the largest sets of the 128^2 geometry, about
+    # 340 entries, just past it): the tables must not change
+    monkeypatch.setenv("PAT_FMM2_LDS_ENTRIES", str(entries))
+    geo = inputs.config(name)
+    _compare(ctx, orc, geo.speed, geo.h, geo.sensors, geo.pix, f"{name}, {entries} trial entries in LDS")
