@@ -135,7 +135,7 @@ int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, int ny, doubl
  * (one map per wave, the marching itself sequential), so the times equal the
  * definition's; rounded once to float32 seconds.  Arguments, seeding and
  * errors as pat_eikonal_tables (grid up to 2^28 nodes); memory
- * about 69 bytes per node per map in flight (maps in chunks of 8 GiB).
+ * about 25 bytes per node per map in flight (maps in chunks of 8 GiB).
  * Synchronises `stream`.  The first 4096 entries of a map's trial set sit in
  * LDS; the environment variable PAT_FMM2_LDS_ENTRIES (0 .. 4096), read at
  * each call, lowers that count, which only moves entries to device memory

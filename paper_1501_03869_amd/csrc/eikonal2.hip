@@ -98,13 +98,14 @@ __device__ double node_update(const double *T, const unsigned char *st, const Ma
     return node_update_at(T, st, m, g.nx, (int)(m % g.nx), (int)(m / g.nx), g, fh);
 }
 
-// The trial set: (key, index) pairs of trial nodes (with stale duplicates,
-// skipped when popped), unordered.  Every lane of the map's wave takes part:
-// a pop scans every 64th entry per lane and finds the smallest with a
-// butterfly over the lanes, then moves the last entry into its place; a push
-// appends.  (key, index) is a strict total order (a node is pushed again only
-// with a smaller key), so the smallest entry is unique and the pops come in
-// the order of a binary heap.  The first lcap <= FMM2_LDS_SET entries live
+// The trial set: one (key, index) pair per trial node, unordered, with each
+// node's position in pos.  Every lane of the map's wave takes part: a pop
+// scans every 64th entry per lane and finds the smallest with a butterfly
+// over the lanes, then moves the last entry into its place; a push appends;
+// a smaller time for a node already in the set overwrites its key in place.
+// The keys are the nodes' current times and (key, index) is a strict total
+// order, so the smallest entry is unique and the nodes come out in the order
+// of a lazily deleting binary heap.  The first lcap <= FMM2_LDS_SET entries live
 // in the workgroup's LDS, the rest in device memory.  n is the same in every lane;
 // lane 0 writes.
 constexpr int FMM2_LDS_SET = 4096;
@@ -114,6 +115,7 @@ struct TrialSet {
     int *idx;
     double *lkey;  // LDS, entries < lcap
     int *lidx;
+    int *pos;  // device memory: position of each trial node
     int n, cap, lcap;
     __device__ void get(int a, double &k, int &i) const {
         if (a < lcap) {
@@ -136,12 +138,19 @@ struct TrialSet {
     __device__ static bool lt(double ka, int ia, double kb, int ib) { return ka < kb || (ka == kb && ia < ib); }
     __device__ bool push(double k, int i, int lane) {
         if (n >= cap) return false;
-        if (lane == 0) put(n, k, i);
+        if (lane == 0) {
+            put(n, k, i);
+            pos[i] = n;
+        }
         ++n;
         return true;
     }
-    // n > 0; every lane returns the smallest entry
-    __device__ void pop(double &k, int &i, int lane) {
+    __device__ void lower(int p, double k, int i, int lane) {
+        if (lane == 0) put(p, k, i);
+    }
+    // n > 0; every lane returns the smallest entry, and the node moved into
+    // its place (mv_i, -1 if none) with its new position mv_p
+    __device__ void pop(double &k, int &i, int &mv_i, int &mv_p, int lane) {
         double bk = INFINITY;  // keys are finite
         int bi = 0x7FFFFFFF, bp = -1;
         for (int a = lane; a < n; a += 64) {
@@ -166,23 +175,30 @@ struct TrialSet {
         k = bk;
         i = bi;
         --n;
-        if (lane == 0 && bp != n) {
+        mv_i = -1;
+        mv_p = bp;
+        if (bp != n) {
             double kl;
             int il;
             get(n, kl, il);
-            put(bp, kl, il);
+            mv_i = il;
+            if (lane == 0) {
+                put(bp, kl, il);
+                pos[il] = bp;
+            }
         }
         if (n >= lcap) __threadfence_block();  // a move in device memory lands before the next scan
     }
 };
 
 // One map per wave.  frozen: this map's nf frozen node indices (ascending)
-// and their times.  err[m] != 0 reports a full trial set or an exceeded step
-// count (neither expected: the set holds 5n + 64 entries and a map takes at
-// most 5n pops).
+// and their times.  err[m] != 0 reports a full trial set, an exceeded step
+// count or a set position out of range (none expected: the set holds n + 64
+// entries, each node at most once, and a map takes at most n pops).
 __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Map2 g, double *__restrict__ T_all,
                                              unsigned char *__restrict__ st_all, double *__restrict__ hkey_all,
-                                             int *__restrict__ hidx_all, const int *__restrict__ frozen_idx,
+                                             int *__restrict__ hidx_all, int *__restrict__ pos_all,
+                                             const int *__restrict__ frozen_idx,
                                              const double *__restrict__ frozen_val, const int *__restrict__ frozen_off,
                                              const int32_t *__restrict__ pix, int P, float *__restrict__ table,
                                              int *__restrict__ err, int lcap) {
@@ -202,8 +218,8 @@ __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Ma
         st[frozen_idx[q]] = ST_KNOWN;
     }
     __syncthreads();
-    TrialSet ts{ hkey_all + (long)m * g.heap_cap, hidx_all + (long)m * g.heap_cap, s_hkey, s_hidx, 0, (int)g.heap_cap,
-                 lcap };
+    TrialSet ts{ hkey_all + (long)m * g.heap_cap, hidx_all + (long)m * g.heap_cap, s_hkey, s_hidx,
+                 pos_all + (long)m * g.n, 0, (int)g.heap_cap, lcap };
     const int lane = threadIdx.x;
     const int di[4] = { -1, 1, 0, 0 }, dj[4] = { 0, 0, -1, 1 };
     __shared__ int s_n0, s_bad0;
@@ -249,7 +265,7 @@ __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Ma
     // more the neighbours' slowness in one round trip, 4 lanes compute the
     // updates, and the wave applies them in neighbour order (lane 0 writes).
     __shared__ double s_T[49], s_t[4], s_fh[4];
-    __shared__ int s_S[49], s_ok[4];
+    __shared__ int s_S[49], s_ok[4], s_pos[4];
     const int sdx = lane % 7 - 3, sdy = lane / 7 - 3;  // snapshot offset of lanes 0 .. 48
     const long max_steps = 6 * g.n + 64;
     long steps = 0;
@@ -260,8 +276,8 @@ __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Ma
             break;
         }
         double key;
-        int k;
-        ts.pop(key, k, lane);
+        int k, mv_i, mv_p;
+        ts.pop(key, k, mv_i, mv_p, lane);
         const int i = k % g.nx, j = k / g.nx;
         if (lane < 49) {
             const int ii = i + sdx, jj = j + sdy;
@@ -278,9 +294,16 @@ __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Ma
             const int d = lane - 49, ii = i + di[d], jj = j + dj[d];
             s_fh[d] = (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny) ? (1.0 / (double)speed[(long)jj * g.nx + ii]) * g.h
                                                                       : 0.0;
+        } else if (lane < 57) {
+            // set positions of the neighbours (meaningful for trial ones)
+            const int d = lane - 53, ii = i + di[d], jj = j + dj[d];
+            s_pos[d] = (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny) ? ts.pos[(long)jj * g.nx + ii] : -1;
         }
         __syncthreads();
-        if (s_S[24] == ST_KNOWN || key != s_T[24]) continue;  // a stale entry
+        if (s_S[24] == ST_KNOWN || key != s_T[24]) {  // a stale entry (none arise: keys are lowered in place)
+            __threadfence_block();
+            continue;
+        }
         if (lane == 0) s_S[24] = ST_KNOWN;
         __syncthreads();
         if (lane < 4) {
@@ -302,7 +325,15 @@ __global__ void __launch_bounds__(64) k_fmm2(const float *__restrict__ speed, Ma
                     T[mm] = t;
                     st[mm] = ST_TRIAL;
                 }
-                if (!ts.push(t, (int)mm, lane)) {
+                if (s_S[qn] == ST_TRIAL) {
+                    // in the set already: its position, unless this pop moved it
+                    const int p = (int)mm == mv_i ? mv_p : s_pos[d];
+                    if ((unsigned)p >= (unsigned)ts.n) {  // a position outside the set: stop with an error
+                        bad = 3;
+                        break;
+                    }
+                    ts.lower(p, t, (int)mm, lane);
+                } else if (!ts.push(t, (int)mm, lane)) {
                     bad = 1;
                     break;
                 }
@@ -355,21 +386,23 @@ extern "C" int pat_eikonal_tables_o2(pat_ctx *ctx, const float *d_speed, int nx,
     }
     if (S == 0 || P == 0) return PAT_OK;
 
-    // per map: times (8 B), states (1 B) and a heap of 5n + 64 entries (12 B)
+    // per map: times (8 B), states (1 B), set positions (4 B) and a trial set
+    // of n + 64 entries (12 B; a node is in it at most once)
     Map2 g;
-    g.nx = nx; g.ny = ny; g.h = h; g.n = n; g.heap_cap = 5 * n + 64;
+    g.nx = nx; g.ny = ny; g.h = h; g.n = n; g.heap_cap = n + 64;
     // trial-set entries kept in LDS; PAT_FMM2_LDS_ENTRIES lowers it (tests of
     // the part in device memory)
     int lds_cap = FMM2_LDS_SET;
     if (const char *e = std::getenv("PAT_FMM2_LDS_ENTRIES")) lds_cap = std::max(0, std::min(FMM2_LDS_SET, std::atoi(e)));
-    const size_t per_map = (size_t)n * 9 + (size_t)g.heap_cap * 12;
+    const size_t per_map = (size_t)n * 13 + (size_t)g.heap_cap * 12;
     const int chunk = (int)std::max<long>(1, std::min<long>(S, (long)((8ull << 30) / per_map)));
     if ((rc = ctx->eik_tq.grow((size_t)chunk * per_map))) return rc;
     char *base = static_cast<char *>(ctx->eik_tq.ptr);
     double *T_all = reinterpret_cast<double *>(base);
     double *hkey = T_all + (size_t)chunk * n;
     int *hidx = reinterpret_cast<int *>(hkey + (size_t)chunk * g.heap_cap);
-    unsigned char *st_all = reinterpret_cast<unsigned char *>(hidx + (size_t)chunk * g.heap_cap);
+    int *pos_all = hidx + (size_t)chunk * g.heap_cap;
+    unsigned char *st_all = reinterpret_cast<unsigned char *>(pos_all + (size_t)chunk * n);
 
     // seeding, as for the first-order tables: nodes within 2h of the sensor
     // at the straight-ray time with the slowness of the nearest node
@@ -412,7 +445,7 @@ extern "C" int pat_eikonal_tables_o2(pat_ctx *ctx, const float *d_speed, int nx,
         PAT_HIP(hipMemcpyAsync(d_fidx, fidx.data(), fidx.size() * sizeof(int), hipMemcpyHostToDevice, st));
         PAT_HIP(hipMemcpyAsync(d_fval, fval.data(), fval.size() * sizeof(double), hipMemcpyHostToDevice, st));
         PAT_HIP(hipMemcpyAsync(d_foff, foff.data(), foff.size() * sizeof(int), hipMemcpyHostToDevice, st));
-        k_fmm2<<<dim3(maps), dim3(64), 0, st>>>(d_speed, g, T_all, st_all, hkey, hidx, d_fidx, d_fval, d_foff, d_pix,
+        k_fmm2<<<dim3(maps), dim3(64), 0, st>>>(d_speed, g, T_all, st_all, hkey, hidx, pos_all, d_fidx, d_fval, d_foff, d_pix,
                                                 P, d_table + (long)s0 * P, d_err, lds_cap);
         PAT_HIP(hipGetLastError());
         PAT_HIP(hipMemcpyAsync(errs.data(), d_err, (size_t)maps * sizeof(int), hipMemcpyDeviceToHost, st));
