@@ -79,11 +79,14 @@ def cpu_baseline(geo, vol, budget_s=12.0):
     before the timed region) and frames synthesised from it."""
     from paper_1501_03869_amd import inputs
     from oracle import oracle as orc
+    tb = time.perf_counter()
     if vol:
         T = orc.tables3(geo.speed, geo.h, geo.sensors, geo.pix)
+        build_s = time.perf_counter() - tb
         frames = [inputs.frame_for3(geo, T, f) for f in range(2)]
     else:
         T = orc.tables(geo.speed, geo.h, geo.sensors, geo.pix)
+        build_s = time.perf_counter() - tb
         phantom = "points" if geo.nx * geo.ny > 512 * 512 else "segments"
         frames = [inputs.frame_for(geo, T, f, phantom=phantom) for f in range(2)]
     n = 0
@@ -97,7 +100,10 @@ def cpu_baseline(geo, vol, budget_s=12.0):
     gathers = n * geo.S * geo.P
     return {"value": gathers / el, "unit": "gathers/s", "cores": orc.max_threads(), "kind": "oracle",
             "sample": f"{n} whole frames ({geo.S} sensors x {geo.P} {'voxels' if vol else 'pixels'}) of the same "
-                      f"workload (the oracle's own table and frames), FP64 filter + gather, {el:.1f} s"}
+                      f"workload (the oracle's own table and frames), FP64 filter + gather, {el:.1f} s",
+            "table_build_s": build_s,
+            "table_build_note": "the oracle's first-order fast marching (FP64, heap) for all sensors, parallel over "
+                                "sensors on the same threads; not part of value"}
 
 
 def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
