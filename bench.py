@@ -49,12 +49,12 @@ HBM_PEAK_GBS = 8000.0
 # SHA-256 of the files below; any change makes the field null until the
 # counters are taken again.  Summaries: profiles/k_bp_px_*_hbm_counters.md.
 TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_common.h")
-TRAFFIC_SHA = "4552aa90f5f8ee786b732b2ae68615271ed06d22072a30149b1859a4c80804c6:" \
+TRAFFIC_SHA = "189c45d77cbf28d960722d31ef689b78ccb90dae8844a78cb4aca670060ac7ba:" \
               "046afad2d9d976f56fb21100e0e5c9f9620cda616a8d09c45b88ba79e760cfe7"
 FETCH_FACTOR = 250000.0 / 125012.32
 WRITE_FACTOR = 1.0
-TRAFFIC_KIB = {"paper": (25133.93, 83.46), "large": (1839643.75, 3275.14),
-               "head3": (24579.54, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+TRAFFIC_KIB = {"paper": (25128.76, 83.48), "large": (1842475.53, 3278.96),
+               "head3": (24550.47, 174.70)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 
 
 def measured_traffic(config: str):

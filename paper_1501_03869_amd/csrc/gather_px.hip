@@ -125,7 +125,10 @@ struct Stage {
 // sw .. sw+2*sps-1 (sw = wv*2*sps, clipped to S); lanes 0-31 take the even
 // ones, lanes 32-63 the odd ones.  wv must be wave-uniform (a scalar) and
 // sw < S.
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC = 0>
+// SHDR: 16-bit tables' tile headers by two scalar loads per record pair
+// (the table pointer is a read-only kernel argument); else by a vector load
+// per lane.
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC = 0, bool SHDR = true>
 __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, int tile, int wv) {
     const int S = J.S, P = J.P, N = J.N, sps = J.sps;
     const float t0dt = J.t0dt, sc = J.scale;
@@ -271,11 +274,20 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             const int s0 = step_s0(i);
             const uint32_t rows = (uint32_t)min(2 * PX_U, S - s0);
             const __amdgpu_buffer_rsrc_t ro = rsrc(off16 + (size_t)s0 * P, rows * (uint32_t)P * 2u);
+            // a tile header is the same for the 32 lanes of a half-wave: two
+            // scalar loads per record pair (records past S read the last one,
+            // for slots that contribute nothing)
             const __amdgpu_buffer_rsrc_t rh = rsrc(hdr32 + (size_t)s0 * tiles, rows * (uint32_t)tiles * 4u);
 #pragma unroll
             for (int j = 0; j < PX_U; ++j) {
                 st.d[j] = __builtin_amdgcn_raw_buffer_load_b16(ro, ooff, 2 * j * P * 2, 0);
-                st.h[j] = __builtin_amdgcn_raw_buffer_load_b32(rh, hoff, 2 * j * tiles * 4, 0);
+                if constexpr (SHDR) {
+                    const int se0 = min(s0 + 2 * j, S - 1), so0 = min(s0 + 2 * j + 1, S - 1);
+                    const uint32_t he = hdr32[(size_t)se0 * tiles + tile], ho = hdr32[(size_t)so0 * tiles + tile];
+                    st.h[j] = half ? ho : he;
+                } else {
+                    st.h[j] = __builtin_amdgcn_raw_buffer_load_b32(rh, hoff, 2 * j * tiles * 4, 0);
+                }
             }
         } else {
             const __amdgpu_buffer_rsrc_t rt = tab_rsrc(step_s0(i));
@@ -462,13 +474,13 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
 
 // One tile of one frame: every wave sums its slots, then the slot sums are
 // added in slot order.  Waves whose slots start past S add zero.
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC = 0>
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC = 0, bool SHDR = true>
 __device__ __forceinline__ void px_block(const PxJob &J, const Delay &dec, int tile, int wv, int nw) {
     __shared__ float red[2 * PX_MAX_WAVES][PX_T];
     const int lane = threadIdx.x & 63;
     const int px = lane & (PX_T - 1);
     float acc = 0.0f;
-    if (wv * 2 * J.sps < J.S) acc = px_slot_sum<Delay, SFMT, FILTERED, HAS_W, CONSTC>(J, dec, tile, wv);
+    if (wv * 2 * J.sps < J.S) acc = px_slot_sum<Delay, SFMT, FILTERED, HAS_W, CONSTC, SHDR>(J, dec, tile, wv);
     red[wv * 2 + (lane >> 5)][px] = acc;
     __syncthreads();
     const int p = tile * PX_T + px;
@@ -488,7 +500,7 @@ struct PxGeom {
     float h, x0, y0, z0, inv_c;
 };
 
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC>
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC, bool SHDR>
 __global__ void __launch_bounds__(64 * PX_MAX_WAVES)
     k_bp_px(const uint32_t *__restrict__ tab, const void *__restrict__ sig, const float *__restrict__ scale,
             const float *__restrict__ w, int S, int P, int N, int sps, Delay dec, float t0dt,
@@ -508,7 +520,7 @@ __global__ void __launch_bounds__(64 * PX_MAX_WAVES)
     // a wave-uniform wave index keeps the descriptors in scalar registers
     const int tile = xcd_tile(blockIdx.x, (P + PX_T - 1) / PX_T);
     if (tile < 0) return;
-    px_block<Delay, SFMT, FILTERED, HAS_W, CONSTC>(J, dec, tile, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
+    px_block<Delay, SFMT, FILTERED, HAS_W, CONSTC, SHDR>(J, dec, tile, __builtin_amdgcn_readfirstlane(threadIdx.x >> 6),
                                                    blockDim.x >> 6);
 }
 
@@ -544,12 +556,12 @@ __global__ void __launch_bounds__(64 * PX_MULTI_WAVES) k_bp_px_multi(const pat_b
         else px_block<DelayQ16, SFMT, false, false>(J, dec, tile, wv, PX_MULTI_WAVES);
     } else {
         DelayR16 dec;
-        if (D.w) px_block<DelayR16, SFMT, false, true>(J, dec, tile, wv, PX_MULTI_WAVES);
-        else px_block<DelayR16, SFMT, false, false>(J, dec, tile, wv, PX_MULTI_WAVES);
+        if (D.w) px_block<DelayR16, SFMT, false, true, 0, false>(J, dec, tile, wv, PX_MULTI_WAVES);
+        else px_block<DelayR16, SFMT, false, false, 0, false>(J, dec, tile, wv, PX_MULTI_WAVES);
     }
 }
 
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC = 0>
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int CONSTC = 0, bool SHDR = true>
 int launch_one(int S, int P, int F, const uint32_t *tab, const void *sig, const float *scale, const float *w, int N,
                Delay dec, float t0dt, float *img, hipStream_t st, const PxGeom &geo = PxGeom{}) {
     // occupancy per block size, computed once per kernel and device
@@ -564,13 +576,13 @@ int launch_one(int S, int P, int F, const uint32_t *tab, const void *sig, const 
             PAT_HIP(hipDeviceGetAttribute(&cache_cus, hipDeviceAttributeMultiprocessorCount, dev));
             for (int W = 1; W <= PX_MAX_WAVES; ++W)
                 PAT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &cache_bpc[W], k_bp_px<Delay, SFMT, FILTERED, HAS_W, CONSTC>, 64 * W, 0));
+                    &cache_bpc[W], k_bp_px<Delay, SFMT, FILTERED, HAS_W, CONSTC, SHDR>, 64 * W, 0));
             cache_dev = dev;
         }
         sh = px_shape(S, P, F, cache_cus, [&](int W) { return cache_bpc[W]; });
     }
     const dim3 grid(xcd_slots(sh.tiles), F);
-    k_bp_px<Delay, SFMT, FILTERED, HAS_W, CONSTC><<<grid, dim3(64 * sh.waves), 0, st>>>(
+    k_bp_px<Delay, SFMT, FILTERED, HAS_W, CONSTC, SHDR><<<grid, dim3(64 * sh.waves), 0, st>>>(
         tab, sig, scale, w, S, P, N, sh.sps, dec, t0dt, img, geo);
     PAT_HIP(hipGetLastError());
     return PAT_OK;
@@ -579,6 +591,19 @@ int launch_one(int S, int P, int F, const uint32_t *tab, const void *sig, const 
 template <class Delay, int SFMT>
 int launch_px(bool filtered, int S, int P, int F, const uint32_t *tab, const void *sig, const float *scale,
               const float *w, int N, Delay dec, float t0dt, float *img, hipStream_t st) {
+    // 16-bit tables: tile headers by scalar loads when the table streams from
+    // HBM (the vector-memory path is then the limit); a cached table's short
+    // latency-bound pipeline does better with vector loads, which it can wait
+    // for one by one
+    if constexpr (Delay::kR16) {
+        if (pat_r16_bytes(S, P) <= PAT_CACHED_TABLE_BYTES) {
+            if (w)
+                return filtered ? launch_one<Delay, SFMT, true, true, 0, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st)
+                                : launch_one<Delay, SFMT, false, true, 0, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
+            return filtered ? launch_one<Delay, SFMT, true, false, 0, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st)
+                            : launch_one<Delay, SFMT, false, false, 0, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
+        }
+    }
     if (w)
         return filtered ? launch_one<Delay, SFMT, true, true>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st)
                         : launch_one<Delay, SFMT, false, true>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
