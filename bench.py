@@ -546,8 +546,10 @@ def main():
         "latency_note": "host frame -> H2D -> fused filter+gather -> D2H image, synchronous, pinned buffers",
         "table_build_s": build_s,
         "table_build_rounds": est["rounds"],
+        "table_build_node_updates_per_s": est["sweeps"] * (512 if vol else 1024) / build_s,
         "table_build_note": "pat_eikonal_tables" + ("_3d" if vol else "") + " wall time for all sensors (second "
-                            "call), host validation and seeding included",
+                            "call), host validation and seeding included; node updates = in-tile sweeps x nodes "
+                            "per tile (32 x 32, or 8^3 for 3-D bricks)",
         "table_build_o2_s": build_o2_s,
         "table_build_o2_note": "pat_eikonal_tables_o2 (the paper's second-order scheme) wall time for all sensors; "
                                "null for 3-D and grids above 512^2",
