@@ -254,9 +254,11 @@ static double node_update2(const double *T, const unsigned char *state, int nx, 
 
 /* Fast marching with the update of the given order (1 or 2); otherwise as
  * orc_fmm (same heap order: the smallest trial time first, ties by index;
- * a trial value is replaced when a newly accepted neighbour lowers it). */
+ * a trial value is replaced when a newly accepted neighbour lowers it).
+ * accepted (may be NULL): the node indices in the order they were accepted,
+ * one per pop (at most nx*ny entries). */
 int orc_fmm2(int nx, int ny, double h, const double *slow, const unsigned char *frozen, double *T, long *npop,
-             int order) {
+             int order, int32_t *accepted) {
     long n = (long)nx * ny;
     unsigned char *state = (unsigned char *)calloc((size_t)n, 1);
     orc_heap hp = { 0, 0, 0 };
@@ -288,6 +290,7 @@ int orc_fmm2(int nx, int ny, double h, const double *slow, const unsigned char *
         long k = it.idx;
         if (state[k] == ORC_KNOWN || it.key != T[k]) continue; /* stale entry */
         state[k] = ORC_KNOWN;
+        if (accepted) accepted[pops] = (int32_t)k;
         ++pops;
         int i = (int)(k % nx), j = (int)(k / nx);
         const int di[4] = { -1, 1, 0, 0 }, dj[4] = { 0, 0, -1, 1 };
@@ -444,7 +447,7 @@ int orc_tables2(int nx, int ny, double h, const float *speed, const double *sxy,
                 rc = -1;
                 continue;
             }
-            if (orc_fmm2(nx, ny, h, slow, fr, T, 0, 2)) {
+            if (orc_fmm2(nx, ny, h, slow, fr, T, 0, 2, 0)) {
 #ifdef _OPENMP
 #pragma omp atomic write
 #endif

@@ -51,7 +51,8 @@ def lib():
         L.orc_seed.restype = C.c_int
         L.orc_tables.argtypes = [C.c_int, C.c_int, C.c_double, _fp, _dp, C.c_int, _i32, C.c_long, _dp, C.c_int]
         L.orc_tables.restype = C.c_int
-        L.orc_fmm2.argtypes = [C.c_int, C.c_int, C.c_double, _dp, _u8, _dp, C.POINTER(C.c_long), C.c_int]
+        L.orc_fmm2.argtypes = [C.c_int, C.c_int, C.c_double, _dp, _u8, _dp, C.POINTER(C.c_long), C.c_int,
+                               C.c_void_p]
         L.orc_fmm2.restype = C.c_int
         L.orc_tables2.argtypes = [C.c_int, C.c_int, C.c_double, _fp, _dp, C.c_int, _i32, C.c_long, _dp, C.c_int]
         L.orc_tables2.restype = C.c_int
@@ -105,16 +106,23 @@ def fmm(slow: np.ndarray, frozen: np.ndarray, T0: np.ndarray, h: float):
     return T, int(pops.value)
 
 
-def fmm2(slow: np.ndarray, frozen: np.ndarray, T0: np.ndarray, h: float, order: int = 2):
+def fmm2(slow: np.ndarray, frozen: np.ndarray, T0: np.ndarray, h: float, order: int = 2,
+         with_order: bool = False):
     """Fast marching with the paper's second-order one-sided differences
-    (order=2) or the first-order update (order=1).  Returns (T, pops)."""
+    (order=2) or the first-order update (order=1).  Returns (T, pops), or
+    (T, pops, accepted) with the flat node indices in acceptance order when
+    with_order is set."""
     ny, nx = slow.shape
     T = np.ascontiguousarray(T0, dtype=np.float64).copy()
     pops = C.c_long(0)
+    acc = np.full(nx * ny, -1, dtype=np.int32)
     rc = lib().orc_fmm2(nx, ny, float(h), np.ascontiguousarray(slow, dtype=np.float64),
-                        np.ascontiguousarray(frozen, dtype=np.uint8), T, C.byref(pops), int(order))
+                        np.ascontiguousarray(frozen, dtype=np.uint8), T, C.byref(pops), int(order),
+                        acc.ctypes.data if with_order else None)
     if rc:
         raise MemoryError("orc_fmm2")
+    if with_order:
+        return T, int(pops.value), acc[:int(pops.value)].copy()
     return T, int(pops.value)
 
 
