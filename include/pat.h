@@ -33,6 +33,14 @@
  *     x_i = (i - (nx-1)/2) h, y_j = (j - (ny-1)/2) h (grid-centred metres).
  *   - Time convention: sample n of a signal is taken at t_n = t0 + n dt
  *     (the laser pulse fires at t = 0).
+ *   - Failure injection, for tests of the error paths (both unset in normal
+ *     use; every kernel still runs to completion):
+ *       PAT_FAULT_ALLOC_BYTES=b  read by pat_ctx_create and pat_server_create:
+ *         that context or server treats every device allocation of b bytes or
+ *         more as failed (PAT_ENOMEM, or a failed map build in a server);
+ *       PAT_EIK_ROUND_CAP=r  read at each pat_eikonal_tables /
+ *         pat_eikonal_tables_3d call: the relaxation stops with PAT_ENOCONV
+ *         after r rounds when r is below the built-in cap.
  */
 #ifndef PAT_H
 #define PAT_H
@@ -117,7 +125,8 @@ size_t pat_backproject_scratch_bytes(int S, int P, int F);
  * time |x_k - s| / c(n*), n* the node nearest the sensor; the rest converge
  * to the upwind fixed point by tile-parallel relaxation in integer fixed
  * point.  Synchronises `stream`.  PAT_ENOCONV if the relaxation exceeds its
- * round cap (never expected).
+ * round cap, 100 (tiles_x + tiles_y) + 1000 rounds of 32 x 32 tiles (never
+ * expected; PAT_EIK_ROUND_CAP lowers it); the context stays usable.
  */
 int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, int ny, double h,
                        const double *h_sensor_xy, int S, const int32_t *d_pix, int P,
@@ -187,10 +196,22 @@ typedef struct pat_eikonal_stats {
 int pat_eikonal_last_stats(pat_ctx *ctx, pat_eikonal_stats *out);
 
 /*
- * Delay table -> 16.16 fixed-point fractional sample index:
- * u = (T - t0) / dt computed in FP64; d_q = round-half-even(u * 65536) when T
- * is finite and 0 <= u <= N-1, else 0xFFFFFFFF.  n elements, N <= 65535.
+ * Delay table -> 16.16 fixed-point fractional sample index (a storage form of
+ * the delays t_{i,j} of Section II-C's back projection sum, not in the paper):
+ * u = (T - t0) / dt computed in FP64; d_q[s][p] = round-half-even(u * 65536)
+ * when T is finite and 0 <= u <= N-1, else 0xFFFFFFFF (no contribution).
+ *
+ *   d_table   float32 [S][P] seconds (pat_eikonal_tables).
+ *   d_q       uint32 [S][P] output; may not overlap d_table.
+ *   t0, dt    sampling of the frames the table will gather (finite t0, dt > 0);
+ *             2 <= N <= 65535 samples.
+ * Stream-ordered; PAT_EINVAL for negative sizes, bad sampling or null pointers
+ * (nothing launched).
  */
+int pat_table_to_fixed(pat_ctx *ctx, const float *d_table, int S, int P, double t0, double dt, int N,
+                       uint32_t *d_q, void *stream);
+/* The same conversion over n consecutive table entries (any [S][P] layout
+ * flattened; n = S*P gives pat_table_to_fixed). */
 int pat_table_to_q16(pat_ctx *ctx, const float *d_table, int64_t n, double t0, double dt, int N,
                      uint32_t *d_q, void *stream);
 
@@ -283,7 +304,7 @@ int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, doubl
  */
 int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
-                    int N, int F, double t0, double dt, float *d_img, void *stream);
+                    int N, double t0, double dt, int F, float *d_img, void *stream);
 
 /*
  * Conventional back projection (Section III's comparison reconstruction): the
@@ -333,7 +354,6 @@ typedef struct pat_server_config {
                                  memory; 0 = 80% of the free memory at creation */
     int table_fmt;            /* PAT_TABLE_F32, PAT_TABLE_Q16 or PAT_TABLE_R16, all maps
                                  (R16: pass the ROI in pat_tile_order order) */
-    int sig_fmt;              /* PAT_SIG_F32 or PAT_SIG_F16, all frames (raw p) */
     int max_batch;            /* frames per launch (0 = 64) */
     int max_inflight;         /* batches on the device at once (0 = 2, <= 8) */
     int max_slots;            /* frames submitted and not yet collected by
@@ -342,7 +362,7 @@ typedef struct pat_server_config {
 
 enum { PAT_MAP_BUILDING = 0, PAT_MAP_READY = 1, PAT_MAP_FAILED = 2, PAT_MAP_EVICTED = 3 };
 
-typedef struct pat_server_stats {
+typedef struct pat_stats {
     int64_t frames_submitted, frames_done, frames_refused, batches, builds, evictions;
     double mean_batch_frames;
     double frames_per_s, gathers_per_s;       /* completed frames over the window
@@ -350,11 +370,17 @@ typedef struct pat_server_stats {
     double latency_p50_us, latency_p99_us, latency_max_us;  /* submit -> image on host */
     uint64_t bytes_budget, bytes_used, bytes_tables;
     int maps_ready, maps_building, queue_depth, inflight_batches;
-} pat_server_stats;
+} pat_stats;
 
-/* Create a server on ctx's device (ctx is not used afterwards; the server owns
- * its streams, threads and a context for table builds).  cfg may be NULL. */
-int pat_server_create(pat_ctx *ctx, const pat_server_config *cfg, pat_server **out);
+/* Create a server on ctx's device with an HBM budget (device bytes for
+ * tables, frames and build working memory; 0 = 80% of the free memory at
+ * creation), float32 resident tables and the defaults of pat_server_config.
+ * ctx is not used afterwards; the server owns its streams, threads and a
+ * context for table builds.  PAT_EINVAL for a null out, PAT_EDEVICE or
+ * PAT_ENOMEM when its streams, events or threads cannot be created. */
+int pat_server_create(pat_ctx *ctx, size_t hbm_budget_bytes, pat_server **out);
+/* The same with every setting given (cfg may be NULL: all defaults). */
+int pat_server_create_ex(pat_ctx *ctx, const pat_server_config *cfg, pat_server **out);
 /* Waits for batches on the device, then frees everything. */
 int pat_server_destroy(pat_server *s);
 
@@ -378,18 +404,24 @@ int pat_server_map_state(pat_server *s, int map_id, int *state);
 /* Unregister an idle map (PAT_EBUSY while it has frames or a build). */
 int pat_server_remove_map(pat_server *s, int map_id);
 
-/* Submit one raw frame p[S][N] (float32 or binary16 per the config; value =
- * sample * scale for binary16, scale ignored for float32) for map_id.  The
- * frame is copied to pinned memory before returning.  When all slots are in
- * use: PAT_EBUSY if nonblocking, else wait for a slot.  *ticket identifies
- * the frame.  An evicted map is rebuilt on demand. */
-int pat_server_submit(pat_server *s, int map_id, const void *h_frame, float scale, int nonblocking,
+/* Submit one raw frame p[S][N] for map_id, host memory, in sig_fmt
+ * (PAT_SIG_F32, or PAT_SIG_F16 with value = sample * scale, scale finite and
+ * > 0; scale is ignored for float32).  Frames of both formats may be mixed;
+ * each launch gathers frames of one format.  The frame is copied to pinned
+ * memory before returning.  When all slots are in use: PAT_EBUSY if
+ * nonblocking, else wait for a slot.  *ticket identifies the frame.  An
+ * evicted map is rebuilt on demand.  PAT_ENOTFOUND for an unknown map,
+ * PAT_EINVAL for a bad format or scale, or float32 frames too large for the
+ * gather's 32-bit offsets. */
+int pat_server_submit(pat_server *s, int map_id, const void *h_frame, int sig_fmt, float scale, int nonblocking,
                       uint64_t *ticket);
 /* Wait for a frame and copy its image [P] to h_img (may be NULL); releases the
  * ticket.  timeout_ms < 0 waits forever; PAT_ETIMEOUT keeps the ticket. */
 int pat_server_wait(pat_server *s, uint64_t ticket, float *h_img, int timeout_ms);
 
-int pat_server_get_stats(pat_server *s, pat_server_stats *out);
+/* Counters, throughput (frames/s, gathers/s), p50/p99 latency and bytes
+ * resident, as of the call. */
+int pat_server_stats(pat_server *s, pat_stats *out);
 /* Restart the throughput window and the latency record. */
 int pat_server_reset_stats(pat_server *s);
 /* hold != 0: frames are still admitted and queued but none is launched;

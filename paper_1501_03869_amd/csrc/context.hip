@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -29,10 +30,28 @@ extern "C" const char *pat_last_error(void) { return g_err; }
 
 extern "C" int pat_version(void) { return 10000; }
 
+size_t pat_env_fault_alloc_bytes() {
+    const char *v = std::getenv("PAT_FAULT_ALLOC_BYTES");
+    if (!v || !*v) return 0;
+    char *end = nullptr;
+    const unsigned long long b = std::strtoull(v, &end, 10);
+    return (end && *end == 0) ? (size_t)b : 0;
+}
+
+long pat_env_round_cap(long builtin_cap) {
+    const char *v = std::getenv("PAT_EIK_ROUND_CAP");
+    if (!v || !*v) return builtin_cap;
+    char *end = nullptr;
+    const long r = std::strtol(v, &end, 10);
+    return (end && *end == 0 && r >= 1 && r < builtin_cap) ? r : builtin_cap;
+}
+
 int pat_devbuf::grow(size_t need) {
     if (need <= bytes) return PAT_OK;
     release();
     size_t b = std::max(need, (size_t)256);
+    if (fault_bytes && b >= fault_bytes)
+        return pat_fail(PAT_ENOMEM, "allocation of %zu bytes refused (PAT_FAULT_ALLOC_BYTES=%zu)", b, fault_bytes);
     hipError_t e = hipMalloc(&ptr, b);
     if (e != hipSuccess) {
         ptr = nullptr;
@@ -65,6 +84,10 @@ extern "C" int pat_ctx_create(int device, pat_ctx **out) {
     pat_ctx *c = new (std::nothrow) pat_ctx();
     if (!c) return pat_fail(PAT_ENOMEM, "host allocation failed");
     c->device = device;
+    const size_t fb = pat_env_fault_alloc_bytes();
+    for (pat_devbuf *b : { &c->gather_scratch, &c->gather_done, &c->sensors, &c->eik_tq, &c->eik_f, &c->eik_flags,
+                           &c->eik_lists, &c->eik_seeds, &c->eik_count })
+        b->fault_bytes = fb;
     hipError_t e = hipHostMalloc((void **)&c->eik_count_host, 4 * sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;
@@ -214,6 +237,15 @@ extern "C" int pat_table_to_q16(pat_ctx *ctx, const float *d_table, int64_t n, d
     return pat_launch_table_to_q16(d_table, n, t0, dt, N, d_q, (hipStream_t)stream);
 }
 
+extern "C" int pat_table_to_fixed(pat_ctx *ctx, const float *d_table, int S, int P, double t0, double dt, int N,
+                                  uint32_t *d_q, void *stream) {
+    if (S < 0 || P < 0) {
+        int rc = pat_make_current(ctx);
+        return rc ? rc : pat_fail(PAT_EINVAL, "negative size (S=%d P=%d)", S, P);
+    }
+    return pat_table_to_q16(ctx, d_table, (int64_t)S * P, t0, dt, N, d_q, stream);
+}
+
 extern "C" size_t pat_table_r16_bytes(int S, int P) {
     if (S <= 0 || P <= 0) return 0;
     return pat_r16_bytes(S, P);
@@ -233,7 +265,7 @@ extern "C" int pat_table_to_r16(pat_ctx *ctx, const float *d_table, int S, int P
 
 extern "C" int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
                                int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
-                               int N, int F, double t0, double dt, float *d_img, void *stream) {
+                               int N, double t0, double dt, int F, float *d_img, void *stream) {
     int rc = pat_make_current(ctx);
     if (rc) return rc;
     if (S < 0 || P < 0 || F < 0) return pat_fail(PAT_EINVAL, "negative size (S=%d P=%d F=%d)", S, P, F);

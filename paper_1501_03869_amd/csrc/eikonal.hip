@@ -301,7 +301,7 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
     PAT_HIP(hipMemsetAsync(ctx->eik_flags.ptr, 0, (size_t)2 * max_tiles * sizeof(uint32_t), st));
     PAT_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(uint32_t), st));
 
-    const long round_cap = 100L * (g.tiles_x + g.tiles_y) + 1000;
+    const long round_cap = pat_env_round_cap(100L * (g.tiles_x + g.tiles_y) + 1000);
     std::vector<int> hij((size_t)2 * chunk);
     std::vector<uint32_t> hval((size_t)chunk * SEED_BOX * SEED_BOX);
     std::vector<uint32_t> init_list;

@@ -317,7 +317,7 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
     PAT_HIP(hipMemsetAsync(ctx->eik_flags.ptr, 0, (size_t)2 * max_bricks * sizeof(uint32_t), st));
     PAT_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(uint32_t), st));
 
-    const long round_cap = 100L * (g.bx + g.by + g.bz) + 1000;
+    const long round_cap = pat_env_round_cap(100L * (g.bx + g.by + g.bz) + 1000);
     constexpr int B3 = SEED_BOX3 * SEED_BOX3 * SEED_BOX3;
     std::vector<int> hijl((size_t)3 * chunk);
     std::vector<uint32_t> hval((size_t)chunk * B3);

@@ -19,10 +19,20 @@ int pat_hip_fail(hipError_t e, const char *what);
         if (e_ != hipSuccess) return pat_hip_fail(e_, #call); \
     } while (0)
 
+// Failure-injection settings read from the environment (host only).
+// PAT_FAULT_ALLOC_BYTES=b, read when a context or server is created: that
+// object refuses every device allocation of b bytes or more as if the device
+// were out of memory (0 or unset: off).
+size_t pat_env_fault_alloc_bytes();
+// PAT_EIK_ROUND_CAP=r, read at each table-build call: the relaxation gives up
+// with PAT_ENOCONV after r rounds when r is below the built-in cap.
+long pat_env_round_cap(long builtin_cap);
+
 // Growable device buffer owned by a context.
 struct pat_devbuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    size_t fault_bytes = 0;  // injected failure threshold (0 = off)
     int grow(size_t need);  // PAT_OK or PAT_ENOMEM; contents are not preserved
     void release();
 };

@@ -68,6 +68,7 @@ struct Map {
 struct Frame {
     uint64_t ticket = 0;
     int map_id = 0;
+    int sig_fmt = PAT_SIG_F32;
     float scale = 1.0f;
     void *h_in = nullptr;
     size_t in_bytes = 0;
@@ -148,6 +149,7 @@ struct pat_server {
     std::deque<BatchSlot *> inflight;
 
     Pool dev_pool, host_pool;
+    size_t fault_bytes = 0;    // injected allocation failure threshold (PAT_FAULT_ALLOC_BYTES; 0 = off)
     size_t used = 0;           // device bytes in use or pooled (tables, frames, scratch, build reservation)
     size_t build_scratch = 0;  // bytes held by the builder's context
 
@@ -195,6 +197,7 @@ struct pat_server {
         void *p = dev_pool.get(bytes);
         if (p) return p;  // pooled bytes are already counted in `used`
         if (!make_room(bytes)) return nullptr;
+        if (fault_bytes && bytes >= fault_bytes) return nullptr;
         if (hipMalloc(&p, bytes) != hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
@@ -360,6 +363,7 @@ void pat_server::scheduler() {
     for (;;) {
         BatchSlot *slot = nullptr;
         std::vector<Frame *> batch;
+        int batch_fmt = -1;
         {
             std::unique_lock<std::mutex> lk(mu);
             for (;;) {
@@ -377,11 +381,14 @@ void pat_server::scheduler() {
                 if (slot && ready && !hold) break;
                 cv_sched.wait_for(lk, std::chrono::milliseconds(50));
             }
-            // take ready frames in arrival order while device memory allows
+            // take ready frames in arrival order while device memory allows; one
+            // launch gathers one signal format, that of the oldest ready frame
+            batch_fmt = -1;
             for (auto it = pending.begin(); it != pending.end() && (int)batch.size() < cfg.max_batch;) {
                 Frame *f = *it;
                 Map *m = maps[f->map_id].get();
-                if (m->state != MAP_READY) { ++it; continue; }
+                if (m->state != MAP_READY || (batch_fmt >= 0 && f->sig_fmt != batch_fmt)) { ++it; continue; }
+                batch_fmt = f->sig_fmt;
                 f->d_in = dev_alloc(f->in_bytes);
                 f->d_out = f->d_in ? static_cast<float *>(dev_alloc(f->out_bytes)) : nullptr;
                 if (!f->d_in || !f->d_out) {
@@ -417,7 +424,7 @@ void pat_server::scheduler() {
                 d.sig = f->d_in;
                 d.w = nullptr;
                 d.img = f->d_out;
-                d.scale = cfg.sig_fmt == PAT_SIG_F16 ? f->scale : 1.0f;
+                d.scale = f->sig_fmt == PAT_SIG_F16 ? f->scale : 1.0f;
                 d.block_begin = blocks;
                 blocks += nb;
             }
@@ -441,7 +448,7 @@ void pat_server::scheduler() {
                 if (hipMemcpyAsync(f->d_in, f->h_in, f->in_bytes, hipMemcpyHostToDevice, st) != hipSuccess) rc = PAT_EDEVICE;
             if (hipMemcpyAsync(slot->d_desc, slot->h_desc, sizeof(pat_bp_desc) * nd, hipMemcpyHostToDevice, st) != hipSuccess)
                 rc = PAT_EDEVICE;
-            if (rc == PAT_OK) rc = pat_launch_px_multi(slot->d_desc, nd, blocks, cfg.table_fmt, cfg.sig_fmt, st);
+            if (rc == PAT_OK) rc = pat_launch_px_multi(slot->d_desc, nd, blocks, cfg.table_fmt, batch_fmt, st);
             for (Frame *f : batch)
                 if (rc == PAT_OK && hipMemcpyAsync(f->h_out, f->d_out, f->out_bytes, hipMemcpyDeviceToHost, st) != hipSuccess)
                     rc = PAT_EDEVICE;
@@ -524,7 +531,7 @@ void pat_server::completion() {
 
 // ----------------------------------------------------------------------------- C ABI
 
-extern "C" int pat_server_create(pat_ctx *ctx, const pat_server_config *cfg, pat_server **out) {
+extern "C" int pat_server_create_ex(pat_ctx *ctx, const pat_server_config *cfg, pat_server **out) {
     int rc = pat_make_current(ctx);
     if (rc) return rc;
     if (!out) return pat_fail(PAT_EINVAL, "out is NULL");
@@ -533,7 +540,6 @@ extern "C" int pat_server_create(pat_ctx *ctx, const pat_server_config *cfg, pat
     if (cfg) c = *cfg;
     if (c.table_fmt != PAT_TABLE_F32 && c.table_fmt != PAT_TABLE_Q16 && c.table_fmt != PAT_TABLE_R16)
         return pat_fail(PAT_EINVAL, "bad table format");
-    if (c.sig_fmt != PAT_SIG_F32 && c.sig_fmt != PAT_SIG_F16) return pat_fail(PAT_EINVAL, "bad signal format");
     if (c.max_batch <= 0) c.max_batch = 64;
     if (c.max_inflight <= 0) c.max_inflight = 2;
     if (c.max_slots <= 0) c.max_slots = 1024;
@@ -549,6 +555,7 @@ extern "C" int pat_server_create(pat_ctx *ctx, const pat_server_config *cfg, pat
     s->device = ctx->device;
     s->cfg = c;
     s->host_pool.host = true;
+    s->fault_bytes = pat_env_fault_alloc_bytes();
     if ((rc = pat_ctx_create(ctx->device, &s->build_ctx))) return rc;
     auto cleanup = [&]() {
         for (auto &sl : s->slots)
@@ -582,6 +589,13 @@ extern "C" int pat_server_create(pat_ctx *ctx, const pat_server_config *cfg, pat
     s->th_build = std::thread([p = s.get()] { p->builder(); });
     *out = s.release();
     return PAT_OK;
+}
+
+extern "C" int pat_server_create(pat_ctx *ctx, size_t hbm_budget_bytes, pat_server **out) {
+    pat_server_config c{};
+    c.hbm_budget_bytes = hbm_budget_bytes;
+    c.table_fmt = PAT_TABLE_F32;
+    return pat_server_create_ex(ctx, &c, out);
 }
 
 extern "C" int pat_server_destroy(pat_server *s) {
@@ -633,7 +647,7 @@ static int add_map(pat_server *s, const float *h_speed, int nx, int ny, int nz, 
                              : nx >= 2 && ny >= 2;
     if (!grid_ok || !(h > 0) || S <= 0 || P <= 0 || N < 4 || !(dt > 0) || !std::isfinite(t0))
         return pat_fail(PAT_EINVAL, "bad map geometry");
-    if (!pat_px_multi_eligible(s->cfg.sig_fmt, S, P, N))
+    if (!pat_px_multi_eligible(PAT_SIG_F16, S, P, N))
         return pat_fail(PAT_EINVAL, "map too large for the frame server (S*P or S*N beyond 32-bit offsets)");
     if (!h_speed || !h_sensor || !h_pix) return pat_fail(PAT_EINVAL, "null map data");
     if (s->cfg.table_fmt != PAT_TABLE_F32 && N > 65535)
@@ -695,16 +709,20 @@ extern "C" int pat_server_map_state(pat_server *s, int map_id, int *state) {
     return PAT_OK;
 }
 
-extern "C" int pat_server_submit(pat_server *s, int map_id, const void *h_frame, float scale, int nonblocking,
-                                 uint64_t *ticket) {
+extern "C" int pat_server_submit(pat_server *s, int map_id, const void *h_frame, int sig_fmt, float scale,
+                                 int nonblocking, uint64_t *ticket) {
     if (!s || !h_frame || !ticket) return pat_fail(PAT_EINVAL, "null argument");
-    if (!(std::isfinite(scale) && scale > 0)) return pat_fail(PAT_EINVAL, "scale must be finite and > 0");
+    if (sig_fmt != PAT_SIG_F32 && sig_fmt != PAT_SIG_F16) return pat_fail(PAT_EINVAL, "unknown signal format %d", sig_fmt);
+    if (sig_fmt == PAT_SIG_F16 && !(std::isfinite(scale) && scale > 0))
+        return pat_fail(PAT_EINVAL, "scale must be finite and > 0");
     std::unique_lock<std::mutex> lk(s->mu);
     auto it = s->maps.find(map_id);
     if (it == s->maps.end() || it->second->removed) return pat_fail(PAT_ENOTFOUND, "unknown map %d", map_id);
     Map *m = it->second.get();
     if (m->state == MAP_FAILED) return pat_fail(m->err ? m->err : PAT_EDEVICE, "map %d failed to build", map_id);
-    const size_t esz = s->cfg.sig_fmt == PAT_SIG_F16 ? 2 : 4;
+    if (!pat_px_multi_eligible(sig_fmt, m->S, m->P, m->N))
+        return pat_fail(PAT_EINVAL, "float32 frames of map %d exceed the gather's 32-bit offsets", map_id);
+    const size_t esz = sig_fmt == PAT_SIG_F16 ? 2 : 4;
     const size_t in_b = (size_t)m->S * m->N * esz, out_b = (size_t)m->P * 4;
     if (in_b + out_b > s->cfg.hbm_budget_bytes) return pat_fail(PAT_EINVAL, "frame larger than the HBM budget");
     if (s->frames_in_system >= s->cfg.max_slots) {
@@ -728,7 +746,8 @@ extern "C" int pat_server_submit(pat_server *s, int map_id, const void *h_frame,
     auto f = std::make_unique<Frame>();
     f->ticket = s->next_ticket++;
     f->map_id = map_id;
-    f->scale = scale;
+    f->sig_fmt = sig_fmt;
+    f->scale = sig_fmt == PAT_SIG_F16 ? scale : 1.0f;
     f->h_in = hin;
     f->in_bytes = in_b;
     f->h_out = static_cast<float *>(hout);
@@ -783,10 +802,10 @@ extern "C" int pat_server_remove_map(pat_server *s, int map_id) {
     return PAT_OK;
 }
 
-extern "C" int pat_server_get_stats(pat_server *s, pat_server_stats *out) {
+extern "C" int pat_server_stats(pat_server *s, pat_stats *out) {
     if (!s || !out) return pat_fail(PAT_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(s->mu);
-    pat_server_stats r{};
+    pat_stats r{};
     r.frames_submitted = s->st_submitted;
     r.frames_done = s->st_done;
     r.frames_refused = s->st_refused;

@@ -22,12 +22,13 @@ SIG_F32, SIG_F16 = 0, 1
 
 EXPORTED = [
     "pat_last_error", "pat_version", "pat_ctx_create", "pat_ctx_destroy", "pat_ctx_reserve",
-    "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_o2", "pat_eikonal_tables_3d", "pat_eikonal_last_stats", "pat_table_to_q16", "pat_table_to_r16", "pat_table_r16_bytes",
-    "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_const", "pat_backproject_const_3d",
-    "pat_server_create", "pat_server_destroy", "pat_server_add_map", "pat_server_add_map_3d", "pat_server_map_state",
-    "pat_server_remove_map", "pat_server_submit", "pat_server_wait", "pat_server_get_stats",
-    "pat_server_reset_stats",
-    "pat_server_hold",
+    "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_o2", "pat_eikonal_tables_3d",
+    "pat_eikonal_last_stats", "pat_table_to_fixed", "pat_table_to_q16", "pat_table_to_r16", "pat_table_r16_bytes",
+    "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_const",
+    "pat_backproject_const_3d",
+    "pat_server_create", "pat_server_create_ex", "pat_server_destroy", "pat_server_add_map", "pat_server_add_map_3d",
+    "pat_server_map_state", "pat_server_remove_map", "pat_server_submit", "pat_server_wait", "pat_server_stats",
+    "pat_server_reset_stats", "pat_server_hold",
 ]
 MAP_BUILDING, MAP_READY, MAP_FAILED, MAP_EVICTED = 0, 1, 2, 3
 
@@ -39,8 +40,8 @@ class PatError(RuntimeError):
 
 
 class ServerConfig(C.Structure):
-    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("table_fmt", C.c_int), ("sig_fmt", C.c_int),
-                ("max_batch", C.c_int), ("max_inflight", C.c_int), ("max_slots", C.c_int)]
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("table_fmt", C.c_int), ("max_batch", C.c_int),
+                ("max_inflight", C.c_int), ("max_slots", C.c_int)]
 
 
 class ServerStats(C.Structure):
@@ -81,6 +82,7 @@ def lib() -> C.CDLL:
         L.pat_eikonal_tables_o2.argtypes = [vp, vp, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
         L.pat_eikonal_tables_3d.argtypes = [vp, vp, i32, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
         L.pat_eikonal_last_stats.argtypes = [vp, C.POINTER(EikonalStats)]
+        L.pat_table_to_fixed.argtypes = [vp, vp, i32, i32, dbl, dbl, i32, vp, vp]
         L.pat_table_to_q16.argtypes = [vp, vp, i64, dbl, dbl, i32, vp, vp]
         L.pat_table_to_r16.argtypes = [vp, vp, i32, i32, dbl, dbl, i32, vp, vp]
         L.pat_table_r16_bytes.argtypes = [i32, i32]
@@ -88,20 +90,21 @@ def lib() -> C.CDLL:
         L.pat_tile_order.argtypes = [i32, i32, vp, i32, i32, i32, vp]
         L.pat_tile_order_3d.argtypes = [i32, i32, i32, vp, i32, i32, i32, i32, vp]
         L.pat_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp]
-        L.pat_backproject.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp, i32, i32, i32, i32, dbl, dbl, vp, vp]
+        L.pat_backproject.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp, i32, i32, i32, dbl, dbl, i32, vp, vp]
         L.pat_backproject_const.argtypes = [vp, i32, i32, dbl, dbl, vp, i32, vp, i32, vp, i32, i32, vp, vp, i32, i32,
                                             dbl, dbl, vp, vp]
         L.pat_backproject_const_3d.argtypes = [vp, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, vp, i32, i32, vp, vp,
                                                i32, i32, dbl, dbl, vp, vp]
-        L.pat_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
+        L.pat_server_create.argtypes = [vp, sz, C.POINTER(vp)]
+        L.pat_server_create_ex.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
         L.pat_server_destroy.argtypes = [vp]
         L.pat_server_add_map.argtypes = [vp, vp, i32, i32, dbl, vp, i32, vp, i32, dbl, dbl, i32, C.POINTER(i32)]
         L.pat_server_add_map_3d.argtypes = [vp, vp, i32, i32, i32, dbl, vp, i32, vp, i32, dbl, dbl, i32, C.POINTER(i32)]
         L.pat_server_map_state.argtypes = [vp, i32, C.POINTER(i32)]
         L.pat_server_remove_map.argtypes = [vp, i32]
-        L.pat_server_submit.argtypes = [vp, i32, vp, C.c_float, i32, C.POINTER(C.c_uint64)]
+        L.pat_server_submit.argtypes = [vp, i32, vp, i32, C.c_float, i32, C.POINTER(C.c_uint64)]
         L.pat_server_wait.argtypes = [vp, C.c_uint64, vp, i32]
-        L.pat_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.pat_server_stats.argtypes = [vp, C.POINTER(ServerStats)]
         L.pat_server_reset_stats.argtypes = [vp]
         L.pat_server_hold.argtypes = [vp, i32]
         _lib = L
@@ -218,13 +221,19 @@ class Context:
         return {k: getattr(st, k) for k, _ in EikonalStats._fields_}
 
     def table_to_q16(self, table, dt: float, N: int, t0: float = 0.0, out=None, stream=None):
+        """16.16 sample-index table (pat_table_to_fixed) of a float32 [S][P] table, as int32 bits."""
         import torch
         _need(table, torch.float32, "table")
         if out is None:
             out = torch.empty(table.shape, dtype=torch.int32, device=table.device)
         _need(out, torch.int32, "out")
-        check(lib().pat_table_to_q16(self.h, _ptr(table), table.numel(), float(t0), float(dt), int(N), _ptr(out),
-                                     _stream(stream)))
+        if table.dim() == 2:
+            S, P = table.shape
+            check(lib().pat_table_to_fixed(self.h, _ptr(table), S, P, float(t0), float(dt), int(N), _ptr(out),
+                                           _stream(stream)))
+        else:
+            check(lib().pat_table_to_q16(self.h, _ptr(table), table.numel(), float(t0), float(dt), int(N),
+                                         _ptr(out), _stream(stream)))
         return out
 
     def table_to_r16(self, table, dt: float, N: int, t0: float = 0.0, stream=None) -> "R16Table":
@@ -273,7 +282,7 @@ class Context:
             out = torch.empty((P,) if single else (F, P), dtype=torch.float32, device=table.device)
         _need(out, torch.float32, "out")
         check(lib().pat_backproject(self.h, _ptr(table), tfmt, _ptr(sig), sfmt, 1 if filtered else 0,
-                                    _ptr(frame_scale), _ptr(w), S, P, N, F, float(t0), float(dt), _ptr(out),
+                                    _ptr(frame_scale), _ptr(w), S, P, N, float(t0), float(dt), F, _ptr(out),
                                     _stream(stream)))
         return out
 
@@ -388,11 +397,17 @@ class Server:
     """Frame server (resident tables, continuous mixed-geometry batching)."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes: int = 0, table_fmt: int = TABLE_F32, sig_fmt: int = SIG_F32,
-                 max_batch: int = 0, max_inflight: int = 0, max_slots: int = 0):
-        cfg = ServerConfig(int(hbm_budget_bytes), int(table_fmt), int(sig_fmt), int(max_batch), int(max_inflight),
-                           int(max_slots))
+                 max_batch: int = 0, max_inflight: int = 0, max_slots: int = 0, budget_only: bool = False):
+        """sig_fmt is the default format of submitted frames (submit may override
+        it per frame).  budget_only: create through pat_server_create (HBM budget
+        only, float32 tables, defaults for the rest)."""
         h = C.c_void_p()
-        check(lib().pat_server_create(ctx.h, C.byref(cfg), C.byref(h)))
+        if budget_only:
+            check(lib().pat_server_create(ctx.h, C.c_size_t(int(hbm_budget_bytes)), C.byref(h)))
+        else:
+            cfg = ServerConfig(int(hbm_budget_bytes), int(table_fmt), int(max_batch), int(max_inflight),
+                               int(max_slots))
+            check(lib().pat_server_create_ex(ctx.h, C.byref(cfg), C.byref(h)))
         self.h = h
         self.sig_fmt = sig_fmt
         self._geo = {}
@@ -444,16 +459,18 @@ class Server:
     def remove_map(self, map_id: int):
         check(lib().pat_server_remove_map(self.h, int(map_id)))
 
-    def submit(self, map_id: int, frame: np.ndarray, scale: float = 1.0, nonblocking: bool = False) -> int:
-        want = np.float16 if self.sig_fmt == SIG_F16 else np.float32
+    def submit(self, map_id: int, frame: np.ndarray, scale: float = 1.0, nonblocking: bool = False,
+               sig_fmt: int | None = None) -> int:
+        fmt = self.sig_fmt if sig_fmt is None else int(sig_fmt)
+        want = np.float16 if fmt == SIG_F16 else np.float32
         f = np.ascontiguousarray(frame, dtype=want)
         if map_id in self._geo:  # unknown ids are reported by the library
             S, P, N = self._geo[map_id]
             if f.shape != (S, N):
                 raise ValueError(f"frame must be {(S, N)}, got {f.shape}")
         t = C.c_uint64()
-        check(lib().pat_server_submit(self.h, int(map_id), f.ctypes.data, C.c_float(scale), 1 if nonblocking else 0,
-                                      C.byref(t)))
+        check(lib().pat_server_submit(self.h, int(map_id), f.ctypes.data, fmt, C.c_float(scale),
+                                      1 if nonblocking else 0, C.byref(t)))
         return t.value
 
     def wait(self, ticket: int, map_id: int | None = None, P: int | None = None, timeout_ms: int = -1):
@@ -465,7 +482,7 @@ class Server:
 
     def stats(self) -> dict:
         st = ServerStats()
-        check(lib().pat_server_get_stats(self.h, C.byref(st)))
+        check(lib().pat_server_stats(self.h, C.byref(st)))
         return {k: getattr(st, k) for k, _ in ServerStats._fields_}
 
     def reset_stats(self):

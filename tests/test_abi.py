@@ -114,3 +114,53 @@ def test_scratch_size_is_host_only():
     assert b >= 2 * 21336 * 4
     # one sensor group needs no scratch
     assert pat.backproject_scratch_bytes(8, 1 << 20, 1) == 0
+
+
+# The boundary's named calls (the operations of Sections II-B, II-C and III:
+# per-sensor tables, their 16.16 form, the filter, the back projection sum and
+# the offline/online frame server) with their parameter types in order.
+BOUNDARY = {
+    "pat_last_error": ["void"],
+    "pat_ctx_create": ["int", "pat_ctx**"],
+    "pat_ctx_destroy": ["pat_ctx*"],
+    "pat_eikonal_tables": ["pat_ctx*", "const float*", "int", "int", "double", "const double*", "int",
+                           "const int32_t*", "int", "float*", "void*"],
+    "pat_table_to_fixed": ["pat_ctx*", "const float*", "int", "int", "double", "double", "int", "uint32_t*",
+                           "void*"],
+    "pat_tile_order": ["int", "int", "const int32_t*", "int", "int", "int", "int32_t*"],
+    "pat_filter": ["pat_ctx*", "const float*", "int", "int", "double", "double", "float*", "void*"],
+    "pat_backproject": ["pat_ctx*", "const void*", "int", "const void*", "int", "int", "const float*",
+                        "const float*", "int", "int", "int", "double", "double", "int", "float*", "void*"],
+    "pat_server_create": ["pat_ctx*", "size_t", "pat_server**"],
+    "pat_server_add_map": ["pat_server*", "const float*", "int", "int", "double", "const double*", "int",
+                           "const int32_t*", "int", "double", "double", "int", "int*"],
+    "pat_server_submit": ["pat_server*", "int", "const void*", "int", "float", "int", "uint64_t*"],
+    "pat_server_wait": ["pat_server*", "uint64_t", "float*", "int"],
+    "pat_server_stats": ["pat_server*", "pat_stats*"],
+    "pat_server_remove_map": ["pat_server*", "int"],
+    "pat_server_destroy": ["pat_server*"],
+}
+
+
+def _declared_params():
+    txt = open(os.path.join(ROOT, "include", "pat.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(pat_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", txt):
+        params = []
+        for p in m.group(2).split(","):
+            p = " ".join(p.replace("*", " * ").split())
+            words = p.split(" ")
+            if words != ["void"]:
+                words = words[:-1]  # drop the parameter name
+            params.append(" ".join(words).replace(" *", "*"))
+        out[m.group(1)] = params
+    return out
+
+
+def test_boundary_calls_exported_with_their_signatures():
+    L = pat.lib()
+    decl = _declared_params()
+    for name, params in BOUNDARY.items():
+        assert hasattr(L, name), name
+        assert decl.get(name) == params, (name, decl.get(name))

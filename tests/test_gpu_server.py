@@ -239,3 +239,41 @@ def test_server_3d_map(ctx, orc):
         print(f"[server 3d] rel L2 vs single launch {e1:.3e}, vs oracle pipeline {e2:.3e}", flush=True)
         assert e1 <= 1e-5
         assert e2 <= 2e-3
+
+
+def test_budget_create_and_mixed_signal_formats(ctx, orc):
+    # pat_server_create with an HBM budget only; float32 and binary16 frames
+    # of two maps submitted together: each launch takes one format, and every
+    # image equals the same frame submitted alone, bit for bit
+    from paper_1501_03869_amd import pat
+    geos = _maps()[:2]
+    tabs = _oracle_tables(orc, geos)
+    frames = _frames(geos, tabs, 3)
+    srv = pat.Server(ctx, hbm_budget_bytes=2 << 30, budget_only=True)
+    try:
+        ids = _add_all(srv, geos)
+        enc = []
+        for k, (gi, p) in enumerate(frames):
+            if k % 2:
+                sc = float(np.abs(p).max() / 2.0 ** 14)
+                enc.append((gi, (p / sc).astype(np.float16), sc, pat.SIG_F16))
+            else:
+                enc.append((gi, p, 1.0, pat.SIG_F32))
+        alone = [srv.wait(srv.submit(ids[gi], p, sc, sig_fmt=fmt), ids[gi], timeout_ms=WAIT_MS)
+                 for gi, p, sc, fmt in enc]
+        srv.reset_stats()
+        b0 = srv.stats()["batches"]
+        srv.hold(True)
+        tickets = [srv.submit(ids[gi], p, sc, sig_fmt=fmt) for gi, p, sc, fmt in enc]
+        srv.hold(False)
+        mixed = [srv.wait(t, ids[gi], timeout_ms=WAIT_MS) for t, (gi, _, _, _) in zip(tickets, enc)]
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["bytes_budget"] == 2 << 30
+    assert st["batches"] - b0 == 2  # one launch per signal format
+    for k, (gi, p) in enumerate(frames):
+        assert np.array_equal(alone[k], mixed[k]), k
+        ref = orc.backproject(tabs[gi], p, geos[gi].dt, geos[gi].t0)
+        err = np.linalg.norm(mixed[k] - ref) / np.linalg.norm(ref)
+        assert err <= (2e-3 if k % 2 == 0 else 5e-3), (k, err)
