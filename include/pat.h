@@ -306,6 +306,32 @@ int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void
                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
                     int N, double t0, double dt, int F, float *d_img, void *stream);
 
+/* Bytes of the fixed device scratch of pat_backproject_noalloc (16 MiB per
+ * device, held from the library's load until the process ends). */
+#define PAT_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/*
+ * pat_backproject for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels, kernel choice and results (bit for bit) as
+ * pat_backproject, but the gather scratch (partial sums and completion
+ * counters of the LDS-windowed and batched kernels) comes from a fixed array
+ * of PAT_NOALLOC_SCRATCH_BYTES in device memory, one per device, instead of
+ * the context's growable buffers: the call makes no hipMalloc, hipFree or
+ * other allocating call.  The counters are cleared by a small kernel on
+ * `stream` before the gather (no memset node).  PAT_EINVAL, with nothing
+ * launched, when the sizes need more scratch than the array holds: at most
+ * 4 ceil(P/256) F bytes of counters rounded up to a multiple of 256, plus
+ * pat_backproject_scratch_bytes(S, P, F); shapes that take the split-sensor
+ * kernel need none.  All calls on one device share that
+ * device's array, which keeps the last call's contents: calls that overlap
+ * on one device (different streams, contexts or threads) race on it and must
+ * be serialised by the caller.
+ */
+int pat_backproject_noalloc(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
+                            int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
+                            int N, double t0, double dt, int F, float *d_img, void *stream);
+
 /*
  * Conventional back projection (Section III's comparison reconstruction): the
  * same filtered delay-and-sum as pat_backproject, with the straight-ray delay

@@ -93,6 +93,14 @@ extern "C" int pat_ctx_create(int device, pat_ctx **out) {
         delete c;
         return pat_hip_fail(e, "hipHostMalloc");
     }
+    // the device's fixed scratch array (pat_backproject_noalloc), looked up
+    // once per device with this device current
+    int rc = pat_fixed_scratch_attach(device, &c->fixed_scratch);
+    if (rc) {
+        (void)hipHostFree(c->eik_count_host);
+        delete c;
+        return rc;
+    }
     *out = c;
     return PAT_OK;
 }
@@ -122,7 +130,7 @@ extern "C" int pat_ctx_reserve(pat_ctx *ctx, int S, int P, int F) {
     if (S == 0 || P == 0 || F == 0) return PAT_OK;
     float *part;
     unsigned int *done;
-    return pat_gather_scratch(ctx, P, F, pat_backproject_scratch_bytes(S, P, F), &part, &done);
+    return pat_gather_scratch(ctx, P, F, pat_backproject_scratch_bytes(S, P, F), &part, &done, nullptr);
 }
 
 extern "C" int pat_eikonal_last_stats(pat_ctx *ctx, pat_eikonal_stats *out) {
@@ -263,9 +271,10 @@ extern "C" int pat_table_to_r16(pat_ctx *ctx, const float *d_table, int S, int P
     return pat_launch_table_to_r16(d_table, S, P, t0, dt, N, d_out, (hipStream_t)stream);
 }
 
-extern "C" int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
-                               int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
-                               int N, double t0, double dt, int F, float *d_img, void *stream) {
+// Checks shared by pat_backproject and pat_backproject_noalloc: PAT_OK to
+// launch, 1 when there is nothing to do, else a negative status.
+static int backproject_args(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt, int S,
+                            int P, int N, double t0, double dt, int F, float *d_img) {
     int rc = pat_make_current(ctx);
     if (rc) return rc;
     if (S < 0 || P < 0 || F < 0) return pat_fail(PAT_EINVAL, "negative size (S=%d P=%d F=%d)", S, P, F);
@@ -277,9 +286,33 @@ extern "C" int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt,
     if (!finite_pos(dt) || !std::isfinite(t0)) return pat_fail(PAT_EINVAL, "need finite t0 and dt > 0");
     if ((long long)S * N > INT32_MAX || (long long)S * P > ((long long)1 << 40))
         return pat_fail(PAT_EINVAL, "sizes too large");
-    if (P == 0 || F == 0) return PAT_OK;
+    if (P == 0 || F == 0) return 1;
     if (!d_img) return pat_fail(PAT_EINVAL, "null image pointer");
     if (S > 0 && (!d_table || !d_sig)) return pat_fail(PAT_EINVAL, "null table or signal pointer");
+    return PAT_OK;
+}
+
+extern "C" int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
+                               int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
+                               int N, double t0, double dt, int F, float *d_img, void *stream) {
+    int rc = backproject_args(ctx, d_table, table_fmt, d_sig, sig_fmt, S, P, N, t0, dt, F, d_img);
+    if (rc) return rc > 0 ? PAT_OK : rc;
+    return pat_launch_backproject(ctx, d_table, table_fmt, d_sig, sig_fmt, sig_is_filtered, d_frame_scale, d_w, S, P,
+                                  N, F, t0, dt, d_img, (hipStream_t)stream);
+}
+
+extern "C" int pat_backproject_noalloc(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig,
+                                       int sig_fmt, int sig_is_filtered, const float *d_frame_scale, const float *d_w,
+                                       int S, int P, int N, double t0, double dt, int F, float *d_img, void *stream) {
+    int rc = backproject_args(ctx, d_table, table_fmt, d_sig, sig_fmt, S, P, N, t0, dt, F, d_img);
+    if (rc) return rc > 0 ? PAT_OK : rc;
+    // the same kernels as pat_backproject; their scratch comes from the
+    // device's fixed array for the duration of this call
+    struct Fixed {
+        pat_ctx *c;
+        explicit Fixed(pat_ctx *x) : c(x) { c->fixed_active = true; }
+        ~Fixed() { c->fixed_active = false; }
+    } fixed(ctx);
     return pat_launch_backproject(ctx, d_table, table_fmt, d_sig, sig_fmt, sig_is_filtered, d_frame_scale, d_w, S, P,
                                   N, F, t0, dt, d_img, (hipStream_t)stream);
 }

@@ -21,6 +21,7 @@
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "gather_common.h"
 #include "pat_internal.h"
@@ -453,8 +454,56 @@ size_t pat_gather_counter_bytes(int P, int F) {
     return ((((size_t)(P + 255) / 256) * (size_t)F * sizeof(unsigned int) + 255) / 256) * 256;
 }
 
-int pat_gather_scratch(pat_ctx *ctx, int P, int F, size_t part_bytes, float **part, unsigned int **done) {
+// Fixed device scratch of the allocation-free entry point
+// (pat_backproject_noalloc): the completion counters at byte 0, then the
+// partial sums.  Each device holds its own copy from module load to process
+// end; host code reaches it only through the address hipGetSymbolAddress
+// gives on that device.
+static __device__ __align__(256) unsigned char scratch[PAT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void *g_fixed_ptr[kMaxDevices] = {};
+}  // namespace
+
+int pat_fixed_scratch_attach(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices)
+        return pat_fail(PAT_EINVAL, "device %d beyond the %d the fixed scratch table holds", device, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_fixed_mu);
+    if (!g_fixed_ptr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return pat_hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        }
+        g_fixed_ptr[device] = p;
+    }
+    *out = g_fixed_ptr[device];
+    return PAT_OK;
+}
+
+int pat_gather_scratch(pat_ctx *ctx, int P, int F, size_t part_bytes, float **part, unsigned int **done,
+                       hipStream_t st) {
     const size_t cb = pat_gather_counter_bytes(P, F);
+    if (ctx->fixed_active) {
+        // the device's fixed array: nothing is allocated; the counters are
+        // cleared by a kernel on the call's stream (a call may be captured)
+        if (!ctx->fixed_scratch) return pat_fail(PAT_EDEVICE, "fixed scratch not attached to this context");
+        if (cb > PAT_NOALLOC_SCRATCH_BYTES || part_bytes > PAT_NOALLOC_SCRATCH_BYTES - cb)
+            return pat_fail(PAT_EINVAL,
+                            "these sizes need %zu bytes of gather scratch (%zu counters + %zu partial sums); the fixed "
+                            "scratch holds %zu (use pat_backproject)",
+                            cb + part_bytes, cb, part_bytes, (size_t)PAT_NOALLOC_SCRATCH_BYTES);
+        unsigned char *base = static_cast<unsigned char *>(ctx->fixed_scratch);
+        int rc = launch_zero(reinterpret_cast<float *>(base), (long)(cb / sizeof(float)), st);
+        if (rc) return rc;
+        *done = reinterpret_cast<unsigned int *>(base);
+        *part = reinterpret_cast<float *>(base + cb);
+        return PAT_OK;
+    }
     if (cb > ctx->gather_done.bytes) {
         int rc = ctx->gather_done.grow(cb);
         if (rc) return rc;
@@ -509,7 +558,7 @@ int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const
     float *part = nullptr;
     unsigned int *done = nullptr;
     if (sh.groups > 1) {
-        int rc = pat_gather_scratch(ctx, P, F, single_part_bytes(S, P, F), &part, &done);
+        int rc = pat_gather_scratch(ctx, P, F, single_part_bytes(S, P, F), &part, &done, st);
         if (rc) return rc;
     }
     const dim3 grid(sh.chunks, sh.groups, F);
@@ -549,7 +598,7 @@ int pat_launch_backproject_const(pat_ctx *ctx, int nx, int ny, double h, double 
     float *part = nullptr;
     unsigned int *done = nullptr;
     if (sh.groups > 1) {
-        int rc = pat_gather_scratch(ctx, P, F, single_part_bytes(S, P, F), &part, &done);
+        int rc = pat_gather_scratch(ctx, P, F, single_part_bytes(S, P, F), &part, &done, st);
         if (rc) return rc;
     }
     DelayF32 d;

@@ -360,7 +360,7 @@ int pat_launch_backproject_batch(pat_ctx *ctx, const void *table, int table_fmt,
     float *part = nullptr;
     unsigned int *done = nullptr;
     if (sh.groups > 1) {
-        int rc = pat_gather_scratch(ctx, P, F, pat_batch_part_bytes(S, P, F), &part, &done);
+        int rc = pat_gather_scratch(ctx, P, F, pat_batch_part_bytes(S, P, F), &part, &done, st);
         if (rc) return rc;
     }
     const dim3 grid(sh.chunks, sh.fgroups, sh.groups);

@@ -49,6 +49,10 @@ struct pat_ctx {
     pat_devbuf eik_tq, eik_f, eik_flags, eik_lists, eik_seeds, eik_count;
     uint32_t *eik_count_host = nullptr;  // pinned: next-round count, guard hits, sweeps (64-bit)
     pat_eikonal_stats last_eik{};
+    // the device's fixed scratch array (pat_backproject_noalloc), and whether
+    // the call in progress takes its gather scratch from there
+    void *fixed_scratch = nullptr;
+    bool fixed_active = false;
 };
 
 int pat_make_current(pat_ctx *ctx);
@@ -103,7 +107,14 @@ int pat_launch_backproject_px_const(int nx, double h, double c, const float *d_s
 int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig, int sig_fmt, int sig_is_filtered,
                               const float *frame_scale, const float *w, int S, int P, int N, int F, double t0,
                               double dt, float *img, hipStream_t st);
-int pat_gather_scratch(pat_ctx *ctx, int P, int F, size_t part_bytes, float **part, unsigned int **done);
+// Partial sums and zeroed completion counters for one gather launch on st:
+// from the context's growable buffers, or, while ctx->fixed_active, from the
+// device's fixed array (counters cleared on st; PAT_EINVAL when they do not fit).
+int pat_gather_scratch(pat_ctx *ctx, int P, int F, size_t part_bytes, float **part, unsigned int **done,
+                       hipStream_t st);
+// Device address of the fixed scratch array on `device` (which must be
+// current), looked up once per device.
+int pat_fixed_scratch_attach(int device, void **out);
 size_t pat_batch_part_bytes(int S, int P, int F);
 bool pat_batch_eligible(int sig_fmt, int N, int F, const void *sig);
 int pat_launch_backproject_batch(pat_ctx *ctx, const void *table, int table_fmt, const void *sig, int sig_fmt,

@@ -16,6 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpat.so")
 
+NOALLOC_SCRATCH_BYTES = 16 << 20  # PAT_NOALLOC_SCRATCH_BYTES
 PAT_OK, PAT_EINVAL, PAT_ENOMEM, PAT_EDEVICE, PAT_EBUSY, PAT_ENOTFOUND, PAT_ETIMEOUT, PAT_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
 TABLE_F32, TABLE_Q16, TABLE_R16 = 0, 1, 2
 SIG_F32, SIG_F16 = 0, 1
@@ -24,7 +25,8 @@ EXPORTED = [
     "pat_last_error", "pat_version", "pat_ctx_create", "pat_ctx_destroy", "pat_ctx_reserve",
     "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_o2", "pat_eikonal_tables_3d",
     "pat_eikonal_last_stats", "pat_table_to_fixed", "pat_table_to_q16", "pat_table_to_r16", "pat_table_r16_bytes",
-    "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_const",
+    "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_noalloc",
+    "pat_backproject_const",
     "pat_backproject_const_3d",
     "pat_server_create", "pat_server_create_ex", "pat_server_destroy", "pat_server_add_map", "pat_server_add_map_3d",
     "pat_server_map_state", "pat_server_remove_map", "pat_server_submit", "pat_server_wait", "pat_server_stats",
@@ -91,6 +93,7 @@ def lib() -> C.CDLL:
         L.pat_tile_order_3d.argtypes = [i32, i32, i32, vp, i32, i32, i32, i32, vp]
         L.pat_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp]
         L.pat_backproject.argtypes = [vp, vp, i32, vp, i32, i32, vp, vp, i32, i32, i32, dbl, dbl, i32, vp, vp]
+        L.pat_backproject_noalloc.argtypes = L.pat_backproject.argtypes
         L.pat_backproject_const.argtypes = [vp, i32, i32, dbl, dbl, vp, i32, vp, i32, vp, i32, i32, vp, vp, i32, i32,
                                             dbl, dbl, vp, vp]
         L.pat_backproject_const_3d.argtypes = [vp, i32, i32, i32, dbl, dbl, vp, i32, vp, i32, vp, i32, i32, vp, vp,
@@ -259,9 +262,13 @@ class Context:
         return out
 
     def backproject(self, table, sig, dt: float, t0: float = 0.0, *, filtered: bool = True, w=None,
-                    frame_scale=None, out=None, stream=None):
-        """table: [S][P] float32 seconds or int32 (16.16 bits); sig: [S][N] or [F][S][N] float32/float16."""
+                    frame_scale=None, out=None, stream=None, noalloc: bool = False):
+        """table: [S][P] float32 seconds or int32 (16.16 bits); sig: [S][N] or [F][S][N] float32/float16.
+        noalloc: call pat_backproject_noalloc (gather scratch from the device's fixed array); `out` must then
+        be given, so that the call allocates nothing."""
         import torch
+        if noalloc and out is None:
+            raise ValueError("noalloc needs a preallocated out")
         S, P = table.shape
         if isinstance(table, R16Table):
             tfmt = TABLE_R16
@@ -281,9 +288,9 @@ class Context:
         if out is None:
             out = torch.empty((P,) if single else (F, P), dtype=torch.float32, device=table.device)
         _need(out, torch.float32, "out")
-        check(lib().pat_backproject(self.h, _ptr(table), tfmt, _ptr(sig), sfmt, 1 if filtered else 0,
-                                    _ptr(frame_scale), _ptr(w), S, P, N, float(t0), float(dt), F, _ptr(out),
-                                    _stream(stream)))
+        fn = lib().pat_backproject_noalloc if noalloc else lib().pat_backproject
+        check(fn(self.h, _ptr(table), tfmt, _ptr(sig), sfmt, 1 if filtered else 0, _ptr(frame_scale), _ptr(w), S, P,
+                 N, float(t0), float(dt), F, _ptr(out), _stream(stream)))
         return out
 
     def backproject_const_3d(self, nx: int, ny: int, nz: int, h: float, c: float, sensors: np.ndarray, vox, sig,
