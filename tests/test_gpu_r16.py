@@ -156,26 +156,38 @@ def test_server_r16_maps(ctx, orc):
         assert rel_l2(img, ref) <= 2e-3
 
 
-@pytest.mark.parametrize("sig,filtered", [("f16", False), ("f32", True)])
-def test_gather_table_past_the_cache(ctx, orc, sig, filtered):
-    # a 16-bit table larger than half the Infinity Cache (1024 x 70016 entries,
-    # 152 MB) takes the kernel form that reads the tile headers with scalar
-    # loads; it must agree with the oracle's 16.16 gather of the decoded table
-    S, P, N, dt = 1024, 70016, 1024, 4e-8
+@pytest.mark.parametrize("sig,filtered,S,P,weights", [("f16", False, 1024, 70016, False),
+                                                      ("f32", True, 1024, 70016, False),
+                                                      ("f32", False, 1021, 70016, False),
+                                                      ("f16", False, 1021, 70001, True),
+                                                      ("f32", True, 1029, 69999, True)])
+def test_gather_table_past_the_cache(ctx, orc, sig, filtered, S, P, weights):
+    # a 16-bit table larger than half the Infinity Cache (about 1024 x 70000
+    # entries, 152 MB) takes the kernel form that reads the tile headers with
+    # scalar loads; it must agree with the oracle's 16.16 gather of the
+    # decoded table.  S not a multiple of 8 leaves a last pipeline step with
+    # records past S (clamped headers, weight 0); P not a multiple of 32
+    # leaves a short last tile; weights take the general sum's weighted form.
+    N, dt = 1024, 4e-8
     T = inputs.random_table(51, S, P, N, dt, 0.0, frac_out=0.02)
     p = inputs.random_signals(52, S, N)
+    w = np.random.default_rng(53).uniform(0.25, 1.75, S).astype(np.float32) if weights else None
+    wd = dev(w) if weights else None
     tab = ctx.table_to_r16(dev(T), dt, N)
     assert tab.buf.numel() > (128 << 20)
     if sig == "f16":
         scale = np.float32(np.abs(p).max() / 2.0 ** 14)
         h = (p / scale).astype(np.float16)
         vals = h.astype(np.float64) * np.float64(scale)
-        got = ctx.backproject(tab, dev(h), dt, filtered=filtered, frame_scale=dev(np.array([scale]))).cpu().numpy()
+        got = ctx.backproject(tab, dev(h), dt, filtered=filtered, w=wd,
+                              frame_scale=dev(np.array([scale]))).cpu().numpy()
     else:
         vals = p.astype(np.float64)
-        got = ctx.backproject(tab, dev(p), dt, filtered=filtered).cpu().numpy()
+        got = ctx.backproject(tab, dev(p), dt, filtered=filtered, w=wd).cpu().numpy()
     off, hdr = orc.table_to_r16(T, dt, N)
-    ref = orc.gather_q16(orc.r16_to_q16(off, hdr), vals if filtered else orc.filt(vals, dt))
+    ref = orc.gather_q16(orc.r16_to_q16(off, hdr), vals if filtered else orc.filt(vals, dt),
+                         None if w is None else w.astype(np.float64))
     err = rel_l2(got, ref)
-    print(f"[r16] table past the cache {sig} filtered={filtered}: rel L2 {err:.3e}", flush=True)
+    print(f"[r16] table past the cache S={S} P={P} {sig} filtered={filtered} weights={weights}: rel L2 {err:.3e}",
+          flush=True)
     assert err <= IMG_TOL
