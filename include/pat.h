@@ -68,9 +68,12 @@ enum {
     PAT_TABLE_F32 = 0,   /* float32 seconds; non-finite = no contribution */
     PAT_TABLE_Q16 = 1,   /* uint32 16.16 fractional sample index,
                             0xFFFFFFFF = no contribution */
-    PAT_TABLE_R16 = 2    /* 16-bit offsets from a base per sensor and 32-entry
+    PAT_TABLE_R16 = 2,   /* 16-bit offsets from a base per sensor and 32-entry
                             tile (pat_table_to_r16): a 16.16 table in about
                             half the bytes */
+    PAT_TABLE_F32X4 = 3  /* float32 seconds with four sensors interleaved per
+                            ROI position (pat_table_to_x4): the same entries
+                            as PAT_TABLE_F32, read four at a time */
 };
 
 /* Signal formats accepted by pat_backproject. */
@@ -243,6 +246,23 @@ int pat_table_to_r16(pat_ctx *ctx, const float *d_table, int S, int P, double t0
 size_t pat_table_r16_bytes(int S, int P);
 
 /*
+ * Delay table -> the same float32 delays (Section II-C's t_{i,j}) with four
+ * sensors interleaved per ROI position (PAT_TABLE_F32X4, a layout for the
+ * gather, not in the paper): d_out[q][p][r] = d_table[4q + r][p] for
+ * q < ceil(S/4), r < 4; entries of padding sensors (4q + r >= S) are NaN and
+ * contribute nothing.  The gather then fetches four sensors' delays at a
+ * pixel with one 16-byte load instead of four.
+ *
+ *   d_table   float32 [S][P] seconds.
+ *   d_out     pat_table_x4_bytes(S, P) bytes, 16-byte aligned; may not
+ *             overlap d_table.  ceil(S/4) * P < 2^31.
+ * Stream-ordered; PAT_EINVAL for bad sizes, null or misaligned pointers.
+ */
+int pat_table_to_x4(pat_ctx *ctx, const float *d_table, int S, int P, float *d_out, void *stream);
+/* Bytes of a PAT_TABLE_F32X4 table: 16 ceil(S/4) P.  Host only. */
+size_t pat_table_x4_bytes(int S, int P);
+
+/*
  * Host helper: reorder ROI node indices tile-major (tiles of tile_w x tile_h
  * nodes; tile rows alternately left to right and right to left, so that
  * consecutive tiles are neighbours; Z-order (Morton) inside a tile), so that every
@@ -281,7 +301,8 @@ int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, doubl
  *
  *   d_table   [S][P], format table_fmt (PAT_TABLE_F32 seconds,
  *             PAT_TABLE_Q16 from pat_table_to_q16 or PAT_TABLE_R16 from
- *             pat_table_to_r16, both with the same t0, dt, N).
+ *             pat_table_to_r16, both with the same t0, dt, N, or
+ *             PAT_TABLE_F32X4 from pat_table_to_x4, 16-byte aligned).
  *   d_sig     [F][S][N] signals, format sig_fmt.  If sig_is_filtered is 0 the
  *             signals are raw pressures p and the filter above is applied
  *             inside the kernel; otherwise they are already b.
@@ -299,8 +320,9 @@ int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, doubl
  * are split inside one workgroup (no scratch) for several frames or for a
  * frame too small to fill the GPU otherwise; the remaining shapes use
  * LDS-windowed workgroups over sensor groups, which add their partial sums
- * in scratch.  PAT_TABLE_R16 tables always take the split-sensor kernel and
- * need N >= 4 and an aligned d_sig (else PAT_EINVAL).
+ * in scratch.  PAT_TABLE_R16 and PAT_TABLE_F32X4 tables always take the
+ * split-sensor kernel and need N >= 4 and an aligned d_sig (else
+ * PAT_EINVAL).
  */
 int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,

@@ -259,6 +259,22 @@ extern "C" size_t pat_table_r16_bytes(int S, int P) {
     return pat_r16_bytes(S, P);
 }
 
+extern "C" size_t pat_table_x4_bytes(int S, int P) {
+    if (S <= 0 || P <= 0) return 0;
+    return pat_x4_bytes(S, P);
+}
+
+extern "C" int pat_table_to_x4(pat_ctx *ctx, const float *d_table, int S, int P, float *d_out, void *stream) {
+    int rc = pat_make_current(ctx);
+    if (rc) return rc;
+    if (S < 0 || P < 0) return pat_fail(PAT_EINVAL, "negative size (S=%d P=%d)", S, P);
+    if ((long long)((S + 3) / 4) * P > INT32_MAX) return pat_fail(PAT_EINVAL, "table too large (S=%d P=%d)", S, P);
+    if (S == 0 || P == 0) return PAT_OK;
+    if (!d_table || !d_out) return pat_fail(PAT_EINVAL, "null table pointer");
+    if ((uintptr_t)d_out % 16 != 0) return pat_fail(PAT_EINVAL, "the interleaved table must be 16-byte aligned");
+    return pat_launch_table_to_x4(d_table, S, P, d_out, (hipStream_t)stream);
+}
+
 extern "C" int pat_table_to_r16(pat_ctx *ctx, const float *d_table, int S, int P, double t0, double dt, int N,
                                 void *d_out, void *stream) {
     int rc = pat_make_current(ctx);
@@ -279,10 +295,14 @@ static int backproject_args(pat_ctx *ctx, const void *d_table, int table_fmt, co
     if (rc) return rc;
     if (S < 0 || P < 0 || F < 0) return pat_fail(PAT_EINVAL, "negative size (S=%d P=%d F=%d)", S, P, F);
     if (N < 2) return pat_fail(PAT_EINVAL, "need N >= 2 samples (N=%d)", N);
-    if (table_fmt != PAT_TABLE_F32 && table_fmt != PAT_TABLE_Q16 && table_fmt != PAT_TABLE_R16)
+    if (table_fmt != PAT_TABLE_F32 && table_fmt != PAT_TABLE_Q16 && table_fmt != PAT_TABLE_R16 &&
+        table_fmt != PAT_TABLE_F32X4)
         return pat_fail(PAT_EINVAL, "unknown table format %d", table_fmt);
     if (sig_fmt != PAT_SIG_F32 && sig_fmt != PAT_SIG_F16) return pat_fail(PAT_EINVAL, "unknown signal format %d", sig_fmt);
-    if (table_fmt != PAT_TABLE_F32 && N > 65535) return pat_fail(PAT_EINVAL, "16.16 and 16-bit tables need N <= 65535");
+    if ((table_fmt == PAT_TABLE_Q16 || table_fmt == PAT_TABLE_R16) && N > 65535)
+        return pat_fail(PAT_EINVAL, "16.16 and 16-bit tables need N <= 65535");
+    if (table_fmt == PAT_TABLE_F32X4 && d_table && (uintptr_t)d_table % 16 != 0)
+        return pat_fail(PAT_EINVAL, "interleaved tables must be 16-byte aligned");
     if (!finite_pos(dt) || !std::isfinite(t0)) return pat_fail(PAT_EINVAL, "need finite t0 and dt > 0");
     if ((long long)S * N > INT32_MAX || (long long)S * P > ((long long)1 << 40))
         return pat_fail(PAT_EINVAL, "sizes too large");

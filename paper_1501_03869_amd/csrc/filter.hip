@@ -86,6 +86,33 @@ int pat_launch_table_to_q16(const float *T, int64_t n, double t0, double dt, int
     return PAT_OK;
 }
 
+// Four sensors interleaved per ROI position: out[q][p][r] = T[4q + r][p],
+// NaN (no contribution) for the padding sensors past S.  One thread per
+// (quad, position): four coalesced 4-byte reads, one 16-byte write.
+__global__ void __launch_bounds__(256) k_table_to_x4(const float *__restrict__ T, float4 *__restrict__ out, int S,
+                                                     int P, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int q = (int)(i / P);
+    const long p = i - (long)q * P;
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int s = 4 * q + r;
+        v[r] = s < S ? T[(long)s * P + p] : __builtin_nanf("");
+    }
+    out[i] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+int pat_launch_table_to_x4(const float *T, int S, int P, float *out, hipStream_t st) {
+    const long n = (long)((S + 3) / 4) * P;
+    const long blk = 256;
+    k_table_to_x4<<<dim3((unsigned)((n + blk - 1) / blk)), dim3((unsigned)blk), 0, st>>>(
+        T, reinterpret_cast<float4 *>(out), S, P, n);
+    PAT_HIP(hipGetLastError());
+    return PAT_OK;
+}
+
 // Tile-relative 16-bit delays: 32 lanes per (sensor, 32-entry tile).  The
 // tile's smallest and largest valid u come from a butterfly over the 32
 // lanes; then b = floor(smallest), k = the largest shift in [0, 16] with

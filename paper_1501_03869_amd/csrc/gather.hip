@@ -540,10 +540,10 @@ int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const
     // frame).  A single frame that would split its sensors over workgroups
     // takes the split-sensor kernel; the rest take the windowed kernel.
     const bool px_ok = pat_px_eligible(sig_fmt, S, P, N, F, sig);
-    if (table_fmt == PAT_TABLE_R16) {
-        if (!px_ok)
-            return pat_fail(PAT_EINVAL, "16-bit tables need N >= 4, a signal pointer aligned to its sample size "
-                                        "and per-step offsets below 2^31 (N=%d)", N);
+    if (table_fmt == PAT_TABLE_R16 || table_fmt == PAT_TABLE_F32X4) {
+        if (!px_ok || (table_fmt == PAT_TABLE_F32X4 && (size_t)P * 32 >= (1ull << 31)))
+            return pat_fail(PAT_EINVAL, "16-bit and interleaved tables need N >= 4, a signal pointer aligned to its "
+                                        "sample size and per-step offsets below 2^31 (N=%d P=%d)", N, P);
         return pat_launch_backproject_px(table, table_fmt, sig, sig_fmt, sig_is_filtered, frame_scale, w, S, P, N, F,
                                          t0, dt, img, st);
     }

@@ -12,6 +12,7 @@ namespace pat_gather {
 
 struct DelayF32 {
     static constexpr bool kR16 = false;
+    static constexpr bool kX4 = false;
     float inv_hi, inv_lo, off;  // u = T * (inv_hi + inv_lo) + off
     float umax;                 // N - 1
     __device__ __forceinline__ bool decode(float T, int N, int &n, float &a) const {
@@ -89,6 +90,7 @@ struct DelayF32 {
 
 struct DelayQ16 {
     static constexpr bool kR16 = false;
+    static constexpr bool kX4 = false;
     __device__ __forceinline__ bool decode(uint32_t q, int N, int &n, float &a) const {
         if (q == 0xFFFFFFFFu) return false;
         n = (int)(q >> 16);
@@ -135,6 +137,13 @@ struct DelayR16 : DelayQ16 {
     __device__ __forceinline__ static uint32_t to_q16(uint32_t off, uint32_t hdr) {
         return off == 0xFFFFu ? 0xFFFFFFFFu : (hdr & 0xFFFF0000u) + (off << (hdr & 31u));
     }
+};
+
+// Float32 seconds with four sensors interleaved per ROI position
+// (PAT_TABLE_F32X4, [ceil(S/4)][P][4]): decoded as DelayF32; one 16-byte
+// load gives a lane the delays of four sensors at its pixel.
+struct DelayF32X4 : DelayF32 {
+    static constexpr bool kX4 = true;
 };
 
 template <int SFMT>

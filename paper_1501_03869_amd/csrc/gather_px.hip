@@ -138,6 +138,11 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     const int pc = min(p, P - 1);  // lanes past the end read a valid column and add nothing
     const int sw = wv * 2 * sps;
     const int se = min(S, sw + 2 * sps);  // end of this wave's sensors
+    // Record of slot j of this half within a step: 2j + half, or 4 half + j
+    // for tables with four sensors interleaved per pixel (whose 16-byte load
+    // holds the step's four consecutive sensors of one half)
+    constexpr int kJR = Delay::kX4 ? 1 : 2;
+    const int hr = Delay::kX4 ? 4 * half : half;
     const int nstep = (se - sw + 2 * PX_U - 1) / (2 * PX_U);  // steps of this wave (the last may hold fewer sensors)
     constexpr uint32_t esz = SFMT == PAT_SIG_F16 ? 2 : 4;
     // Step i covers sensors s0 + 2j + half (j < U) with s0 = sw + 2*i*U.  Its
@@ -181,12 +186,12 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     // so that it still lies in the record.
     auto load4 = [&](const SigRsrc &g, int j, int c, float (&q)[4]) {
         if constexpr (SFMT == PAT_SIG_F32) {
-            const auto v = __builtin_amdgcn_raw_buffer_load_b128(g.r, 4u * ((uint32_t)(half * N) + (uint32_t)c),
-                                                                 2 * j * N * 4, 0);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(g.r, 4u * ((uint32_t)(hr * N) + (uint32_t)c),
+                                                                 kJR * j * N * 4, 0);
             q[0] = __uint_as_float(v[0]); q[1] = __uint_as_float(v[1]);
             q[2] = __uint_as_float(v[2]); q[3] = __uint_as_float(v[3]);
         } else {
-            const uint32_t h = g.res + (uint32_t)((2 * j + half) * N + c);
+            const uint32_t h = g.res + (uint32_t)((kJR * j + hr) * N + c);
             const auto v = __builtin_amdgcn_raw_buffer_load_b96(g.r, 2u * (h & ~1u), 0, 0);
             q[0] = __uint_as_float(v[0]);
             q[1] = __uint_as_float(v[1]);
@@ -211,12 +216,12 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     // byte shift of n in q[3], cut out when summed
     auto load2 = [&](const SigRsrc &g, int j, int n, float (&q)[4]) {
         if constexpr (SFMT == PAT_SIG_F32) {
-            const auto v = __builtin_amdgcn_raw_buffer_load_b64(g.r, 4u * ((uint32_t)(half * N) + (uint32_t)n),
-                                                                2 * j * N * 4, 0);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(g.r, 4u * ((uint32_t)(hr * N) + (uint32_t)n),
+                                                                kJR * j * N * 4, 0);
             q[1] = __uint_as_float(v[0]);
             q[2] = __uint_as_float(v[1]);
         } else {
-            const uint32_t h = g.res + (uint32_t)((2 * j + half) * N + n);
+            const uint32_t h = g.res + (uint32_t)((kJR * j + hr) * N + n);
             const auto v = __builtin_amdgcn_raw_buffer_load_b64(g.r, 2u * (h & ~1u), 0, 0);
             q[1] = __uint_as_float(v[0]);
             q[2] = __uint_as_float(v[1]);
@@ -289,6 +294,16 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
                     st.h[j] = __builtin_amdgcn_raw_buffer_load_b32(rh, hoff, 2 * j * tiles * 4, 0);
                 }
             }
+        } else if constexpr (Delay::kX4) {
+            // quads q0 (this step's first four sensors, half 0) and q0 + 1
+            // (half 1): one 16-byte load per lane; a step past the wave's
+            // end re-reads the quad of its last sensor
+            const int q0 = step_s0(i) >> 2;
+            const uint32_t quads = (uint32_t)min(2, ((S + 3) >> 2) - q0);
+            const __amdgpu_buffer_rsrc_t rt = rsrc(J.tab + (size_t)q0 * P * 4, quads * (uint32_t)P * 16u);
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rt, ((uint32_t)(half * P) + (uint32_t)pc) * 16u, 0, 0);
+#pragma unroll
+            for (int j = 0; j < PX_U; ++j) st.d[j] = v[j];
         } else {
             const __amdgpu_buffer_rsrc_t rt = tab_rsrc(step_s0(i));
 #pragma unroll
@@ -314,7 +329,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
     // F32 decoding: the offset -t0/dt in a vector register, so the decode's
     // FMA reads only one scalar operand
     Delay dv = dec;
-    constexpr bool kF32T = std::is_same<Delay, DelayF32>::value;
+    constexpr bool kF32T = std::is_base_of<DelayF32, Delay>::value;
     if constexpr (kF32T) {
         float offv;
         asm("v_mov_b32 %0, %1" : "=v"(offv) : "s"(dec.off));
@@ -372,7 +387,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
                 }
                 const float v = fmaf(a, b1 - b0, b0);
                 if constexpr (HAS_W) {
-                    acc = fmaf(half ? J.w[s0 + 2 * j + 1] : J.w[s0 + 2 * j], v, acc);
+                    acc = fmaf(J.w[s0 + kJR * j + hr], v, acc);
                 } else {
                     acc += v;
                 }
@@ -395,13 +410,10 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             } else {
                 dok = dv.decode_bf1(st.x[j], N, n, a);
             }
-            const int sa = s0 + 2 * j, sb = sa + 1;
-            float w0 = sa < se ? 1.0f : 0.0f, w1 = sb < se ? 1.0f : 0.0f;
-            if constexpr (HAS_W) {
-                w0 *= J.w[min(sa, S - 1)];
-                w1 *= J.w[min(sb, S - 1)];
-            }
-            const float w = dok ? (half ? w1 : w0) : 0.0f;
+            const int sr = s0 + kJR * j + hr;  // this lane's sensor
+            float ws = sr < se ? 1.0f : 0.0f;
+            if constexpr (HAS_W) ws *= J.w[min(sr, S - 1)];
+            const float w = dok ? ws : 0.0f;
             // FP16 loads were clamped to the shorter fast range: read the
             // samples again at this path's own start (one unaligned load; buffer
             // accesses take any byte address in the unaligned access mode the
@@ -409,7 +421,7 @@ __device__ __forceinline__ float px_slot_sum(const PxJob &J, const Delay &dec, i
             float qs[4] = {st.q[j][0], st.q[j][1], st.q[j][2], st.q[j][3]};
             if constexpr (F16) {
                 const SigRsrc g = sig_rsrc(step_s0(i));
-                const uint32_t r = g.res + (uint32_t)((2 * j + half) * N);
+                const uint32_t r = g.res + (uint32_t)((kJR * j + hr) * N);
                 if constexpr (FILTERED) {
                     qs[1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(g.r, 2u * (r + (uint32_t)n), 0, 0));
                     qs[2] = 0.0f;
@@ -678,6 +690,17 @@ int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig,
         return sig_fmt == PAT_SIG_F32
                    ? launch_px<DelayF32, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
                    : launch_px<DelayF32, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
+    }
+    if (table_fmt == PAT_TABLE_F32X4) {
+        DelayF32X4 d;
+        const double inv = 1.0 / dt;
+        d.inv_hi = (float)inv;
+        d.inv_lo = (float)(inv - (double)d.inv_hi);
+        d.off = (float)(-t0 / dt);
+        d.umax = (float)(N - 1);
+        return sig_fmt == PAT_SIG_F32
+                   ? launch_px<DelayF32X4, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
+                   : launch_px<DelayF32X4, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
     }
     if (table_fmt == PAT_TABLE_R16) {
         DelayR16 d;

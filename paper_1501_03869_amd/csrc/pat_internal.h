@@ -91,6 +91,9 @@ int pat_launch_filter(const float *p, long rows, int N, double t0, double dt, fl
 int pat_launch_table_to_q16(const float *T, int64_t n, double t0, double dt, int N, uint32_t *q,
                             hipStream_t st);
 int pat_launch_table_to_r16(const float *T, int S, int P, double t0, double dt, int N, void *out, hipStream_t st);
+int pat_launch_table_to_x4(const float *T, int S, int P, float *out, hipStream_t st);
+// PAT_TABLE_F32X4 layout: float32 [ceil(S/4)][P][4]
+__host__ __device__ inline size_t pat_x4_bytes(long long S, long long P) { return (size_t)(16 * ((S + 3) / 4) * P); }
 // Gather scratch shared by the single-frame and batched kernels.
 size_t pat_gather_counter_bytes(int P, int F);
 // Tables up to this size are taken to stay cached between frames (half of

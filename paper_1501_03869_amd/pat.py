@@ -18,13 +18,14 @@ LIB_PATH = os.path.join(_HERE, "libpat.so")
 
 NOALLOC_SCRATCH_BYTES = 16 << 20  # PAT_NOALLOC_SCRATCH_BYTES
 PAT_OK, PAT_EINVAL, PAT_ENOMEM, PAT_EDEVICE, PAT_EBUSY, PAT_ENOTFOUND, PAT_ETIMEOUT, PAT_ENOCONV = 0, -1, -2, -3, -4, -5, -6, -7
-TABLE_F32, TABLE_Q16, TABLE_R16 = 0, 1, 2
+TABLE_F32, TABLE_Q16, TABLE_R16, TABLE_F32X4 = 0, 1, 2, 3
 SIG_F32, SIG_F16 = 0, 1
 
 EXPORTED = [
     "pat_last_error", "pat_version", "pat_ctx_create", "pat_ctx_destroy", "pat_ctx_reserve",
     "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_o2", "pat_eikonal_tables_3d",
     "pat_eikonal_last_stats", "pat_table_to_fixed", "pat_table_to_q16", "pat_table_to_r16", "pat_table_r16_bytes",
+    "pat_table_to_x4", "pat_table_x4_bytes",
     "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_noalloc",
     "pat_backproject_const",
     "pat_backproject_const_3d",
@@ -89,6 +90,9 @@ def lib() -> C.CDLL:
         L.pat_table_to_r16.argtypes = [vp, vp, i32, i32, dbl, dbl, i32, vp, vp]
         L.pat_table_r16_bytes.argtypes = [i32, i32]
         L.pat_table_r16_bytes.restype = sz
+        L.pat_table_to_x4.argtypes = [vp, vp, i32, i32, vp, vp]
+        L.pat_table_x4_bytes.argtypes = [i32, i32]
+        L.pat_table_x4_bytes.restype = sz
         L.pat_tile_order.argtypes = [i32, i32, vp, i32, i32, i32, vp]
         L.pat_tile_order_3d.argtypes = [i32, i32, i32, vp, i32, i32, i32, i32, vp]
         L.pat_filter.argtypes = [vp, vp, i32, i32, dbl, dbl, vp, vp]
@@ -249,6 +253,15 @@ class Context:
                                      _stream(stream)))
         return R16Table(buf, S, P)
 
+    def table_to_x4(self, table, stream=None) -> "X4Table":
+        """Four sensors interleaved per ROI position (see pat_table_to_x4)."""
+        import torch
+        _need(table, torch.float32, "table")
+        S, P = table.shape
+        buf = torch.empty(((S + 3) // 4, P, 4), dtype=torch.float32, device=table.device)
+        check(lib().pat_table_to_x4(self.h, _ptr(table), S, P, _ptr(buf), _stream(stream)))
+        return X4Table(buf, S, P)
+
     # ------------------------------------------------------------------ frames
     def filter(self, p, dt: float, t0: float = 0.0, out=None, stream=None):
         import torch
@@ -273,6 +286,9 @@ class Context:
         if isinstance(table, R16Table):
             tfmt = TABLE_R16
             _need(table.buf, torch.uint8, "table")
+        elif isinstance(table, X4Table):
+            tfmt = TABLE_F32X4
+            _need(table.buf, torch.float32, "table")
         else:
             tfmt = TABLE_Q16 if table.dtype == torch.int32 else TABLE_F32
             _need(table, torch.int32 if tfmt == TABLE_Q16 else torch.float32, "table")
@@ -344,6 +360,29 @@ class Context:
                                           _ptr(pix), P, _ptr(sig), sfmt, 1 if filtered else 0, _ptr(frame_scale),
                                           _ptr(w), N, F, float(t0), float(dt), _ptr(out), _stream(stream)))
         return out
+
+
+class X4Table:
+    """A PAT_TABLE_F32X4 table: the float32 [ceil(S/4)][P][4] device buffer and
+    the S x P shape of the table it interleaves."""
+
+    def __init__(self, buf, S: int, P: int):
+        self.buf, self.shape = buf, (int(S), int(P))
+
+    @property
+    def device(self):
+        return self.buf.device
+
+    def data_ptr(self) -> int:
+        return self.buf.data_ptr()
+
+    def is_contiguous(self) -> bool:
+        return True
+
+    def table(self):
+        """The [S][P] view of the same delays (a copy)."""
+        S, P = self.shape
+        return self.buf.permute(0, 2, 1).reshape(-1, P)[:S].contiguous()
 
 
 class R16Table:

@@ -107,6 +107,14 @@ def test_tile_order_3d_host_helper():
         pat.tile_order_3d(nx, ny, nz, np.array([nx * ny * nz], np.int32), 4, 4, 2)
 
 
+def test_interleaved_table_size_is_host_only():
+    L = pat.lib()
+    assert L.pat_table_x4_bytes(0, 10) == 0
+    assert L.pat_table_x4_bytes(1, 10) == 160
+    assert L.pat_table_x4_bytes(5, 7) == 2 * 7 * 16
+    assert L.pat_table_x4_bytes(512, 21336) == 512 * 21336 * 4
+
+
 def test_scratch_size_is_host_only():
     assert pat.backproject_scratch_bytes(0, 10, 1) == 0
     # several sensor groups at this size: at least two partial images
