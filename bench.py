@@ -42,19 +42,22 @@ HBM_PEAK_GBS = 8000.0
 
 # Memory traffic of the single-frame gather kernel per launch, from two
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch, mean over the dispatches), each scaled by the same counter's
+# dispatch, mean over the dispatches of `--only headline` or, for the table
+# streamed from HBM, `--only rotated`), each scaled by the same counter's
 # reading for a plain 256 MB device copy (--copy-calibration 256: FETCH_SIZE
-# reads 125012 KiB of 250000 KiB moved, factor 2.0; WRITE_SIZE reads 250000,
-# factor 1.0).  Valid only for the kernel sources they were taken on: the
-# SHA-256 of the files below; any change makes the field null until the
-# counters are taken again.  Summaries: profiles/k_bp_px_*_hbm_counters.md.
+# reads 125013 KiB of 250000 KiB moved, factor 2.0; WRITE_SIZE reads 250000,
+# factor 1.0).  FETCH_SIZE counts L2 read requests to the fabric, so reads
+# served by the Infinity Cache count as well.  Valid only for the kernel
+# sources they were taken on: the SHA-256 of the files below; any change makes
+# the field null until the counters are taken again.  Summaries:
+# profiles/k_bp_px_*_hbm_counters.md.
 TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_common.h")
-TRAFFIC_SHA = "189c45d77cbf28d960722d31ef689b78ccb90dae8844a78cb4aca670060ac7ba:" \
-              "046afad2d9d976f56fb21100e0e5c9f9620cda616a8d09c45b88ba79e760cfe7"
-FETCH_FACTOR = 250000.0 / 125012.32
+TRAFFIC_SHA = "ccff1d1ddd90c6f37b7b037e1f9dff30663e302449cf1bacd28ff94dc99155d5:" \
+              "2d791c80f57a0c9f448436bfbee163cce25cf24f4d37f6030070c52971251ba9"
+FETCH_FACTOR = 250000.0 / 125013.18
 WRITE_FACTOR = 1.0
-TRAFFIC_KIB = {"paper": (25128.76, 83.48), "large": (1842475.53, 3278.96),
-               "head3": (24550.47, 174.70)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+TRAFFIC_KIB = {"paper": (24383.45, 83.39), "large": (1704613.54, 3514.57),
+               "paper_rotated": (24325.52, 83.44)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 
 
 def measured_traffic(config: str):
@@ -106,6 +109,95 @@ def cpu_baseline(geo, vol, budget_s=12.0):
                                 "sensors on the same threads; not part of value"}
 
 
+def rotated_tables(ctx, geo, table, frames, img, stream, steps):
+    """The headline gather with its table forced out of the 256 MB Infinity
+    Cache: K distinct resident copies of the interleaved table (K x table >
+    512 MiB), one per launch in turn, so that every launch streams its table
+    from HBM.  Mean launch duration from HIP events around back-to-back
+    launches.  None when one table alone exceeds 128 MiB (it streams anyway)."""
+    import torch
+    S, P, N = geo.S, geo.P, geo.n_samples
+    tbytes = S * P * 4
+    if tbytes >= (128 << 20):
+        return None
+    K = max(8, -(-(512 << 20) // tbytes))
+    copies = [ctx.table_to_x4(table) for _ in range(K)]
+    R = frames.shape[0]
+    torch.cuda.synchronize()
+
+    def rot(i):
+        r = i % R
+        ctx.backproject(copies[i % K], frames[r], geo.dt, geo.t0, filtered=False, out=img[r], stream=stream)
+    for i in range(2 * K):
+        rot(i)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = max(steps, 4 * K)
+    e0.record(stream)
+    for i in range(steps):
+        rot(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / steps
+    b = 4 * S * P + 4 * S * N + 4 * P
+    del copies
+    return {"bound": "hbm", "achieved": b / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": b / t / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic(geo.name + "_rotated"),
+            "tables_rotated": K, "resident_table_bytes": K * tbytes, "device_ms_per_frame_mean": t * 1e3,
+            "gathers_per_s": S * P / t, "algorithmic_bytes_per_launch": b,
+            "timing_note": "HIP events around back-to-back launches, each on the next of K copies of the "
+                           "interleaved table (K x table > 512 MiB), so every launch streams its table from HBM",
+            "traffic_note": "FETCH_SIZE + WRITE_SIZE of the same rotated launches (bench.py --only rotated), "
+                            "scaled by a plain copy's counters; FETCH_SIZE counts L2 read requests to the "
+                            "fabric, Infinity Cache hits included"}
+
+
+def run_batch64(ctx, geo, table, frames, frames_h, stream, timed, args,
+                names=("batch64_v0_f32", "batch64_v3_q16_f16", "batch64_v4_r16_f16")):
+    """64 frames per launch, table read once per launch (per 16 frames for
+    tables past the cache), replayed from a HIP graph."""
+    import torch
+    S, P, N = geo.S, geo.P, geo.n_samples
+    dev = table.device
+    R = len(frames_h)
+    p = np.stack(frames_h).astype(np.float32)
+    scale = (np.abs(p).reshape(R, -1).max(1) / 2.0 ** 14).astype(np.float32)
+    half = torch.from_numpy((p / scale[:, None, None]).astype(np.float16)).to(dev)
+    scale_d = torch.from_numpy(scale).to(dev)
+    tabs = {"batch64_v0_f32": table}
+    if "batch64_v3_q16_f16" in names:
+        tabs["batch64_v3_q16_f16"] = ctx.table_to_q16(table, geo.dt, N, geo.t0)
+    if "batch64_v4_r16_f16" in names:
+        tabs["batch64_v4_r16_f16"] = ctx.table_to_r16(table, geo.dt, N, geo.t0)
+    F = 64
+    idx = np.arange(F) % R
+    sigs = {"f32": frames[torch.from_numpy(idx).to(dev)].contiguous(),
+            "f16": half[torch.from_numpy(idx).to(dev)].contiguous()}
+    scl = scale_d[torch.from_numpy(idx).to(dev)].contiguous()
+    outF = torch.empty((F, P), dtype=torch.float32, device=dev)
+    res = {}
+    for name in names:
+        tab = tabs[name]
+        sk = "f32" if name.endswith("f32") else "f16"
+        sig = sigs[sk]
+        sc = scl if sk == "f16" else None
+        ctx.reserve(S, P, F)
+        g = torch.cuda.CUDAGraph()
+        s2 = torch.cuda.Stream()
+        s2.wait_stream(stream)
+        with torch.cuda.stream(s2):
+            ctx.backproject(tab, sig, geo.dt, geo.t0, filtered=False, frame_scale=sc, out=outF, stream=s2)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            ctx.backproject(tab, sig, geo.dt, geo.t0, filtered=False, frame_scale=sc, out=outF)
+        steps = max(20, args.steps // 8)
+        wall, ms = timed(lambda i: g.replay(), steps, 5)
+        res[name] = {"frames_per_launch": F, "gathers_per_s": steps * F * S * P / wall,
+                     "frames_per_s": steps * F / wall, "device_ms_p50": percentile(ms, 50),
+                     "device_ms_p99": percentile(ms, 99), "hip_graph": True}
+    return res
+
+
 def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
     """Reduced-precision and batched variants on the same geometry and frames."""
     import torch
@@ -133,6 +225,7 @@ def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
 
     r16 = ctx.table_to_r16(table, geo.dt, N, geo.t0)
     single("v0_f32_table_f32_signal", table, frames, None)
+    single("v0x4_interleaved_f32_table_f32_signal", ctx.table_to_x4(table), frames, None)
     single("v1_q16_table_f32_signal", q16, frames, None)
     single("v2_f32_table_f16_signal", table, half, scale_d)
     single("v3_q16_table_f16_signal", q16, half, scale_d)
@@ -158,34 +251,8 @@ def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
                        "device_ms_*: HIP events around each", "device_ms_p50": percentile(ms, 50),
         "device_ms_p99": percentile(ms, 99)}
 
-    # the same single-frame gather with the table forced out of the 256 MB
-    # Infinity Cache: K distinct resident copies (K x table > 512 MiB),
-    # one per launch in turn, so every launch streams its table from HBM
-    tbytes = table.numel() * 4
-    if tbytes < (128 << 20):
-        K = max(8, -(-(512 << 20) // tbytes))
-        copies = [table.clone() for _ in range(K)]
-        torch.cuda.synchronize()
-
-        def rot(i):
-            r = i % R
-            ctx.backproject(copies[i % K], frames[r], geo.dt, geo.t0, filtered=False, out=img[r], stream=stream)
-        timed(rot, 2 * K, 0)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        steps = max(args.steps, 4 * K)
-        e0.record(stream)
-        for i in range(steps):
-            rot(i)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) * 1e-3 / steps
-        b = 4 * S * P + 4 * S * N + 4 * P
-        res["v0_rotated_tables_hbm"] = {
-            "frames_per_launch": 1, "tables_rotated": K, "resident_table_bytes": K * tbytes,
-            "device_ms_per_frame_mean": t * 1e3, "gathers_per_s": S * P / t,
-            "achieved_GBps": b / t / 1e9, "frac_hbm_peak": b / t / 1e9 / HBM_PEAK_GBS,
-            "timing_note": "HIP events around back-to-back eager launches, each on the next of K table copies"}
-        del copies
+    # (the same single-frame gather with the table forced out of the 256 MB
+    # Infinity Cache is reported as roofline_hbm)
 
     # the UBP filter alone (pat_filter): one pass over the frame, 4 B read and
     # 4 B written per sample
@@ -204,29 +271,7 @@ def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
                           "timing_note": "HIP events around back-to-back pat_filter launches on one frame each"}
 
     # batched: F frames per launch, table read once; replayed from a HIP graph
-    F = 64
-    idx = np.arange(F) % R
-    sigs = {"f32": frames[torch.from_numpy(idx).to(dev)].contiguous(), "f16": half[torch.from_numpy(idx).to(dev)].contiguous()}
-    scl = scale_d[torch.from_numpy(idx).to(dev)].contiguous()
-    outF = torch.empty((F, P), dtype=torch.float32, device=dev)
-    for name, tab, sk in (("batch64_v0_f32", table, "f32"), ("batch64_v3_q16_f16", q16, "f16"),
-                          ("batch64_v4_r16_f16", r16, "f16")):
-        sig = sigs[sk]
-        sc = scl if sk == "f16" else None
-        ctx.reserve(S, P, F)
-        g = torch.cuda.CUDAGraph()
-        s2 = torch.cuda.Stream()
-        s2.wait_stream(stream)
-        with torch.cuda.stream(s2):
-            ctx.backproject(tab, sig, geo.dt, geo.t0, filtered=False, frame_scale=sc, out=outF, stream=s2)
-        torch.cuda.synchronize()
-        with torch.cuda.graph(g):
-            ctx.backproject(tab, sig, geo.dt, geo.t0, filtered=False, frame_scale=sc, out=outF)
-        steps = max(20, args.steps // 8)
-        wall, ms = timed(lambda i: g.replay(), steps, 5)
-        res[name] = {"frames_per_launch": F, "gathers_per_s": steps * F * S * P / wall,
-                     "frames_per_s": steps * F / wall, "device_ms_p50": percentile(ms, 50),
-                     "device_ms_p99": percentile(ms, 99), "hip_graph": True}
+    res.update(run_batch64(ctx, geo, table, frames, frames_h, stream, timed, args))
     return res
 
 
@@ -367,6 +412,10 @@ def main():
     ap.add_argument("--serve", type=float, default=5.0, help="seconds of the serving mix per variant (0 = skip)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 10 times (HBM counter calibration)")
+    ap.add_argument("--only", choices=("headline", "rotated", "batch64"), default=None,
+                    help="profiling runs: build the tables, then only the headline single-frame launches, only "
+                         "the gather on rotated table copies (the table streamed from HBM), or only 64-frame "
+                         "launches; prints no JSON line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -414,6 +463,7 @@ def main():
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t
     est = ctx.eikonal_stats()
+    n_nodes = geo.nx * geo.ny * (geo.nz if vol else 1)
     print(f"[bench] tables built in {build_s:.3f} s ({est['rounds']} rounds)", file=sys.stderr, flush=True)
     build_o2_s = None
     if not vol and geo.nx * geo.ny <= 512 * 512:
@@ -426,6 +476,10 @@ def main():
         print(f"[bench] second-order tables built in {build_o2_s:.3f} s", file=sys.stderr, flush=True)
 
     table_h = table.cpu().numpy()
+    # the resident table, laid out four sensors per 16-byte entry for the
+    # gather (pat_table_to_x4; the same float32 delays, built once offline)
+    table_x4 = ctx.table_to_x4(table)
+    torch.cuda.synchronize()
     if vol:
         frames_h = [inputs.frame_for3(geo, table_h, f) for f in range(args.frames)]
     else:
@@ -455,14 +509,29 @@ def main():
 
     def step(i, st=None):
         r = i % args.frames
-        ctx.backproject(table, frames[r], geo.dt, geo.t0, filtered=False, out=img[r], stream=st or stream)
+        ctx.backproject(table_x4, frames[r], geo.dt, geo.t0, filtered=False, out=img[r], stream=st or stream)
+
+    S, P, N = geo.S, geo.P, geo.n_samples
+    bytes_per_frame = 4 * S * P + 4 * S * N + 4 * P
+    if args.only == "headline":
+        for i in range(args.warmup + args.steps):
+            step(i)
+        torch.cuda.synchronize()
+        print("[bench] headline launches done", file=sys.stderr, flush=True)
+        return
+    if args.only == "rotated":
+        rotated_tables(ctx, geo, table, frames, img, stream, max(args.steps, 1))
+        print("[bench] rotated-table launches done", file=sys.stderr, flush=True)
+        return
+    if args.only == "batch64":
+        run_batch64(ctx, geo, table, frames, frames_h, stream, timed, args, names=("batch64_v0_f32", "batch64_v3_q16_f16"))
+        print("[bench] 64-frame launches done", file=sys.stderr, flush=True)
+        return
 
     # (a) per-launch device time: HIP events around every launch on its
     # stream (p50/p99), and two events around the whole run of back-to-back
     # launches (the mean launch duration the roofline uses)
     _, dev_ms = timed(step, args.steps, args.warmup)
-    S, P, N = geo.S, geo.P, geo.n_samples
-    bytes_per_frame = 4 * S * P + 4 * S * N + 4 * P
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
@@ -531,9 +600,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{geo.name}: {grid} grid h={geo.h * 1e3:g} mm, {S} sensors, {P} ROI "
                                f"{'voxels' if vol else 'pixels'}, {N} samples at {1e-6 / geo.dt:g} MHz, "
-                               f"FP32 table + FP32 signals, "
+                               f"FP32 table (four sensors interleaved) + FP32 signals, "
                                f"fused filter+gather, one frame per step",
-                   "sensors": S, "pixels": P, "samples": N, "frames_per_step": 1, "table_format": "f32"},
+                   "sensors": S, "pixels": P, "samples": N, "frames_per_step": 1,
+                   "table_format": "f32 seconds, four sensors interleaved per pixel (pat_table_to_x4)"},
         "frames_per_s": args.steps / wall,
         "timing_note": "value/frames_per_s: single-frame launches replayed from a HIP graph of up to 64 launches; "
                        "device_ms_*: HIP events around each eager launch; roofline: HIP events around the run of "
@@ -546,22 +616,32 @@ def main():
         "latency_note": "host frame -> H2D -> fused filter+gather -> D2H image, synchronous, pinned buffers",
         "table_build_s": build_s,
         "table_build_rounds": est["rounds"],
-        "table_build_node_updates_per_s": est["sweeps"] * (512 if vol else 1024) / build_s,
+        "table_build_nodes_per_s": S * n_nodes / build_s,
+        "table_build_tile_node_sweeps": est["sweeps"] * (512 if vol else 1024),
         "table_build_note": "pat_eikonal_tables" + ("_3d" if vol else "") + " wall time for all sensors (second "
-                            "call), host validation and seeding included; node updates = in-tile sweeps x nodes "
-                            "per tile (32 x 32, or 8^3 for 3-D bricks)",
+                            "call), host validation and seeding included; nodes_per_s = sensors x grid nodes solved "
+                            "per second; tile_node_sweeps = in-tile relaxation sweeps x nodes per tile (32 x 32, or "
+                            "8^3 for 3-D bricks), a work counter",
         "table_build_o2_s": build_o2_s,
         "table_build_o2_note": "pat_eikonal_tables_o2 (the paper's second-order scheme) wall time for all sensors; "
                                "null for 3-D and grids above 512^2",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
+                     "table_residency": ("infinity_cache" if 4 * S * P < (256 << 20) else "hbm"),
+                     "residency_note": "a table below the 256 MB Infinity Cache is re-read from it between "
+                                       "launches, so achieved is algorithmic bytes per second, not HBM "
+                                       "bandwidth; roofline_hbm streams copies of it from HBM",
                      "kernel": "pat_backproject, one launch per frame (k_bp_px at these shapes: fused UBP filter "
-                               "+ delay-and-sum gather, sensors split inside 32-pixel-tile workgroups)",
+                               "+ delay-and-sum gather, sensors split inside 32-pixel-tile workgroups, table "
+                               "interleaved by four sensors)",
                      "algorithmic_bytes_per_launch": bytes_per_frame,
                      "traffic_note": "bytes per launch from FETCH_SIZE + WRITE_SIZE scaled by a plain copy's "
                                      "counters; null when not measured for this config or kernel source"},
         "paper_context": "123.79 ms for 512 sensors x 21323 pixels on an NVIDIA Tesla C2075, transfers included",
     }
+    rh = rotated_tables(ctx, geo, table, frames, img, stream, args.steps)
+    if rh is not None:
+        out["roofline_hbm"] = rh
     if not args.no_variants:
         out["variants"] = run_variants(ctx, geo, table, frames, frames_h, stream, timed, args)
     if args.serve > 0 and not vol:
