@@ -57,7 +57,8 @@ TRAFFIC_SHA = "ccff1d1ddd90c6f37b7b037e1f9dff30663e302449cf1bacd28ff94dc99155d5:
 FETCH_FACTOR = 250000.0 / 125013.18
 WRITE_FACTOR = 1.0
 TRAFFIC_KIB = {"paper": (24383.45, 83.39), "large": (1704613.54, 3514.57),
-               "paper_rotated": (24325.52, 83.44)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+               "paper_rotated": (24325.52, 83.44), "head3": (24019.11, 174.70),
+               "head3_rotated": (23992.91, 174.70)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 
 
 def measured_traffic(config: str):
