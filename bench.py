@@ -52,13 +52,13 @@ HBM_PEAK_GBS = 8000.0
 # the field null until the counters are taken again.  Summaries:
 # profiles/k_bp_px_*_hbm_counters.md.
 TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_common.h")
-TRAFFIC_SHA = "ccff1d1ddd90c6f37b7b037e1f9dff30663e302449cf1bacd28ff94dc99155d5:" \
+TRAFFIC_SHA = "4d2259dda99be6a4e509e38fec25fe496079ddb631e8ab4a9b072f5be6978236:" \
               "2d791c80f57a0c9f448436bfbee163cce25cf24f4d37f6030070c52971251ba9"
 FETCH_FACTOR = 250000.0 / 125013.18
 WRITE_FACTOR = 1.0
-TRAFFIC_KIB = {"paper": (24383.45, 83.39), "large": (1704613.54, 3514.57),
-               "paper_rotated": (24325.52, 83.44), "head3": (24019.11, 174.70),
-               "head3_rotated": (23992.91, 174.70)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+TRAFFIC_KIB = {"paper": (24246.18, 83.34), "large": (1704467.70, 3516.67),
+               "paper_rotated": (24238.22, 83.36), "head3": (23663.20, 174.69),
+               "head3_rotated": (23664.99, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 
 
 def measured_traffic(config: str):
