@@ -153,13 +153,41 @@ def rotated_tables(ctx, geo, table, frames, img, stream, steps):
                             "fabric, Infinity Cache hits included"}
 
 
+def _frame_worker(args):
+    from paper_1501_03869_amd import inputs
+    parts, N, dt, t0, f, snr = args
+    return inputs.frame_from_parts(parts, N, dt, t0, f, snr)
+
+
+def batch_frames(geo, table_h, F=64, snr_db=20.0):
+    """F distinct frames: each its own seeded phantom plus white Gaussian
+    noise at snr_db (the batched-frames configuration).  The pulse sums run in
+    worker processes started fresh (spawn: they never touch the GPU); the
+    phantoms' table columns are gathered here."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_1501_03869_amd import inputs
+    phantom = "points" if geo.nx * geo.ny > 512 * 512 else "segments"
+    jobs = [(inputs.frame_parts(geo, table_h, f, phantom), geo.n_samples, geo.dt, geo.t0, f, snr_db) for f in range(F)]
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4), mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_frame_worker, jobs))
+
+
 def run_batch64(ctx, geo, table, frames, frames_h, stream, timed, args,
-                names=("batch64_v0_f32", "batch64_v3_q16_f16", "batch64_v4_r16_f16")):
+                names=("batch64_v0_f32", "batch64_v3_q16_f16", "batch64_v4_r16_f16"), table_h=None):
     """64 frames per launch, table read once per launch (per 16 frames for
-    tables past the cache), replayed from a HIP graph."""
+    tables past the cache), replayed from a HIP graph.  With table_h (2-D
+    geometries) the 64 frames are distinct phantoms with 20 dB noise;
+    otherwise the resident frames are cycled."""
     import torch
     S, P, N = geo.S, geo.P, geo.n_samples
     dev = table.device
+    if table_h is not None:
+        t = time.perf_counter()
+        frames_h = batch_frames(geo, table_h)
+        frames = torch.from_numpy(np.stack(frames_h)).to(dev)
+        print(f"[bench] {len(frames_h)} noisy frames synthesised in {time.perf_counter() - t:.1f} s",
+              file=sys.stderr, flush=True)
     R = len(frames_h)
     p = np.stack(frames_h).astype(np.float32)
     scale = (np.abs(p).reshape(R, -1).max(1) / 2.0 ** 14).astype(np.float32)
@@ -195,11 +223,13 @@ def run_batch64(ctx, geo, table, frames, frames_h, stream, timed, args,
         wall, ms = timed(lambda i: g.replay(), steps, 5)
         res[name] = {"frames_per_launch": F, "gathers_per_s": steps * F * S * P / wall,
                      "frames_per_s": steps * F / wall, "device_ms_p50": percentile(ms, 50),
-                     "device_ms_p99": percentile(ms, 99), "hip_graph": True}
+                     "device_ms_p99": percentile(ms, 99), "hip_graph": True,
+                     "frames": ("64 distinct phantoms, 20 dB white noise" if table_h is not None
+                                else f"{R} resident frames cycled")}
     return res
 
 
-def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
+def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args, table_h=None):
     """Reduced-precision and batched variants on the same geometry and frames."""
     import torch
     S, P, N = geo.S, geo.P, geo.n_samples
@@ -272,7 +302,7 @@ def run_variants(ctx, geo, table, frames, frames_h, stream, timed, args):
                           "timing_note": "HIP events around back-to-back pat_filter launches on one frame each"}
 
     # batched: F frames per launch, table read once; replayed from a HIP graph
-    res.update(run_batch64(ctx, geo, table, frames, frames_h, stream, timed, args))
+    res.update(run_batch64(ctx, geo, table, frames, frames_h, stream, timed, args, table_h=table_h))
     return res
 
 
@@ -525,7 +555,8 @@ def main():
         print("[bench] rotated-table launches done", file=sys.stderr, flush=True)
         return
     if args.only == "batch64":
-        run_batch64(ctx, geo, table, frames, frames_h, stream, timed, args, names=("batch64_v0_f32", "batch64_v3_q16_f16"))
+        run_batch64(ctx, geo, table, frames, frames_h, stream, timed, args, names=("batch64_v0_f32", "batch64_v3_q16_f16"),
+                    table_h=None if vol else table_h)
         print("[bench] 64-frame launches done", file=sys.stderr, flush=True)
         return
 
@@ -644,7 +675,8 @@ def main():
     if rh is not None:
         out["roofline_hbm"] = rh
     if not args.no_variants:
-        out["variants"] = run_variants(ctx, geo, table, frames, frames_h, stream, timed, args)
+        out["variants"] = run_variants(ctx, geo, table, frames, frames_h, stream, timed, args,
+                                       table_h=None if vol else table_h)
     if args.serve > 0 and not vol:
         out["serving"] = [run_serving(ctx, args.serve, v) for v in ("v0", "v3")]
     if not args.no_cpu:

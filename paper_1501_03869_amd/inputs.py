@@ -257,7 +257,7 @@ def npulse_signals(src_delay: np.ndarray, src_amp: np.ndarray, src_dist: np.ndar
         tau = (t0 + idx * dt) - d[:, None]
         val = a[:, None] * (-tau / sigma) * np.exp(0.5 - tau * tau / (2.0 * sigma * sigma))
         good = (idx >= 0) & (idx < n_samples)
-        np.add.at(out[s], idx[good], val[good])
+        out[s] += np.bincount(idx[good], weights=val[good], minlength=n_samples)
     return out.astype(np.float32)
 
 
@@ -269,12 +269,11 @@ def source_distances(geo: Geometry, src_nodes: np.ndarray) -> np.ndarray:
     return np.hypot(xs[None, :] - geo.sensors[:, 0:1], ys[None, :] - geo.sensors[:, 1:2])
 
 
-def frame_for(geo: Geometry, table: np.ndarray, frame: int = 0, noise_snr_db: float | None = None,
-              phantom: str = "segments") -> np.ndarray:
-    """One synthetic frame p[S][N] for the given delay table T[S][P] (seconds).
-
-    The phantom's nodes must lie inside the ROI (true for the built-in
-    geometries); their travel times are read from the table's columns."""
+def frame_parts(geo: Geometry, table: np.ndarray, frame: int = 0, phantom: str = "segments"):
+    """The inputs of one synthetic frame: the phantom's arrival times at every
+    sensor (read from the table's columns), amplitudes and source-sensor
+    distances.  The phantom's nodes must lie inside the ROI (true for the
+    built-in geometries)."""
     if phantom == "points":
         nodes, amp = point_absorbers(SEED_PHANTOM + frame, geo.nx, geo.ny, geo.h)
     else:
@@ -285,14 +284,32 @@ def frame_for(geo: Geometry, table: np.ndarray, frame: int = 0, noise_snr_db: fl
     c = col[nodes]
     keep = c >= 0
     nodes, amp, c = nodes[keep], amp[keep], c[keep]
-    delay = np.asarray(table, dtype=np.float64)[:, c]
-    p = npulse_signals(delay, amp, source_distances(geo, nodes), geo.n_samples, geo.dt, geo.t0)
+    delay = np.asarray(table[:, c], dtype=np.float64)
+    return delay, amp, source_distances(geo, nodes)
+
+
+def frame_from_parts(parts, n_samples: int, dt: float, t0: float = 0.0, frame: int = 0,
+                     noise_snr_db: float | None = None) -> np.ndarray:
+    """p[S][N] from frame_parts: N-pulses, plus white Gaussian noise at the
+    given SNR (seed SEED_NOISE + frame) if requested."""
+    delay, amp, dist = parts
+    p = npulse_signals(delay, amp, dist, n_samples, dt, t0)
     if noise_snr_db is not None:
         rng = np.random.Generator(np.random.PCG64(SEED_NOISE + frame))
         rms = float(np.sqrt(np.mean(p.astype(np.float64) ** 2)))
         sd = rms / (10.0 ** (noise_snr_db / 20.0))
         p = (p + sd * rng.standard_normal(p.shape)).astype(np.float32)
     return p
+
+
+def frame_for(geo: Geometry, table: np.ndarray, frame: int = 0, noise_snr_db: float | None = None,
+              phantom: str = "segments") -> np.ndarray:
+    """One synthetic frame p[S][N] for the given delay table T[S][P] (seconds).
+
+    The phantom's nodes must lie inside the ROI (true for the built-in
+    geometries); their travel times are read from the table's columns."""
+    return frame_from_parts(frame_parts(geo, table, frame, phantom), geo.n_samples, geo.dt, geo.t0, frame,
+                            noise_snr_db)
 
 
 def random_table(seed: int, S: int, P: int, n_samples: int, dt: float, t0: float = 0.0,
