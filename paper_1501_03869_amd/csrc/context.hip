@@ -46,6 +46,11 @@ long pat_env_round_cap(long builtin_cap) {
     return (end && *end == 0 && r >= 1 && r < builtin_cap) ? r : builtin_cap;
 }
 
+bool pat_env_force_win() {
+    const char *v = std::getenv("PAT_GATHER_FORCE");
+    return v && std::strcmp(v, "win") == 0;
+}
+
 int pat_devbuf::grow(size_t need) {
     if (need <= bytes) return PAT_OK;
     release();

@@ -146,6 +146,19 @@ struct DelayF32X4 : DelayF32 {
     static constexpr bool kX4 = true;
 };
 
+// Workgroups are dealt to the 8 XCDs round-robin by workgroup index, each
+// XCD with its own L2.  A tile's table row segment generally straddles cache
+// lines shared with the neighbouring tiles, so neighbouring tiles are kept on
+// one XCD: launch slot b (8 * ceil(T/8) slots) runs tile x*q + min(x, r) + k
+// of the T tiles (x = b % 8, k = b / 8, T = 8q + r), i.e. XCD x takes one
+// contiguous run of tiles; -1 for the at most 7 slots with no tile.
+__device__ __forceinline__ int xcd_tile(int b, int T) {
+    const int q = T >> 3, r = T & 7, x = b & 7, k = b >> 3;
+    return k < q + (x < r ? 1 : 0) ? x * q + min(x, r) + k : -1;
+}
+
+__host__ __device__ inline int xcd_slots(int T) { return (T + 7) & ~7; }
+
 template <int SFMT>
 __device__ __forceinline__ float load_sig(const void *sig, long i, float scale) {
     if constexpr (SFMT == PAT_SIG_F32) {

@@ -88,20 +88,6 @@ __device__ __forceinline__ float h2f(uint32_t bits16) {
     return __half2float(__ushort_as_half((unsigned short)bits16));
 }
 
-// Workgroups are dealt to the 8 XCDs round-robin by workgroup index, each
-// XCD with its own L2.  Tile rows of the table are 128 bytes that generally
-// straddle two cache lines, shared with the neighbouring tiles, so
-// neighbouring tiles are kept on one XCD: launch slot b (8 * ceil(T/8) slots)
-// runs tile x*q + min(x, r) + k of the T tiles (x = b % 8, k = b / 8,
-// T = 8q + r), i.e. XCD x takes one contiguous run of tiles; -1 for the at
-// most 7 slots with no tile.
-__device__ __forceinline__ int xcd_tile(int b, int T) {
-    const int q = T >> 3, r = T & 7, x = b & 7, k = b >> 3;
-    return k < q + (x < r ? 1 : 0) ? x * q + min(x, r) + k : -1;
-}
-
-__host__ __device__ inline int xcd_slots(int T) { return (T + 7) & ~7; }
-
 // One workgroup's work: tile `tile` of one frame, all S sensors.
 struct PxJob {
     const uint32_t *tab;  // [S][P] delays

@@ -1,0 +1,435 @@
+// Back projection of frames with many ROI positions: one wave per run of
+// consecutive table columns (PPL per lane) and a run of sensors, the signal
+// read from a window in the wave's own slice of LDS.
+//
+// The sum is the delay-and-sum of Section II-C: the UBP-filtered signal
+// b = p - t dp/dt of every sensor, read at the position's delay with linear
+// interpolation, weighted and summed over sensors.  Per sensor a wave
+//   - loads its 64 * PPL delays (16-byte loads, one contiguous run of the
+//     table row),
+//   - places a 128-sample window just below the smallest sample index among
+//     the first and last delay of every lane (a wave-wide minimum by DPP and
+//     four lane reads), less a margin for the lanes' inner columns,
+//   - loads those 128 samples, two per lane, evaluates the filter on them
+//     (central differences, the neighbouring samples taken from the adjacent
+//     lanes by DPP wave shifts) and writes them to its LDS slice,
+//   - reads b[n], b[n+1] of every gather from the window.
+// So 64 * PPL gathers cost PPL/4 + 1 vector-memory loads per lane, against
+// 5 per 256 gathers in the split-sensor kernel, where every lane loads its own
+// taps.  A delay whose interval is not inside the window (the delays of the
+// wave's positions spread over more than about 110 samples, or the record's
+// first and last samples, where the filter is one-sided) is gathered from
+// global memory instead, with the general-path arithmetic of the other
+// kernels.
+//
+// Table loads of sensor i+D and the window of sensor i+LW are in flight while
+// sensor i is summed.  The waves of a workgroup take disjoint runs of the
+// sensors, and their partial sums are added in LDS in wave order, so results
+// are reproducible run to run.
+#include <mutex>
+#include <type_traits>
+
+#include "gather_common.h"
+#include "pat_internal.h"
+
+using namespace pat_gather;
+
+namespace {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int WN_WIN = 128;              // window samples, two per lane
+constexpr int WN_MAXW = 16;              // waves per workgroup
+constexpr int WN_RSRC_W3 = 0x00020000;   // buffer descriptor word 3: raw 32-bit dwords
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wrsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, WN_RSRC_W3);
+}
+
+// DPP lane moves (all 64 lanes active): CTRL 0xB1 / 0x4E swap lanes within
+// quads, 0x141 mirrors each half-row of 8, 0x140 each row of 16; 0x138 shifts
+// the wave right by one lane (lane l reads lane l-1) and 0x130 left (lane l
+// reads lane l+1); lanes with no source read 0.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// Minimum of v over the 64 lanes, wave-uniform.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+    v = min(v, dpp<0xB1>(v));
+    v = min(v, dpp<0x4E>(v));
+    v = min(v, dpp<0x141>(v));
+    v = min(v, dpp<0x140>(v));  // every lane holds its row's minimum
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return min(min(a, b), min(c, d));
+}
+
+__device__ __forceinline__ float wh2f(uint32_t bits16) {
+    return __half2float(__ushort_as_half((unsigned short)bits16));
+}
+
+template <int PPL>
+struct Quads {
+    u32x4 q[PPL / 4];
+    __device__ __forceinline__ uint32_t at(int k) const { return q[k >> 2][k & 3]; }
+};
+
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int PPL, int D, int LW>
+__global__ void __launch_bounds__(64 * WN_MAXW)
+    k_bp_win(const uint32_t *__restrict__ tab, const void *__restrict__ sig, const float *__restrict__ scale,
+             const float *__restrict__ w, int S, int P, int N, int F, int spw, Delay dec, float t0dt,
+             float *__restrict__ img) {
+    static_assert(PPL % 4 == 0 && D % LW == 0 && D >= 2 * LW, "pipeline shape");
+    constexpr int PIX = 64 * PPL;
+    extern __shared__ float wl[];  // [waves][PIX]: a wave's window, then its partial sums
+    constexpr bool kF32T = std::is_base_of<DelayF32, Delay>::value;
+    constexpr bool F16 = SFMT == PAT_SIG_F16;
+    constexpr uint32_t esz = F16 ? 2 : 4;
+    // launch slot -> (group, frame), frames fastest: an XCD runs the frames
+    // of a group together, so their table rows are read from HBM about once
+    const int groups = (P + PIX - 1) / PIX;
+    const int gf = xcd_tile(blockIdx.x, groups * F);
+    if (gf < 0) return;
+    const int g = gf / F, f = gf - g * F;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int pb = g * PIX;
+    const int c0 = pb + PPL * lane;  // this lane's first column
+    const int s_begin = wv * spw;
+    const int ns = min(S, s_begin + spw) - s_begin;
+    const char *sigf = static_cast<const char *>(sig) + (size_t)f * S * N * esz;
+    float *wwin = wl + wv * PIX;
+    float acc[PPL];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) acc[k] = 0.0f;
+
+    // LAST: the group that ends past P, whose lanes load each column on its
+    // own (columns past P read column P-1 and are not stored)
+    auto body = [&](auto last_tag) {
+        constexpr bool LAST = decltype(last_tag)::value;
+        auto tload = [&](int i, Quads<PPL> &t) {
+            const int s = s_begin + min(i, ns - 1);
+            const __amdgpu_buffer_rsrc_t r = wrsrc(tab + (size_t)s * P, (uint32_t)P * 4u);
+            if constexpr (LAST) {
+#pragma unroll
+                for (int k = 0; k < PPL; ++k)
+                    t.q[k >> 2][k & 3] = __builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)min(c0 + k, P - 1) * 4u, 0, 0);
+            } else {
+#pragma unroll
+                for (int j = 0; j < PPL / 4; ++j)
+                    t.q[j] = __builtin_amdgcn_raw_buffer_load_b128(r, (uint32_t)c0 * 4u, 16 * j, 0);
+            }
+        };
+        auto cols = [&](const Quads<PPL> &t, uint32_t (&d)[PPL]) {
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) d[k] = t.at(k);
+        };
+        // Window anchor from the lane's first and last delay: the smallest
+        // sample index among them, less a margin for the inner columns and the
+        // filter's lower neighbour; an even start for FP16 records.  Float32
+        // sample positions are compared as bit patterns: for non-negative
+        // values that is their order, and negative ones and NaN sort last (a
+        // window placed by a delay that does not contribute costs only misses).
+        constexpr int MARGIN = PPL + (FILTERED ? 0 : 1);
+        auto key = [&](uint32_t dq) -> uint32_t {
+            if constexpr (kF32T) {
+                return __float_as_uint(dec.u1(__uint_as_float(dq)));
+            } else {
+                return dq;  // 16.16 index; the sentinel sorts last
+            }
+        };
+        auto anchor = [&](const Quads<PPL> &t) -> int {
+            uint32_t d[PPL];
+            cols(t, d);
+            const uint32_t m = wave_min(min(key(d[0]), key(d[PPL - 1])));
+            int n;
+            if constexpr (kF32T) {
+                // any u >= 2^31 (NaN, inf, negative bit patterns): window at 0
+                const float u = __uint_as_float(m);
+                n = u < 2147483648.0f ? (int)u : 0;
+            } else {
+                n = (int)(m >> 16);
+            }
+            int r0 = n - MARGIN;
+            if constexpr (F16) r0 &= ~1;
+            return __builtin_amdgcn_readfirstlane(max(0, min(r0, N - WN_WIN)));
+        };
+        auto wload = [&](int i, int r0) -> u32x2 {
+            const int s = s_begin + min(i, ns - 1);
+            const __amdgpu_buffer_rsrc_t r = wrsrc(sigf + (size_t)s * N * esz, (uint32_t)N * esz);
+            const uint32_t off = (uint32_t)(r0 + 2 * lane) * esz;
+            if constexpr (F16) {
+                u32x2 v;
+                v[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+                v[1] = 0u;
+                return v;
+            } else {
+                return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+            }
+        };
+        // b[r0 + 2l], b[r0 + 2l + 1] into the lane's two window slots (raw
+        // input: valid in slots 1 .. 126, lanes 0 and 63 lack a neighbour)
+        const float t0h = 0.5f * t0dt;
+        auto wstore = [&](const u32x2 &v, int r0) {
+            float p0, p1;
+            if constexpr (F16) {
+                p0 = wh2f(v[0] & 0xFFFFu);
+                p1 = wh2f(v[0] >> 16);
+            } else {
+                p0 = __uint_as_float(v[0]);
+                p1 = __uint_as_float(v[1]);
+            }
+            float b0 = p0, b1 = p1;
+            if constexpr (!FILTERED) {
+                const float pm = __uint_as_float(dpp<0x138>(__float_as_uint(p1)));  // p[r0 + 2l - 1]
+                const float pn = __uint_as_float(dpp<0x130>(__float_as_uint(p0)));  // p[r0 + 2l + 2]
+                const float k0 = fmaf((float)(r0 + 2 * lane), 0.5f, t0h);           // (j + t0/dt) / 2
+                b0 = fmaf(-k0, p1 - pm, p0);
+                b1 = fmaf(-(k0 + 0.5f), pn - p0, p1);
+            }
+            reinterpret_cast<float2 *>(wwin)[lane] = make_float2(b0, b1);
+        };
+        // window-relative range of n whose b[n], b[n+1] the window holds
+        constexpr int LO = FILTERED ? 0 : 1;
+        constexpr int HI = FILTERED ? WN_WIN - 1 : WN_WIN - 2;  // n < r0 + HI
+        Delay dv = dec;
+        auto gather = [&](const Quads<PPL> &t, int i, int r0) {
+            uint32_t d[PPL];
+            cols(t, d);
+            const int s = s_begin + i;
+            float ws = 1.0f;
+            if constexpr (HAS_W) ws = w[s];
+            if constexpr (kF32T) dv.off = dec.off - (float)r0;  // u relative to the window
+            bool in[PPL];
+            uint64_t anymiss = 0;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                int n;
+                float a;
+                if constexpr (kF32T) {
+                    const float u = dv.u1(__uint_as_float(d[k]));  // u - r0
+                    const float uc = __builtin_amdgcn_fmed3f(u, (float)LO, __uint_as_float(__float_as_uint((float)HI) - 1u));
+                    in[k] = uc == u;
+                    n = (int)uc;
+                    a = __builtin_amdgcn_fractf(uc);
+                } else {
+                    const int n0 = (int)(d[k] >> 16) - r0;
+                    in[k] = (uint32_t)(n0 - LO) < (uint32_t)(HI - LO);
+                    n = min(max(n0, LO), HI - 1);
+                    a = (float)(d[k] & 0xFFFFu) * (1.0f / 65536.0f);
+                }
+                const float b0 = wwin[n], b1 = wwin[n + 1];
+                const float v = fmaf(a, b1 - b0, b0);
+                if constexpr (HAS_W) {
+                    acc[k] = in[k] ? fmaf(ws, v, acc[k]) : acc[k];  // v may be NaN where not in
+                } else {
+                    acc[k] += in[k] ? v : 0.0f;
+                }
+                anymiss |= __builtin_amdgcn_ballot_w64(!in[k]);
+            }
+            if (anymiss == 0) return;
+            // delays outside the window (or not contributing): taps from
+            // global memory, the filter one-sided at both ends of the record
+            const __amdgpu_buffer_rsrc_t r = wrsrc(sigf + (size_t)(s_begin + i) * N * esz, (uint32_t)N * esz);
+            auto tap = [&](int m) -> float {
+                if constexpr (F16) return wh2f(__builtin_amdgcn_raw_buffer_load_b16(r, (uint32_t)m * 2u, 0, 0));
+                else return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)m * 4u, 0, 0));
+            };
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                if (in[k]) continue;
+                int n;
+                float a;
+                if (!dec.decode_bf1(d[k], N, n, a)) continue;  // does not contribute
+                float b0, b1;
+                if constexpr (FILTERED) {
+                    b0 = tap(n);
+                    b1 = tap(n + 1);
+                } else {
+                    const float pm = tap(max(n - 1, 0)), p0 = tap(n), p1 = tap(n + 1), p2 = tap(min(n + 2, N - 1));
+                    const float k0 = fmaf((float)n, 0.5f, t0h);
+                    const float d0 = n == 0 ? 2.0f * (p1 - p0) : p1 - pm;
+                    const float d1 = n + 1 == N - 1 ? 2.0f * (p1 - p0) : p2 - p0;
+                    b0 = fmaf(-k0, d0, p0);
+                    b1 = fmaf(-(k0 + 0.5f), d1, p1);
+                }
+                acc[k] = fmaf(ws, fmaf(a, b1 - b0, b0), acc[k]);
+            }
+        };
+
+        // Rings: table loads of D sensors, windows of LW.  Iteration i
+        // filters and stores window i, places and issues window i+LW, sums
+        // sensor i from the window and issues the table loads of sensor i+D.
+        // Loads past the wave's sensors re-read its last records.
+        Quads<PPL> T[D];
+        u32x2 Wr[LW];
+        int R0[LW];
+        // prologue in the loop's issue order (window j, then the table of
+        // sensor D - LW + j), so that the loop's first waits are its steady ones
+#pragma unroll
+        for (int j = 0; j < D - LW; ++j) tload(j, T[j]);
+#pragma unroll
+        for (int j = 0; j < LW; ++j) {
+            R0[j] = anchor(T[j]);
+            Wr[j] = wload(j, R0[j]);
+            tload(D - LW + j, T[D - LW + j]);
+        }
+        // whole blocks of D iterations (one loop state for the compiler's
+        // waits); iterations past the last sensor sum nothing
+        const int nsr = (ns + D - 1) / D * D;
+        for (int base = 0; base < nsr; base += D) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const int i = base + k;
+                const int r0 = R0[k % LW];
+                wstore(Wr[k % LW], r0);
+                R0[k % LW] = anchor(T[(k + LW) % D]);
+                Wr[k % LW] = wload(i + LW, R0[k % LW]);
+                if (i < ns) gather(T[k], i, r0);
+                tload(i + D, T[k]);
+            }
+        }
+    };
+    if (ns > 0) {
+        if (pb + PIX > P) body(std::true_type{});
+        else body(std::false_type{});
+    }
+
+    const float sc = (F16 && scale) ? scale[f] : 1.0f;  // filter and interpolation are linear
+    float *out = img + (size_t)f * P;
+    if (nw == 1) {
+#pragma unroll
+        for (int k = 0; k < PPL; ++k)
+            if (c0 + k < P) out[c0 + k] = acc[k] * sc;
+        return;
+    }
+    // partial sums in the wave's own slice (its window is no longer read)
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) wwin[PPL * lane + k] = acc[k] * sc;
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+            float s = 0.0f;
+            for (int m = 0; m < nw; ++m) s += wl[m * PIX + PPL * lane + k];
+            if (c0 + k < P) out[c0 + k] = s;
+        }
+    }
+}
+
+}  // namespace
+
+namespace {
+
+// Columns per lane, table loads and windows in flight per wave: the fastest
+// of the shapes measured on the 1024^2 workload (4 columns per lane with 8,
+// 4 or 6 loads ahead, 8 columns with 4; 1 or 2 windows ahead), 615 us
+// against 614-680 us for the others.
+constexpr int WN_PPL = 4, WN_D = 4, WN_LW = 2;
+// Waves per compute unit the launch aims at: 24 (6 per SIMD) did best on the
+// 1024^2 workload and on its first 256K and 512K columns; 12 was 5-17 %
+// slower there.
+constexpr long WN_WAVES_PER_CU = 24;
+constexpr int WN_PIX = 64 * WN_PPL;
+
+struct WinShape {
+    int groups, waves, spw;
+};
+
+// Waves per workgroup: about per_cu waves per compute unit over the launch,
+// and never more than keep every workgroup resident at once
+// (blocks_per_cu(W) * CUs >= groups * F); sensors split evenly.
+template <class BlocksPerCu>
+WinShape win_shape(int S, int P, int F, int cus, long per_cu, BlocksPerCu blocks_per_cu) {
+    WinShape s;
+    s.groups = (P + WN_PIX - 1) / WN_PIX;
+    const long wgs = (long)s.groups * std::max(F, 1);
+    int W = 1;
+    for (int cand = WN_MAXW; cand >= 1; --cand) {
+        if ((long)blocks_per_cu(cand) * cus >= wgs) { W = cand; break; }
+    }
+    const long target = (per_cu * cus + wgs / 2) / wgs;
+    W = (int)std::max(1L, std::min<long>(W, target));
+    W = std::min(W, std::max(S, 1));
+    s.spw = (std::max(S, 1) + W - 1) / W;
+    s.waves = (std::max(S, 1) + s.spw - 1) / s.spw;
+    return s;
+}
+
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W>
+int launch_win_one(int S, int P, int F, const uint32_t *tab, const void *sig, const float *scale, const float *w,
+                   int N, Delay dec, float t0dt, float *img, hipStream_t st) {
+    auto kern = k_bp_win<Delay, SFMT, FILTERED, HAS_W, WN_PPL, WN_D, WN_LW>;
+    // occupancy per block size, computed once per kernel and device
+    static std::mutex mu;
+    static int cache_dev = -1, cache_cus = 0, cache_bpc[WN_MAXW + 1];
+    int dev = 0;
+    PAT_HIP(hipGetDevice(&dev));
+    WinShape sh;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (cache_dev != dev) {
+            PAT_HIP(hipDeviceGetAttribute(&cache_cus, hipDeviceAttributeMultiprocessorCount, dev));
+            for (int W = 1; W <= WN_MAXW; ++W)
+                PAT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&cache_bpc[W], kern, 64 * W,
+                                                                     (size_t)W * WN_PIX * sizeof(float)));
+            cache_dev = dev;
+        }
+        sh = win_shape(S, P, F, cache_cus, WN_WAVES_PER_CU, [&](int W) { return cache_bpc[W]; });
+    }
+    const dim3 grid(xcd_slots(sh.groups * F));
+    kern<<<grid, dim3(64 * sh.waves), (size_t)sh.waves * WN_PIX * sizeof(float), st>>>(tab, sig, scale, w, S, P, N, F,
+                                                                                    sh.spw, dec, t0dt, img);
+    PAT_HIP(hipGetLastError());
+    return PAT_OK;
+}
+
+template <class Delay, int SFMT>
+int launch_win(bool filtered, int S, int P, int F, const uint32_t *tab, const void *sig, const float *scale,
+               const float *w, int N, Delay dec, float t0dt, float *img, hipStream_t st) {
+    if (w)
+        return filtered ? launch_win_one<Delay, SFMT, true, true>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st)
+                        : launch_win_one<Delay, SFMT, false, true>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
+    return filtered ? launch_win_one<Delay, SFMT, true, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st)
+                    : launch_win_one<Delay, SFMT, false, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
+}
+
+}  // namespace
+
+bool pat_win_eligible(int table_fmt, int sig_fmt, int S, int P, int N, int F, const void *sig) {
+    if (table_fmt != PAT_TABLE_F32 && table_fmt != PAT_TABLE_Q16) return false;
+    if (S <= 0 || F <= 0 || N < WN_WIN || P < WN_PIX || P >= (1 << 29)) return false;
+    if ((long long)((P + WN_PIX - 1) / WN_PIX) * F + 8 >= (1ll << 31)) return false;
+    if ((uintptr_t)sig % 4 != 0) return false;
+    if (sig_fmt == PAT_SIG_F16 && N % 2 != 0) return false;
+    return true;
+}
+
+int pat_launch_backproject_win(const void *table, int table_fmt, const void *sig, int sig_fmt, int sig_is_filtered,
+                               const float *frame_scale, const float *w, int S, int P, int N, int F, double t0,
+                               double dt, float *img, hipStream_t st) {
+    const float t0dt = (float)(t0 / dt);
+    const bool filt = sig_is_filtered != 0;
+    const uint32_t *tab = static_cast<const uint32_t *>(table);
+    if (table_fmt == PAT_TABLE_F32) {
+        DelayF32 d;
+        const double inv = 1.0 / dt;
+        d.inv_hi = (float)inv;
+        d.inv_lo = (float)(inv - (double)d.inv_hi);
+        d.off = (float)(-t0 / dt);
+        d.umax = (float)(N - 1);
+        return sig_fmt == PAT_SIG_F32
+                   ? launch_win<DelayF32, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
+                   : launch_win<DelayF32, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
+    }
+    DelayQ16 d;
+    return sig_fmt == PAT_SIG_F32
+               ? launch_win<DelayQ16, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
+               : launch_win<DelayQ16, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
+}

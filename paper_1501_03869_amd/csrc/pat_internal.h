@@ -27,6 +27,10 @@ size_t pat_env_fault_alloc_bytes();
 // PAT_EIK_ROUND_CAP=r, read at each table-build call: the relaxation gives up
 // with PAT_ENOCONV after r rounds when r is below the built-in cap.
 long pat_env_round_cap(long builtin_cap);
+// Test hook: PAT_GATHER_FORCE=win makes pat_backproject take the wave-window
+// gather wherever that kernel can run, so tests reach it at sizes the oracle
+// checks.
+bool pat_env_force_win();
 
 // Growable device buffer owned by a context.
 struct pat_devbuf {
@@ -110,6 +114,17 @@ int pat_launch_backproject_px_const(int nx, double h, double c, const float *d_s
 int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig, int sig_fmt, int sig_is_filtered,
                               const float *frame_scale, const float *w, int S, int P, int N, int F, double t0,
                               double dt, float *img, hipStream_t st);
+// wave-window gather: one wave per run of table columns, the signal read
+// from a per-wave LDS window (float32 or 16.16 tables, N >= 128).  Chosen for
+// tables that stream from HBM with at least PAT_WIN_MIN_P columns (two 256-
+// column groups per compute unit): on the 1024^2 workload's first 128K
+// columns it took 0.11 ms against 0.13 for the split-sensor kernel, on its
+// first 64K 0.059 against 0.054.
+constexpr int PAT_WIN_MIN_P = 131072;
+bool pat_win_eligible(int table_fmt, int sig_fmt, int S, int P, int N, int F, const void *sig);
+int pat_launch_backproject_win(const void *table, int table_fmt, const void *sig, int sig_fmt, int sig_is_filtered,
+                               const float *frame_scale, const float *w, int S, int P, int N, int F, double t0,
+                               double dt, float *img, hipStream_t st);
 // Partial sums and zeroed completion counters for one gather launch on st:
 // from the context's growable buffers, or, while ctx->fixed_active, from the
 // device's fixed array (counters cleared on st; PAT_EINVAL when they do not fit).
