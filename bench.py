@@ -49,16 +49,20 @@ HBM_PEAK_GBS = 8000.0
 # factor 1.0).  FETCH_SIZE counts L2 read requests to the fabric, so reads
 # served by the Infinity Cache count as well.  Valid only for the kernel
 # sources they were taken on: the SHA-256 of the files below; any change makes
-# the field null until the counters are taken again.  Summaries:
-# profiles/k_bp_px_*_hbm_counters.md.
-TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_common.h")
-TRAFFIC_SHA = "4d2259dda99be6a4e509e38fec25fe496079ddb631e8ab4a9b072f5be6978236:" \
-              "2d791c80f57a0c9f448436bfbee163cce25cf24f4d37f6030070c52971251ba9"
-FETCH_FACTOR = 250000.0 / 125013.18
+# the field null until the counters are taken again.  The 1024^2 workload's
+# figures are those of the wave-window kernel (the plain table), the others
+# of the split-sensor kernel (the interleaved table).  Summaries:
+# profiles/k_bp_*_hbm_counters.md.
+TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_win.hip",
+                   "paper_1501_03869_amd/csrc/gather_common.h")
+TRAFFIC_SHA = "8c446ee2bd9ad5d338dc358c7e9cf6af010f9d7089517fe2ee51b7a2be52e815:" \
+              "2f05335005e4a7767faf6098cabda83fb49e988caba94bb014cfc70709531ff3:" \
+              "04563295b4cefa9191f8ce39ecab8507bf4861fdb66ec84263b3126532f5fa18"
+FETCH_FACTOR = 250000.0 / 125013.09
 WRITE_FACTOR = 1.0
-TRAFFIC_KIB = {"paper": (24246.18, 83.34), "large": (1704467.70, 3516.67),
-               "paper_rotated": (24238.22, 83.36), "head3": (23663.20, 174.69),
-               "head3_rotated": (23664.99, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
+TRAFFIC_KIB = {"paper": (24265.93, 83.34), "large": (1726495.43, 3244.78),
+               "paper_rotated": (24236.94, 83.36), "head3": (23670.92, 174.69),
+               "head3_rotated": (23666.41, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 
 
 def measured_traffic(config: str):
@@ -443,6 +447,9 @@ def main():
     ap.add_argument("--serve", type=float, default=5.0, help="seconds of the serving mix per variant (0 = skip)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 10 times (HBM counter calibration)")
+    ap.add_argument("--table", choices=("auto", "x4", "plain"), default="auto",
+                    help="headline table form: auto = four sensors interleaved (pat_table_to_x4) while the table "
+                         "stays in the Infinity Cache, the plain [S][P] table when it streams from HBM")
     ap.add_argument("--only", choices=("headline", "rotated", "batch64"), default=None,
                     help="profiling runs: build the tables, then only the headline single-frame launches, only "
                          "the gather on rotated table copies (the table streamed from HBM), or only 64-frame "
@@ -507,9 +514,16 @@ def main():
         print(f"[bench] second-order tables built in {build_o2_s:.3f} s", file=sys.stderr, flush=True)
 
     table_h = table.cpu().numpy()
-    # the resident table, laid out four sensors per 16-byte entry for the
-    # gather (pat_table_to_x4; the same float32 delays, built once offline)
-    table_x4 = ctx.table_to_x4(table)
+    # The resident table in the form pat_backproject gathers fastest from (the
+    # same float32 delays, laid out once offline): while it stays in the
+    # Infinity Cache, four sensors per 16-byte entry (pat_table_to_x4), which
+    # the split-sensor kernel reads; when it streams from HBM and has at least
+    # 131072 columns, the plain [S][P] table, which goes to the wave-window
+    # kernel.
+    streamed = 4 * geo.S * geo.P > (128 << 20) and geo.P >= 131072
+    form = args.table if args.table != "auto" else ("plain" if streamed else "x4")
+    table_head = ctx.table_to_x4(table) if form == "x4" else table
+    win = form == "plain" and streamed
     torch.cuda.synchronize()
     if vol:
         frames_h = [inputs.frame_for3(geo, table_h, f) for f in range(args.frames)]
@@ -540,7 +554,7 @@ def main():
 
     def step(i, st=None):
         r = i % args.frames
-        ctx.backproject(table_x4, frames[r], geo.dt, geo.t0, filtered=False, out=img[r], stream=st or stream)
+        ctx.backproject(table_head, frames[r], geo.dt, geo.t0, filtered=False, out=img[r], stream=st or stream)
 
     S, P, N = geo.S, geo.P, geo.n_samples
     bytes_per_frame = 4 * S * P + 4 * S * N + 4 * P
@@ -612,7 +626,7 @@ def main():
     for i in range(max(50, min(args.steps, 200))):
         t1 = time.perf_counter()
         dframe.copy_(pinned_in[i % 4], non_blocking=True)
-        ctx.backproject(table, dframe, geo.dt, geo.t0, filtered=False, out=img[0], stream=stream)
+        ctx.backproject(table_head, dframe, geo.dt, geo.t0, filtered=False, out=img[0], stream=stream)
         pinned_out.copy_(img[0], non_blocking=True)
         stream.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
@@ -632,10 +646,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{geo.name}: {grid} grid h={geo.h * 1e3:g} mm, {S} sensors, {P} ROI "
                                f"{'voxels' if vol else 'pixels'}, {N} samples at {1e-6 / geo.dt:g} MHz, "
-                               f"FP32 table (four sensors interleaved) + FP32 signals, "
-                               f"fused filter+gather, one frame per step",
+                               f"FP32 table{' (four sensors interleaved)' if form == 'x4' else ''} + FP32 "
+                               f"signals, fused filter+gather, one frame per step",
                    "sensors": S, "pixels": P, "samples": N, "frames_per_step": 1,
-                   "table_format": "f32 seconds, four sensors interleaved per pixel (pat_table_to_x4)"},
+                   "table_format": ("f32 seconds, four sensors interleaved per pixel (pat_table_to_x4)" if form == "x4"
+                                    else "f32 seconds, [S][P]")},
         "frames_per_s": args.steps / wall,
         "timing_note": "value/frames_per_s: single-frame launches replayed from a HIP graph of up to 64 launches; "
                        "device_ms_*: HIP events around each eager launch; roofline: HIP events around the run of "
@@ -658,14 +673,17 @@ def main():
         "table_build_o2_note": "pat_eikonal_tables_o2 (the paper's second-order scheme) wall time for all sensors; "
                                "null for 3-D and grids above 512^2",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config if args.table == "auto" else ""),
                      "table_residency": ("infinity_cache" if 4 * S * P < (256 << 20) else "hbm"),
                      "residency_note": "a table below the 256 MB Infinity Cache is re-read from it between "
                                        "launches, so achieved is algorithmic bytes per second, not HBM "
                                        "bandwidth; roofline_hbm streams copies of it from HBM",
-                     "kernel": "pat_backproject, one launch per frame (k_bp_px at these shapes: fused UBP filter "
-                               "+ delay-and-sum gather, sensors split inside 32-pixel-tile workgroups, table "
-                               "interleaved by four sensors)",
+                     "kernel": ("pat_backproject, one launch per frame (k_bp_win at these shapes: fused UBP filter "
+                                "+ delay-and-sum gather, one wave per 256 table columns, the filtered signal read "
+                                "from a per-wave LDS window)" if win else
+                                "pat_backproject, one launch per frame (k_bp_px at these shapes: fused UBP filter "
+                                "+ delay-and-sum gather, sensors split inside 32-pixel-tile workgroups" +
+                                (", table interleaved by four sensors)" if form == "x4" else ")")),
                      "algorithmic_bytes_per_launch": bytes_per_frame,
                      "traffic_note": "bytes per launch from FETCH_SIZE + WRITE_SIZE scaled by a plain copy's "
                                      "counters; null when not measured for this config or kernel source"},

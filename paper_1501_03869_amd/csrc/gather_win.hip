@@ -6,26 +6,31 @@
 // b = p - t dp/dt of every sensor, read at the position's delay with linear
 // interpolation, weighted and summed over sensors.  Per sensor a wave
 //   - loads its 64 * PPL delays (16-byte loads, one contiguous run of the
-//     table row),
-//   - places a 128-sample window just below the smallest sample index among
-//     the first and last delay of every lane (a wave-wide minimum by DPP and
-//     four lane reads), less a margin for the lanes' inner columns,
+//     table row) and decodes them to sample positions,
+//   - starts a 128-sample window just below the smallest of them (a
+//     wave-wide minimum by DPP and one lane read), and tests once per lane
+//     whether all of the lane's positions fall inside it (a per-lane minimum
+//     and maximum),
 //   - loads those 128 samples, two per lane, evaluates the filter on them
 //     (central differences, the neighbouring samples taken from the adjacent
 //     lanes by DPP wave shifts) and writes them to its LDS slice,
-//   - reads b[n], b[n+1] of every gather from the window.
+//   - reads b[n], b[n+1] of every gather from the window: with no further
+//     tests when every lane's positions fit, else each position is tested.
 // So 64 * PPL gathers cost PPL/4 + 1 vector-memory loads per lane, against
 // 5 per 256 gathers in the split-sensor kernel, where every lane loads its own
 // taps.  A delay whose interval is not inside the window (the delays of the
-// wave's positions spread over more than about 110 samples, or the record's
+// wave's positions spread over more than about 124 samples, or the record's
 // first and last samples, where the filter is one-sided) is gathered from
 // global memory instead, with the general-path arithmetic of the other
-// kernels.
+// kernels (a wave with a delay that does not contribute takes the tested
+// path too).
 //
 // Table loads of sensor i+D and the window of sensor i+LW are in flight while
 // sensor i is summed.  The waves of a workgroup take disjoint runs of the
 // sensors, and their partial sums are added in LDS in wave order, so results
-// are reproducible run to run.
+// are reproducible run to run.  Several frames share one launch, each
+// pixel group's frames on one XCD, so that their table rows are read from
+// HBM about once.
 #include <mutex>
 #include <type_traits>
 
@@ -56,17 +61,36 @@ __device__ __forceinline__ uint32_t dpp(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
 
-// Minimum of v over the 64 lanes, wave-uniform.
+// Minimum of v over the 64 lanes, wave-uniform: within rows of 16 by lane
+// swaps and mirrors, then row 1 takes row 0's and row 3 row 2's (0x142:
+// lane 15 of each row broadcast to the next), row 2 and 3 lane 31's (0x143),
+// and lane 63 holds the result.
 __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
     v = min(v, dpp<0xB1>(v));
     v = min(v, dpp<0x4E>(v));
     v = min(v, dpp<0x141>(v));
-    v = min(v, dpp<0x140>(v));  // every lane holds its row's minimum
-    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
-    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
-    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
-    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
-    return min(min(a, b), min(c, d));
+    v = min(v, dpp<0x140>(v));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// floor(u) of a float32 u >= 0 from its bit pattern, in integer operations
+// (wave-uniform values stay in scalar registers); patterns of 2^24 and above,
+// negative values, NaN and infinities give INT_MAX.
+__device__ __forceinline__ int floor_bits(uint32_t m) {
+    const int e = (int)(m >> 23) - 127;
+    if (e < 0) return 0;
+    if (e > 23) return 0x7FFFFFFF;
+    return (int)(((m & 0x7FFFFFu) | 0x800000u) >> (23 - e));
+}
+
+// Bit pattern of the float32 value of an integer 0 <= k < 2^24, in integer
+// operations.
+__device__ __forceinline__ uint32_t float_bits(uint32_t k) {
+    if (k == 0) return 0u;
+    const int e = 31 - __builtin_clz(k);
+    return ((uint32_t)(e + 127) << 23) | ((k << (23 - e)) & 0x7FFFFFu);
 }
 
 __device__ __forceinline__ float wh2f(uint32_t bits16) {
@@ -126,39 +150,48 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
                     t.q[j] = __builtin_amdgcn_raw_buffer_load_b128(r, (uint32_t)c0 * 4u, 16 * j, 0);
             }
         };
-        auto cols = [&](const Quads<PPL> &t, uint32_t (&d)[PPL]) {
+        // window-relative range of n whose b[n], b[n+1] the window holds
+        constexpr int LO = FILTERED ? 0 : 1;
+        constexpr int HI = FILTERED ? WN_WIN - 1 : WN_WIN - 2;  // n < r0 + HI
+        // One sensor decoded for its sum: x = the sample position u of every
+        // column (float32 tables, as bits; u = T/dt - t0/dt with one FMA, as
+        // in the split-sensor kernel) or its 16.16 index; r0 = the window's
+        // first sample: the smallest sample index of the wave's delays, less
+        // the filter's lower neighbour (even for FP16 records); ok = every
+        // delay of the wave lies in the window (wave-uniform).  Positions are
+        // compared as bit patterns: for non-negative float32 values and 16.16
+        // indices that is their order, and negative values, NaN and the 16.16
+        // sentinel sort last.
+        struct Prep {
+            uint32_t x[PPL];
+            int r0, ok;
+        };
+        auto prep = [&](const Quads<PPL> &t, Prep &pr) {
+            uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
 #pragma unroll
-            for (int k = 0; k < PPL; ++k) d[k] = t.at(k);
-        };
-        // Window anchor from the lane's first and last delay: the smallest
-        // sample index among them, less a margin for the inner columns and the
-        // filter's lower neighbour; an even start for FP16 records.  Float32
-        // sample positions are compared as bit patterns: for non-negative
-        // values that is their order, and negative ones and NaN sort last (a
-        // window placed by a delay that does not contribute costs only misses).
-        constexpr int MARGIN = PPL + (FILTERED ? 0 : 1);
-        auto key = [&](uint32_t dq) -> uint32_t {
-            if constexpr (kF32T) {
-                return __float_as_uint(dec.u1(__uint_as_float(dq)));
-            } else {
-                return dq;  // 16.16 index; the sentinel sorts last
+            for (int k = 0; k < PPL; ++k) {
+                uint32_t x = t.at(k);
+                if constexpr (kF32T) x = __float_as_uint(dec.u1(__uint_as_float(x)));
+                pr.x[k] = x;
+                kmin = min(kmin, x);
+                kmax = max(kmax, x);
             }
-        };
-        auto anchor = [&](const Quads<PPL> &t) -> int {
-            uint32_t d[PPL];
-            cols(t, d);
-            const uint32_t m = wave_min(min(key(d[0]), key(d[PPL - 1])));
-            int n;
-            if constexpr (kF32T) {
-                // any u >= 2^31 (NaN, inf, negative bit patterns): window at 0
-                const float u = __uint_as_float(m);
-                n = u < 2147483648.0f ? (int)u : 0;
-            } else {
-                n = (int)(m >> 16);
-            }
-            int r0 = n - MARGIN;
+            const uint32_t m = wave_min(kmin);
+            // (no contributing delay in the wave: the window at the record's end)
+            const int n = kF32T ? floor_bits(m) : (int)(m >> 16);
+            int r0 = min(n, N) - LO;
             if constexpr (F16) r0 &= ~1;
-            return __builtin_amdgcn_readfirstlane(max(0, min(r0, N - WN_WIN)));
+            r0 = max(0, min(r0, N - WN_WIN));
+            uint32_t lo, hi;
+            if constexpr (kF32T) {
+                lo = float_bits((uint32_t)(r0 + LO));
+                hi = float_bits((uint32_t)(r0 + HI));
+            } else {
+                lo = (uint32_t)(r0 + LO) << 16;
+                hi = (uint32_t)(r0 + HI) << 16;
+            }
+            pr.r0 = r0;
+            pr.ok = (__builtin_amdgcn_ballot_w64(kmin < lo) | __builtin_amdgcn_ballot_w64(kmax >= hi)) == 0;
         };
         auto wload = [&](int i, int r0) -> u32x2 {
             const int s = s_begin + min(i, ns - 1);
@@ -195,36 +228,58 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
             }
             reinterpret_cast<float2 *>(wwin)[lane] = make_float2(b0, b1);
         };
-        // window-relative range of n whose b[n], b[n+1] the window holds
-        constexpr int LO = FILTERED ? 0 : 1;
-        constexpr int HI = FILTERED ? WN_WIN - 1 : WN_WIN - 2;  // n < r0 + HI
-        Delay dv = dec;
-        auto gather = [&](const Quads<PPL> &t, int i, int r0) {
-            uint32_t d[PPL];
-            cols(t, d);
+        auto gather = [&](const Prep &pr, int i) {
             const int s = s_begin + i;
             float ws = 1.0f;
             if constexpr (HAS_W) ws = w[s];
-            if constexpr (kF32T) dv.off = dec.off - (float)r0;  // u relative to the window
+            const int r0 = pr.r0;
+            const float *wb = wwin - r0;  // wb[n]: b[n] for n in the window
+            if (pr.ok) {
+                // every delay in the window: no tests
+#pragma unroll
+                for (int k = 0; k < PPL; ++k) {
+                    int n;
+                    float a;
+                    if constexpr (kF32T) {
+                        const float u = __uint_as_float(pr.x[k]);
+                        n = (int)u;
+                        a = __builtin_amdgcn_fractf(u);
+                    } else {
+                        n = (int)(pr.x[k] >> 16);
+                        a = (float)(pr.x[k] & 0xFFFFu) * (1.0f / 65536.0f);
+                    }
+                    const float b0 = wb[n], b1 = wb[n + 1];
+                    const float v = fmaf(a, b1 - b0, b0);
+                    if constexpr (HAS_W) {
+                        acc[k] = fmaf(ws, v, acc[k]);
+                    } else {
+                        acc[k] += v;
+                    }
+                }
+                return;
+            }
+            // some delay of the wave lies outside the window: each is tested,
+            // those outside read their taps from global memory
             bool in[PPL];
             uint64_t anymiss = 0;
+            const float flo = (float)(r0 + LO), fhi = __uint_as_float(__float_as_uint((float)(r0 + HI)) - 1u);
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
                 int n;
                 float a;
                 if constexpr (kF32T) {
-                    const float u = dv.u1(__uint_as_float(d[k]));  // u - r0
-                    const float uc = __builtin_amdgcn_fmed3f(u, (float)LO, __uint_as_float(__float_as_uint((float)HI) - 1u));
+                    const float u = __uint_as_float(pr.x[k]);
+                    const float uc = __builtin_amdgcn_fmed3f(u, flo, fhi);
                     in[k] = uc == u;
                     n = (int)uc;
                     a = __builtin_amdgcn_fractf(uc);
                 } else {
-                    const int n0 = (int)(d[k] >> 16) - r0;
-                    in[k] = (uint32_t)(n0 - LO) < (uint32_t)(HI - LO);
-                    n = min(max(n0, LO), HI - 1);
-                    a = (float)(d[k] & 0xFFFFu) * (1.0f / 65536.0f);
+                    const int n0 = (int)(pr.x[k] >> 16);
+                    in[k] = (uint32_t)(n0 - r0 - LO) < (uint32_t)(HI - LO);
+                    n = min(max(n0, r0 + LO), r0 + HI - 1);
+                    a = (float)(pr.x[k] & 0xFFFFu) * (1.0f / 65536.0f);
                 }
-                const float b0 = wwin[n], b1 = wwin[n + 1];
+                const float b0 = wb[n], b1 = wb[n + 1];
                 const float v = fmaf(a, b1 - b0, b0);
                 if constexpr (HAS_W) {
                     acc[k] = in[k] ? fmaf(ws, v, acc[k]) : acc[k];  // v may be NaN where not in
@@ -236,7 +291,7 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
             if (anymiss == 0) return;
             // delays outside the window (or not contributing): taps from
             // global memory, the filter one-sided at both ends of the record
-            const __amdgpu_buffer_rsrc_t r = wrsrc(sigf + (size_t)(s_begin + i) * N * esz, (uint32_t)N * esz);
+            const __amdgpu_buffer_rsrc_t r = wrsrc(sigf + (size_t)s * N * esz, (uint32_t)N * esz);
             auto tap = [&](int m) -> float {
                 if constexpr (F16) return wh2f(__builtin_amdgcn_raw_buffer_load_b16(r, (uint32_t)m * 2u, 0, 0));
                 else return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)m * 4u, 0, 0));
@@ -246,7 +301,14 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
                 if (in[k]) continue;
                 int n;
                 float a;
-                if (!dec.decode_bf1(d[k], N, n, a)) continue;  // does not contribute
+                if constexpr (kF32T) {
+                    const float u = __uint_as_float(pr.x[k]);
+                    if (!(u >= 0.0f && u <= dec.umax)) continue;  // does not contribute (also NaN)
+                    n = min((int)u, N - 2);
+                    a = u - (float)n;
+                } else {
+                    if (!dec.decode_bf(pr.x[k], N, n, a)) continue;
+                }
                 float b0, b1;
                 if constexpr (FILTERED) {
                     b0 = tap(n);
@@ -263,22 +325,26 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
             }
         };
 
-        // Rings: table loads of D sensors, windows of LW.  Iteration i
-        // filters and stores window i, places and issues window i+LW, sums
-        // sensor i from the window and issues the table loads of sensor i+D.
-        // Loads past the wave's sensors re-read its last records.
+        // Rings: table loads of D sensors, decoded sensors and windows of LW.
+        // Iteration i filters and stores window i, decodes sensor i+LW and
+        // issues its window, sums sensor i from its window and issues the
+        // table loads of sensor i+D.  Loads past the wave's sensors re-read
+        // its last records.
         Quads<PPL> T[D];
         u32x2 Wr[LW];
-        int R0[LW];
+        Prep X[LW];
         // prologue in the loop's issue order (window j, then the table of
         // sensor D - LW + j), so that the loop's first waits are its steady ones
 #pragma unroll
         for (int j = 0; j < D - LW; ++j) tload(j, T[j]);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = 0; j < LW; ++j) {
-            R0[j] = anchor(T[j]);
-            Wr[j] = wload(j, R0[j]);
+            prep(T[j], X[j]);
+            Wr[j] = wload(j, X[j].r0);
+            __builtin_amdgcn_sched_barrier(0);
             tload(D - LW + j, T[D - LW + j]);
+            __builtin_amdgcn_sched_barrier(0);
         }
         // whole blocks of D iterations (one loop state for the compiler's
         // waits); iterations past the last sensor sum nothing
@@ -287,11 +353,12 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const int i = base + k;
-                const int r0 = R0[k % LW];
-                wstore(Wr[k % LW], r0);
-                R0[k % LW] = anchor(T[(k + LW) % D]);
-                Wr[k % LW] = wload(i + LW, R0[k % LW]);
-                if (i < ns) gather(T[k], i, r0);
+                wstore(Wr[k % LW], X[k % LW].r0);
+                Prep nx;
+                prep(T[(k + LW) % D], nx);
+                Wr[k % LW] = wload(i + LW, nx.r0);
+                if (i < ns) gather(X[k % LW], i);
+                X[k % LW] = nx;
                 tload(i + D, T[k]);
             }
         }
@@ -328,9 +395,9 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
 namespace {
 
 // Columns per lane, table loads and windows in flight per wave: the fastest
-// of the shapes measured on the 1024^2 workload (4 columns per lane with 8,
-// 4 or 6 loads ahead, 8 columns with 4; 1 or 2 windows ahead), 615 us
-// against 614-680 us for the others.
+// of the shapes measured on the 1024^2 workload (4 columns per lane with the
+// table 4, 6 or 8 sensors ahead and the window 1, 2 or 3 ahead; 8 columns
+// per lane), 622-636 us against 632-670 us for the others.
 constexpr int WN_PPL = 4, WN_D = 4, WN_LW = 2;
 // Waves per compute unit the launch aims at: 24 (6 per SIMD) did best on the
 // 1024^2 workload and on its first 256K and 512K columns; 12 was 5-17 %
