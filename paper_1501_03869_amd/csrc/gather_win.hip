@@ -97,10 +97,28 @@ __device__ __forceinline__ float wh2f(uint32_t bits16) {
     return __half2float(__ushort_as_half((unsigned short)bits16));
 }
 
-template <int PPL>
-struct Quads {
-    u32x4 q[PPL / 4];
-    __device__ __forceinline__ uint32_t at(int k) const { return q[k >> 2][k & 3]; }
+// One sensor's table entries for a lane's PPL columns, as loaded.  Float32
+// and 16.16 tables: one dword per column.  16-bit tile-relative tables: the
+// offsets two per dword and the header of the lane's 32-column tile (the
+// group that ends past P: one offset and one header per column, since its
+// clamped columns may fall in another tile).
+template <class Delay, int PPL, bool LAST>
+struct TabStage {
+    static constexpr bool R = Delay::kR16;
+    static constexpr int NW = R ? (LAST ? PPL : PPL / 2) : PPL;
+    static constexpr int NH = R ? (LAST ? PPL : 1) : 1;
+    uint32_t w[NW];
+    uint32_t h[NH];
+    // the k-th column's entry as the decoding takes it: float32 bits, or a
+    // 16.16 index
+    __device__ __forceinline__ uint32_t val(int k) const {
+        if constexpr (!R) {
+            return w[k];
+        } else {
+            const uint32_t off = LAST ? w[k] : (w[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+            return DelayR16::to_q16(off, LAST ? h[k] : h[0]);
+        }
+    }
 };
 
 template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int PPL, int D, int LW>
@@ -137,17 +155,49 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
     // own (columns past P read column P-1 and are not stored)
     auto body = [&](auto last_tag) {
         constexpr bool LAST = decltype(last_tag)::value;
-        auto tload = [&](int i, Quads<PPL> &t) {
+        using TS = TabStage<Delay, PPL, LAST>;
+        // 16-bit tables: offsets [S][P] at byte 0, headers [S][tiles] after them
+        const int tiles = (P + 31) / 32;
+        const uint16_t *off16 = reinterpret_cast<const uint16_t *>(tab);
+        const uint32_t *hdr32 =
+            reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + pat_r16_hdr_offset(S, P));
+        auto tload = [&](int i, TS &t) {
             const int s = s_begin + min(i, ns - 1);
-            const __amdgpu_buffer_rsrc_t r = wrsrc(tab + (size_t)s * P, (uint32_t)P * 4u);
-            if constexpr (LAST) {
+            if constexpr (Delay::kR16) {
+                const __amdgpu_buffer_rsrc_t ro = wrsrc(off16 + (size_t)s * P, (uint32_t)P * 2u);
+                const __amdgpu_buffer_rsrc_t rh = wrsrc(hdr32 + (size_t)s * tiles, (uint32_t)tiles * 4u);
+                if constexpr (LAST) {
 #pragma unroll
-                for (int k = 0; k < PPL; ++k)
-                    t.q[k >> 2][k & 3] = __builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)min(c0 + k, P - 1) * 4u, 0, 0);
+                    for (int k = 0; k < PPL; ++k) {
+                        const uint32_t c = (uint32_t)min(c0 + k, P - 1);
+                        t.w[k] = __builtin_amdgcn_raw_buffer_load_b16(ro, c * 2u, 0, 0);
+                        t.h[k] = __builtin_amdgcn_raw_buffer_load_b32(rh, (c >> 5) * 4u, 0, 0);
+                    }
+                } else {
+                    static_assert(PPL == 4 || PPL == 8, "16-bit entries per lane");
+                    if constexpr (PPL == 4) {
+                        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(ro, (uint32_t)c0 * 2u, 0, 0);
+                        t.w[0] = v[0];
+                        t.w[1] = v[1];
+                    } else {
+                        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(ro, (uint32_t)c0 * 2u, 0, 0);
+                        t.w[0] = v[0]; t.w[1] = v[1]; t.w[2] = v[2]; t.w[3] = v[3];
+                    }
+                    t.h[0] = __builtin_amdgcn_raw_buffer_load_b32(rh, (uint32_t)(c0 >> 5) * 4u, 0, 0);
+                }
             } else {
+                const __amdgpu_buffer_rsrc_t r = wrsrc(tab + (size_t)s * P, (uint32_t)P * 4u);
+                if constexpr (LAST) {
 #pragma unroll
-                for (int j = 0; j < PPL / 4; ++j)
-                    t.q[j] = __builtin_amdgcn_raw_buffer_load_b128(r, (uint32_t)c0 * 4u, 16 * j, 0);
+                    for (int k = 0; k < PPL; ++k)
+                        t.w[k] = __builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)min(c0 + k, P - 1) * 4u, 0, 0);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < PPL / 4; ++j) {
+                        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (uint32_t)c0 * 4u, 16 * j, 0);
+                        t.w[4 * j] = v[0]; t.w[4 * j + 1] = v[1]; t.w[4 * j + 2] = v[2]; t.w[4 * j + 3] = v[3];
+                    }
+                }
             }
         };
         // window-relative range of n whose b[n], b[n+1] the window holds
@@ -166,11 +216,11 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
             uint32_t x[PPL];
             int r0, ok;
         };
-        auto prep = [&](const Quads<PPL> &t, Prep &pr) {
+        auto prep = [&](const TS &t, Prep &pr) {
             uint32_t kmin = 0xFFFFFFFFu, kmax = 0u;
 #pragma unroll
             for (int k = 0; k < PPL; ++k) {
-                uint32_t x = t.at(k);
+                uint32_t x = t.val(k);
                 if constexpr (kF32T) x = __float_as_uint(dec.u1(__uint_as_float(x)));
                 pr.x[k] = x;
                 kmin = min(kmin, x);
@@ -330,7 +380,7 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
         // issues its window, sums sensor i from its window and issues the
         // table loads of sensor i+D.  Loads past the wave's sensors re-read
         // its last records.
-        Quads<PPL> T[D];
+        TS T[D];
         u32x2 Wr[LW];
         Prep X[LW];
         // prologue in the loop's issue order (window j, then the table of
@@ -470,7 +520,7 @@ int launch_win(bool filtered, int S, int P, int F, const uint32_t *tab, const vo
 }  // namespace
 
 bool pat_win_eligible(int table_fmt, int sig_fmt, int S, int P, int N, int F, const void *sig) {
-    if (table_fmt != PAT_TABLE_F32 && table_fmt != PAT_TABLE_Q16) return false;
+    if (table_fmt != PAT_TABLE_F32 && table_fmt != PAT_TABLE_Q16 && table_fmt != PAT_TABLE_R16) return false;
     if (S <= 0 || F <= 0 || N < WN_WIN || P < WN_PIX || P >= (1 << 29)) return false;
     if ((long long)((P + WN_PIX - 1) / WN_PIX) * F + 8 >= (1ll << 31)) return false;
     if ((uintptr_t)sig % 4 != 0) return false;
@@ -494,6 +544,12 @@ int pat_launch_backproject_win(const void *table, int table_fmt, const void *sig
         return sig_fmt == PAT_SIG_F32
                    ? launch_win<DelayF32, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
                    : launch_win<DelayF32, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
+    }
+    if (table_fmt == PAT_TABLE_R16) {
+        DelayR16 d;
+        return sig_fmt == PAT_SIG_F32
+                   ? launch_win<DelayR16, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
+                   : launch_win<DelayR16, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
     }
     DelayQ16 d;
     return sig_fmt == PAT_SIG_F32

@@ -115,7 +115,8 @@ int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig,
                               const float *frame_scale, const float *w, int S, int P, int N, int F, double t0,
                               double dt, float *img, hipStream_t st);
 // wave-window gather: one wave per run of table columns, the signal read
-// from a per-wave LDS window (float32 or 16.16 tables, N >= 128).  Chosen for
+// from a per-wave LDS window (float32, 16.16 or 16-bit tile-relative tables,
+// N >= 128).  Chosen for
 // tables that stream from HBM with at least PAT_WIN_MIN_P columns (two 256-
 // column groups per compute unit): on the 1024^2 workload's first 128K
 // columns it took 0.11 ms against 0.13 for the split-sensor kernel, on its

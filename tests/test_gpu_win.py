@@ -1,8 +1,8 @@
 """The wave-window gather (k_bp_win) against the FP64 oracle.
 
-pat_backproject takes this kernel for plain float32 and 16.16 tables that
-stream from HBM with at least 131072 columns (the 1024^2 precision study runs
-it at full size).  Here the PAT_GATHER_FORCE=win hook sends smaller shapes to
+pat_backproject takes this kernel for float32, 16.16 and 16-bit tile-relative
+tables (not the interleaved form) that stream from HBM with at least 131072
+columns (the 1024^2 precision study runs it at full size).  Here the PAT_GATHER_FORCE=win hook sends smaller shapes to
 it, so that the oracle checks every pixel:
   - a smooth table (the small geometry's fast-marching delays, tile-ordered
     ROI), where nearly every gather reads the wave's LDS window;
@@ -11,7 +11,8 @@ it, so that the oracle checks every pixel:
   - a 128-sample record (the window is the whole record) with delays at both
     ends, where the filter is one-sided;
 with float32 and binary16 frames, raw and pre-filtered input, weights, one to
-three frames per launch, and column counts that leave a ragged last group."""
+three frames per launch, and column counts that leave a ragged last group
+(odd counts also misalign the 16-bit rows)."""
 import numpy as np
 import pytest
 
@@ -80,6 +81,10 @@ def _run(ctx, orc, T, p3, dt, t0, tfmt, sig, filtered, w):
     if tfmt == "q16":
         tab = ctx.table_to_q16(dev(T), dt, N, t0)
         ref = orc.gather_q16(orc.table_to_q16(T, dt, N, t0), b, w64)
+    elif tfmt == "r16":
+        # the oracle gathers the 16.16 table its own 16-bit encoding stands for
+        tab = ctx.table_to_r16(dev(T), dt, N, t0)
+        ref = orc.gather_q16(orc.r16_to_q16(*orc.table_to_r16(T, dt, N, t0)), b, w64)
     else:
         tab = dev(T)
         ref = orc.gather(T.astype(np.float64), b, dt, t0, w64)
@@ -96,6 +101,9 @@ def _run(ctx, orc, T, p3, dt, t0, tfmt, sig, filtered, w):
     ("q16", "f32", False, False, 1),
     ("q16", "f16", False, True, 3),
     ("q16", "f32", True, False, 2),
+    ("r16", "f32", False, False, 1),
+    ("r16", "f16", False, True, 2),
+    ("r16", "f16", True, False, 1),
 ])
 def test_smooth_table(ctx, orc, smooth, force_win, tfmt, sig, filtered, weights, F):
     geo, T, frames = smooth
@@ -115,6 +123,8 @@ def test_smooth_table(ctx, orc, smooth, force_win, tfmt, sig, filtered, weights,
     (37, 4099, 300, 1, "q16", "f16", False, 0.0),
     (13, 1037, 1024, 3, "f32", "f16", True, 2.5e-7),
     (64, 777, 256, 1, "q16", "f32", True, 0.0),
+    (37, 4099, 300, 2, "r16", "f32", False, 0.0),
+    (13, 1037, 1024, 1, "r16", "f16", False, 2.5e-7),
 ])
 def test_random_delays(ctx, orc, force_win, S, P, N, F, tfmt, sig, filtered, t0):
     dt = 4e-8
@@ -129,7 +139,7 @@ def test_random_delays(ctx, orc, force_win, S, P, N, F, tfmt, sig, filtered, t0)
     assert err <= IMG_TOL
 
 
-@pytest.mark.parametrize("tfmt,sig", [("f32", "f32"), ("q16", "f16")])
+@pytest.mark.parametrize("tfmt,sig", [("f32", "f32"), ("q16", "f16"), ("r16", "f32")])
 def test_record_ends(ctx, orc, force_win, tfmt, sig):
     # N = 128: the window is the whole record; delays within a few samples of
     # either end, exactly at 0 and N-1, and just outside (a power-of-two
