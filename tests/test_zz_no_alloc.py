@@ -3,8 +3,9 @@ scratch taken from the device's fixed array.  Its images must equal
 pat_backproject's bit for bit, on two calls in a row (the second with a
 smaller input, so stale partial sums or counters of the first would show),
 for the shapes that use scratch: the LDS-windowed kernel over several sensor
-groups and the batched kernel; and it must allocate nothing, which a context
-that refuses every device allocation shows."""
+groups and the batched kernel (and for the split-sensor and wave-window
+kernels, which use none); and it must allocate nothing, which a context that
+refuses every device allocation shows."""
 import os
 
 import numpy as np
@@ -53,6 +54,9 @@ CASES = {
     "batched": [(320, 120000, 64, 3, True), (280, 121000, 64, 2, True)],
     # the split-sensor kernel (no scratch) through the same entry point
     "split_sensor": [(512, 21336, 2048, 1, False), (64, 4099, 1024, 1, True)],
+    # tables above 128 MiB with at least 131072 columns: the wave-window
+    # kernel (no scratch)
+    "wave_window": [(256, 140000, 256, 2, True), (260, 135000, 200, 1, False)],
 }
 
 
@@ -62,7 +66,7 @@ def test_noalloc_equals_backproject_on_two_calls(case):
     try:
         for i, (S, P, N, F, f16) in enumerate(CASES[case]):
             need = pat.backproject_scratch_bytes(S, P, F)
-            if case != "split_sensor":
+            if case in ("windowed", "batched"):
                 assert need > 0, (case, S, P, F)
             assert need < pat.NOALLOC_SCRATCH_BYTES
             print(f"[noalloc] {case} call {i}: S={S} P={P} N={N} F={F} fp16={f16} scratch<={need}", flush=True)
