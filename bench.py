@@ -157,6 +157,54 @@ def rotated_tables(ctx, geo, table, frames, img, stream, steps):
                             "fabric, Infinity Cache hits included"}
 
 
+def large_hbm(ctx, stream, steps=50, warmup=10):
+    """The 1024^2 workload's table (1024 sensors x 823 592 pixels, 3.37 GB,
+    built here by pat_eikonal_tables) gathered by pat_backproject in the form
+    it is fastest with (the plain [S][P] table: the wave-window kernel), one
+    launch per frame: a table that always streams from HBM.  One white-noise
+    frame (the content does not change the work).  Mean launch duration from
+    HIP events around back-to-back launches."""
+    import torch
+    from paper_1501_03869_amd import inputs, pat
+    geo = inputs.config("large")
+    geo.pix = pat.tile_order(geo.nx, geo.ny, geo.pix, 32, 32)
+    dev = torch.device("cuda")
+    S, P, N = geo.S, geo.P, geo.n_samples
+    t = time.perf_counter()
+    table = ctx.eikonal_tables(torch.from_numpy(geo.speed).to(dev), geo.h, geo.sensors,
+                               torch.from_numpy(geo.pix).to(dev))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    frame = torch.from_numpy(inputs.random_signals(11, S, N)).to(dev)
+    img = torch.empty(P, dtype=torch.float32, device=dev)
+
+    def one():
+        ctx.backproject(table, frame, geo.dt, geo.t0, filtered=False, out=img, stream=stream)
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        one()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    tl = e0.elapsed_time(e1) * 1e-3 / steps
+    b = 4 * S * P + 4 * S * N + 4 * P
+    del table, frame, img
+    torch.cuda.empty_cache()
+    return {"bound": "hbm", "achieved": b / tl / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": b / tl / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic("large"),
+            "workload": "large: 1024x1024 grid h=0.05 mm, 1024 sensors, 823592 ROI pixels, 4096 samples at 40 MHz, "
+                        "FP32 table [S][P] (3.37 GB) + FP32 signals, fused filter+gather, one frame per launch",
+            "kernel": "pat_backproject (k_bp_win at this shape)", "device_ms_per_frame_mean": tl * 1e3,
+            "gathers_per_s": S * P / tl, "algorithmic_bytes_per_launch": b, "table_build_s": build_s,
+            "timing_note": "HIP events around back-to-back launches on one resident table that does not fit the "
+                           "256 MB Infinity Cache (one white-noise frame)",
+            "traffic_note": "FETCH_SIZE + WRITE_SIZE of bench.py --config large --only headline, scaled by a plain "
+                            "copy's counters; null when not measured for this kernel source"}
+
+
 def _frame_worker(args):
     from paper_1501_03869_amd import inputs
     parts, N, dt, t0, f, snr = args
@@ -444,6 +492,8 @@ def main():
     ap.add_argument("--frames", type=int, default=8, help="distinct resident frames cycled through")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the reduced-precision and batched variants")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 1024^2 workload's HBM-streamed gather block (paper config only)")
     ap.add_argument("--serve", type=float, default=5.0, help="seconds of the serving mix per variant (0 = skip)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 10 times (HBM counter calibration)")
@@ -692,6 +742,9 @@ def main():
     rh = rotated_tables(ctx, geo, table, frames, img, stream, args.steps)
     if rh is not None:
         out["roofline_hbm"] = rh
+    if args.config == "paper" and not args.no_large:
+        # the same gather on the 1024^2 workload, whose table streams from HBM
+        out["roofline_large_hbm"] = large_hbm(ctx, stream)
     if not args.no_variants:
         out["variants"] = run_variants(ctx, geo, table, frames, frames_h, stream, timed, args,
                                        table_h=None if vol else table_h)
