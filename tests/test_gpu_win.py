@@ -171,3 +171,24 @@ def test_same_as_the_other_kernels_and_reproducible(ctx, smooth, monkeypatch):
     print(f"[win] against the split-sensor kernel: rel L2 {rel_l2(a, other):.3e}", flush=True)
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
     assert rel_l2(a, other) <= 1e-5
+
+
+@pytest.mark.parametrize("S,P,N,F,tfmt,sig", [
+    (1, 256, 128, 1, "f32", "f32"),     # one sensor, exactly one group of 256 columns
+    (2, 257, 130, 2, "f32", "f16"),     # a last group with one column
+    (5, 511, 300, 5, "q16", "f32"),     # more waves than sensors would fill: one sensor per wave
+    (3, 1280, 256, 3, "r16", "f16"),    # whole groups only, three frames
+])
+def test_small_shapes(ctx, orc, force_win, S, P, N, F, tfmt, sig):
+    dt = 5e-8
+    # delays inside the record with a compact spread per group, as a tile-ordered ROI gives
+    rng = np.random.default_rng(200 + S)
+    base = rng.uniform(2.0, N - 70.0, (S, 1))
+    u = base + rng.uniform(0.0, 60.0, (S, P))
+    T = (u * dt).astype(np.float32)
+    p = inputs.random_signals(201 + S, S, N, F)
+    p3 = p if F > 1 else p[None]
+    got, ref = _run(ctx, orc, T, p3, dt, 0.0, tfmt, sig, False, None)
+    err = rel_l2(got, ref)
+    print(f"[win] small shape S={S} P={P} N={N} F={F} {tfmt} {sig}: rel L2 {err:.3e}", flush=True)
+    assert err <= IMG_TOL
