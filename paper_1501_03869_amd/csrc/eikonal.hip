@@ -13,8 +13,11 @@
 //    one-node halo into LDS and relaxes it in place until no node changes
 //    (workgroup OR-reduction), then writes the changed nodes back and
 //    activates the neighbour tiles whose shared edge changed.  Rounds repeat
-//    until no tile is active.  Values only decrease, so every relaxation
-//    order reaches the same fixed point.
+//    until no tile is active.  Values only decrease, and a sweep that changes
+//    nothing leaves every node at its update.  The update rounds to whole
+//    fixed-point units, so it is monotone only to within a unit: the
+//    relaxation order (the workgroup schedule) can move a node by a unit or
+//    two, about one float32 ulp in a few entries per million.
 //  * The local update is computed in FP32 from the exact integer difference
 //    d = |a - b| of the two upwind neighbours:
 //    T = min(a, b) + F when d >= F, else min(a, b) + (d + sqrt(2 F^2 - d^2)) / 2,
@@ -128,58 +131,78 @@ __global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ 
         T[l] = in ? map[(long)gy * g.nx + gx] : TQ_INF;
     }
 
-    // this thread's nodes: column lx, rows 4*strip .. 4*strip+3
+    // This thread's nodes in the two sweep layouts: column lx, rows
+    // 4*strip .. 4*strip+3 (layout C), and row lx, columns 4*strip ..
+    // 4*strip+3 (layout R).  Sweeps alternate C down, R right, C up, R left:
+    // information crosses a thread's four nodes within one sweep, along y in
+    // layout C and along x in layout R, instead of along y only.
+    __shared__ float Fl[TS * TS];
     const int lx = tid % TS;
     const int strip = tid / TS;
     const int gx = gx0 + lx;
-    float F[ROWS_PER_THREAD];
-    uint32_t own[ROWS_PER_THREAD];
-    unsigned live = 0;  // bit q: node q is inside the grid and not frozen
+    uint32_t own0[ROWS_PER_THREAD];  // layout C values at the start of the visit
+    unsigned live_c = 0, live_r = 0;  // bit q: node q is inside the grid and not frozen
     for (int q = 0; q < ROWS_PER_THREAD; ++q) {
         const int ly = strip * ROWS_PER_THREAD + q;
         const int gy = gy0 + ly;
         const bool in = gx < g.nx && gy < g.ny;
         uint32_t v = TQ_INF;
-        F[q] = 0.0f;
+        float f = 0.0f;
         if (in) {
             v = map[(long)gy * g.nx + gx];
-            F[q] = Fmap[(long)gy * g.nx + gx];
+            f = Fmap[(long)gy * g.nx + gx];
             uint32_t sv;
-            if (!is_frozen(gx, gy, seed_ij, seed_val, m, sv)) live |= 1u << q;
+            if (!is_frozen(gx, gy, seed_ij, seed_val, m, sv)) live_c |= 1u << q;
         }
-        own[q] = v;
+        own0[q] = v;
         T[(ly + 1) * HS + lx + 1] = v;
+        Fl[ly * TS + lx] = f;
+        // layout R: node (4*strip + q, lx)
+        const int rx = gx0 + strip * ROWS_PER_THREAD + q, ry = gy0 + lx;
+        uint32_t sv;
+        if (rx < g.nx && ry < g.ny && !is_frozen(rx, ry, seed_ij, seed_val, m, sv)) live_r |= 1u << q;
     }
     __syncthreads();
+    float Fc[ROWS_PER_THREAD], Fr[ROWS_PER_THREAD];
+    for (int q = 0; q < ROWS_PER_THREAD; ++q) {
+        Fc[q] = Fl[(strip * ROWS_PER_THREAD + q) * TS + lx];
+        Fr[q] = Fl[lx * TS + strip * ROWS_PER_THREAD + q];
+    }
 
-    unsigned changed = 0;
     unsigned int *guard = counters + 1;
     int it = 0;
+    // one node of a sweep (q static, so the per-node registers stay registers)
+    auto relax = [&](bool rows, int q, int &any) {
+        if (!((rows ? live_r : live_c) & (1u << q))) return;
+        const int n = strip * ROWS_PER_THREAD + q;
+        const int c = rows ? (lx + 1) * HS + n + 1 : (n + 1) * HS + lx + 1;
+        const uint32_t a = min(T[c - 1], T[c + 1]);
+        const uint32_t b = min(T[c - HS], T[c + HS]);
+        const uint32_t nv = godunov_q(a, b, rows ? Fr[q] : Fc[q], guard);
+        if (nv < T[c]) {
+            T[c] = nv;
+            any = 1;
+        }
+    };
     for (; it < LOCAL_ITER_CAP; ++it) {
         int any = 0;
-        // alternate the strip direction so information crosses a strip in one pass
-        for (int qq = 0; qq < ROWS_PER_THREAD; ++qq) {
-            const int q = (it & 1) ? ROWS_PER_THREAD - 1 - qq : qq;
-            if (!(live & (1u << q))) continue;
-            const int c = (strip * ROWS_PER_THREAD + q + 1) * HS + lx + 1;
-            const uint32_t a = min(T[c - 1], T[c + 1]);
-            const uint32_t b = min(T[c - HS], T[c + HS]);
-            const uint32_t nv = godunov_q(a, b, F[q], guard);
-            if (nv < own[q]) {
-                own[q] = nv;
-                T[c] = nv;
-                changed |= 1u << q;
-                any = 1;
-            }
+        const bool rows = it & 1;  // layout R on odd sweeps
+        if ((it >> 1) & 1) {       // up / left on every other sweep of a layout
+#pragma unroll
+            for (int q = ROWS_PER_THREAD - 1; q >= 0; --q) relax(rows, q, any);
+        } else {
+#pragma unroll
+            for (int q = 0; q < ROWS_PER_THREAD; ++q) relax(rows, q, any);
         }
         if (!__syncthreads_or(any)) break;
     }
 
     unsigned sides = 0;
     for (int q = 0; q < ROWS_PER_THREAD; ++q) {
-        if (!(changed & (1u << q))) continue;
         const int ly = strip * ROWS_PER_THREAD + q;
-        map[(long)(gy0 + ly) * g.nx + gx] = own[q];
+        const uint32_t v = T[(ly + 1) * HS + lx + 1];
+        if (v == own0[q]) continue;  // values only decrease: unchanged
+        map[(long)(gy0 + ly) * g.nx + gx] = v;
         if (ly == 0) sides |= 1u;
         if (ly == TS - 1) sides |= 2u;
         if (lx == 0) sides |= 4u;
