@@ -313,16 +313,19 @@ int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, doubl
  * for fixed inputs and sizes.  Uses context scratch of
  * pat_backproject_scratch_bytes(S, P, F) bytes (allocated on first need, or
  * up front by pat_ctx_reserve).  Kernel choice (results agree to the stated
- * tolerances, not bitwise, across kernels): with F >= 2, a table above
- * 128 MiB, N a multiple of 8 (FP16) or 4 (FP32) and d_sig 16-byte aligned,
- * one launch reads the table once per 16 frames; otherwise, when N >= 4 and
- * d_sig is aligned to its sample size, the sensors of each 32-pixel tile
- * are split inside one workgroup (no scratch) for several frames or for a
- * frame too small to fill the GPU otherwise; the remaining shapes use
- * LDS-windowed workgroups over sensor groups, which add their partial sums
- * in scratch.  PAT_TABLE_R16 and PAT_TABLE_F32X4 tables always take the
- * split-sensor kernel and need N >= 4 and an aligned d_sig (else
- * PAT_EINVAL).
+ * tolerances, not bitwise, across kernels): a table above 128 MiB (half the
+ * Infinity Cache) with at least 131072 columns, in any format but
+ * PAT_TABLE_F32X4, with N >= 128 and d_sig 4-byte aligned (and N even for
+ * FP16), takes one wave per 256 columns reading each sensor's filtered
+ * signal from a per-wave window in LDS (no scratch), for any F; else, with
+ * F >= 2, a table above 128 MiB, N a multiple of 8 (FP16) or 4 (FP32) and
+ * d_sig 16-byte aligned, one launch reads the table once per 16 frames;
+ * otherwise, when N >= 4 and d_sig is aligned to its sample size, the
+ * sensors of each 32-pixel tile are split inside one workgroup (no scratch)
+ * for several frames or for a frame too small to fill the GPU otherwise;
+ * the remaining shapes use LDS-windowed workgroups over sensor groups, which
+ * add their partial sums in scratch.  PAT_TABLE_R16 and PAT_TABLE_F32X4
+ * tables need N >= 4 and an aligned d_sig (else PAT_EINVAL).
  */
 int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,

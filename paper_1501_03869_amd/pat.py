@@ -276,7 +276,8 @@ class Context:
 
     def backproject(self, table, sig, dt: float, t0: float = 0.0, *, filtered: bool = True, w=None,
                     frame_scale=None, out=None, stream=None, noalloc: bool = False):
-        """table: [S][P] float32 seconds or int32 (16.16 bits); sig: [S][N] or [F][S][N] float32/float16.
+        """table: [S][P] float32 seconds or int32 (16.16 bits), or an R16Table / X4Table from
+        table_to_r16 / table_to_x4; sig: [S][N] or [F][S][N] float32/float16.
         noalloc: call pat_backproject_noalloc (gather scratch from the device's fixed array); `out` must then
         be given, so that the call allocates nothing."""
         import torch
