@@ -532,21 +532,21 @@ int pat_launch_backproject(pat_ctx *ctx, const void *table, int table_fmt, const
     if (S == 0) {
         return launch_zero(img, (long)P * F, st);
     }
-    // Kernel choice.  A table that streams from HBM (above half the 256 MB
-    // Infinity Cache) with at least PAT_WIN_MIN_P columns, in any form but
-    // the interleaved one, takes the wave-window kernel whatever the frame
-    // count (1024^2 workload: 0.62 ms per frame against 0.81 for the
-    // split-sensor kernel on the interleaved table; 16 frames per launch:
-    // 0.39 against 0.64 ms per frame for the batched kernel).  Several
-    // frames whose table stays in the cache between frames are fastest with
-    // the split-sensor kernel, one table read per frame (paper workload, 64
-    // frames: 10 us per frame against 17 for the batched kernel); other large
-    // tables are read once per 16 frames by the batched kernel.  A single
-    // frame that would split its sensors over workgroups takes the
-    // split-sensor kernel; the rest take the windowed kernel.
+    // Kernel choice.  A table above half the 256 MB Infinity Cache, in any
+    // form but the interleaved one, takes the wave-window kernel when it has
+    // PAT_WIN_MIN_P columns or, for several frames, enough (group, frame)
+    // pairs to fill the GPU (1024^2 workload: 0.62 ms per frame against 0.81
+    // for the split-sensor kernel on the interleaved table; 16 frames per
+    // launch: 0.22 against 0.64 ms per frame for the batched kernel).
+    // Several frames whose table stays in the cache between frames are
+    // fastest with the split-sensor kernel, one table read per frame (paper
+    // workload, 64 frames: 10 us per frame against 17 for the batched
+    // kernel); other large tables are read once per 16 frames by the batched
+    // kernel.  A single frame that would split its sensors over workgroups
+    // takes the split-sensor kernel; the rest take the windowed kernel.
     const bool px_ok = pat_px_eligible(sig_fmt, S, P, N, F, sig);
     const size_t table_bytes = table_fmt == PAT_TABLE_R16 ? pat_r16_bytes(S, P) : (size_t)S * P * 4;
-    if (((table_bytes > PAT_CACHED_TABLE_BYTES && P >= PAT_WIN_MIN_P) || pat_env_force_win()) &&
+    if ((pat_win_preferred(P, F, table_bytes) || pat_env_force_win()) &&
         pat_win_eligible(table_fmt, sig_fmt, S, P, N, F, sig))
         return pat_launch_backproject_win(table, table_fmt, sig, sig_fmt, sig_is_filtered, frame_scale, w, S, P, N, F,
                                           t0, dt, img, st);

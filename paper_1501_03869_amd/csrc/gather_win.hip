@@ -121,23 +121,28 @@ struct TabStage {
     }
 };
 
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int PPL, int D, int LW>
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int PPL, int D, int LW, int FPW>
 __global__ void __launch_bounds__(64 * WN_MAXW)
     k_bp_win(const uint32_t *__restrict__ tab, const void *__restrict__ sig, const float *__restrict__ scale,
              const float *__restrict__ w, int S, int P, int N, int F, int spw, Delay dec, float t0dt,
              float *__restrict__ img) {
     static_assert(PPL % 4 == 0 && D % LW == 0 && D >= 2 * LW, "pipeline shape");
     constexpr int PIX = 64 * PPL;
-    extern __shared__ float wl[];  // [waves][PIX]: a wave's window, then its partial sums
+    // [waves][FPW][PIX]: a wave's window of each of its frames, then its
+    // partial sums
+    extern __shared__ float wl[];
     constexpr bool kF32T = std::is_base_of<DelayF32, Delay>::value;
     constexpr bool F16 = SFMT == PAT_SIG_F16;
     constexpr uint32_t esz = F16 ? 2 : 4;
-    // launch slot -> (group, frame), frames fastest: an XCD runs the frames
-    // of a group together, so their table rows are read from HBM about once
+    // launch slot -> (group, block of FPW frames), frame blocks fastest: an
+    // XCD runs the frames of a group together, so their table rows are read
+    // from HBM about once; a wave decodes each table entry once for its FPW
+    // frames
     const int groups = (P + PIX - 1) / PIX;
-    const int gf = xcd_tile(blockIdx.x, groups * F);
+    const int FB = (F + FPW - 1) / FPW;
+    const int gf = xcd_tile(blockIdx.x, groups * FB);
     if (gf < 0) return;
-    const int g = gf / F, f = gf - g * F;
+    const int g = gf / FB, fb = gf - g * FB;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
@@ -145,11 +150,18 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
     const int c0 = pb + PPL * lane;  // this lane's first column
     const int s_begin = wv * spw;
     const int ns = min(S, s_begin + spw) - s_begin;
-    const char *sigf = static_cast<const char *>(sig) + (size_t)f * S * N * esz;
-    float *wwin = wl + wv * PIX;
-    float acc[PPL];
+    // frame fb * FPW + q of the block (q < FPW); frames past F repeat the
+    // last one and are not stored
+    const char *sigf[FPW];
+    float *wwin[FPW];
+    float acc2[FPW][PPL];
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) acc[k] = 0.0f;
+    for (int q = 0; q < FPW; ++q) {
+        sigf[q] = static_cast<const char *>(sig) + (size_t)min(fb * FPW + q, F - 1) * S * N * esz;
+        wwin[q] = wl + (wv * FPW + q) * PIX;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) acc2[q][k] = 0.0f;
+    }
 
     // LAST: the group that ends past P, whose lanes load each column on its
     // own (columns past P read column P-1 and are not stored)
@@ -243,9 +255,9 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
             pr.r0 = r0;
             pr.ok = (__builtin_amdgcn_ballot_w64(kmin < lo) | __builtin_amdgcn_ballot_w64(kmax >= hi)) == 0;
         };
-        auto wload = [&](int i, int r0) -> u32x2 {
+        auto wload = [&](int i, int r0, int q) -> u32x2 {
             const int s = s_begin + min(i, ns - 1);
-            const __amdgpu_buffer_rsrc_t r = wrsrc(sigf + (size_t)s * N * esz, (uint32_t)N * esz);
+            const __amdgpu_buffer_rsrc_t r = wrsrc(sigf[q] + (size_t)s * N * esz, (uint32_t)N * esz);
             const uint32_t off = (uint32_t)(r0 + 2 * lane) * esz;
             if constexpr (F16) {
                 u32x2 v;
@@ -259,7 +271,7 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
         // b[r0 + 2l], b[r0 + 2l + 1] into the lane's two window slots (raw
         // input: valid in slots 1 .. 126, lanes 0 and 63 lack a neighbour)
         const float t0h = 0.5f * t0dt;
-        auto wstore = [&](const u32x2 &v, int r0) {
+        auto wstore = [&](const u32x2 &v, int r0, int q) {
             float p0, p1;
             if constexpr (F16) {
                 p0 = wh2f(v[0] & 0xFFFFu);
@@ -276,14 +288,15 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
                 b0 = fmaf(-k0, p1 - pm, p0);
                 b1 = fmaf(-(k0 + 0.5f), pn - p0, p1);
             }
-            reinterpret_cast<float2 *>(wwin)[lane] = make_float2(b0, b1);
+            reinterpret_cast<float2 *>(wwin[q])[lane] = make_float2(b0, b1);
         };
-        auto gather = [&](const Prep &pr, int i) {
+        auto gather = [&](const Prep &pr, int i, int fq) {
             const int s = s_begin + i;
             float ws = 1.0f;
             if constexpr (HAS_W) ws = w[s];
             const int r0 = pr.r0;
-            const float *wb = wwin - r0;  // wb[n]: b[n] for n in the window
+            const float *wb = wwin[fq] - r0;  // wb[n]: b[n] for n in the window
+            float (&acc)[PPL] = acc2[fq];
             if (pr.ok) {
                 // every delay in the window: no tests
 #pragma unroll
@@ -341,7 +354,7 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
             if (anymiss == 0) return;
             // delays outside the window (or not contributing): taps from
             // global memory, the filter one-sided at both ends of the record
-            const __amdgpu_buffer_rsrc_t r = wrsrc(sigf + (size_t)s * N * esz, (uint32_t)N * esz);
+            const __amdgpu_buffer_rsrc_t r = wrsrc(sigf[fq] + (size_t)s * N * esz, (uint32_t)N * esz);
             auto tap = [&](int m) -> float {
                 if constexpr (F16) return wh2f(__builtin_amdgcn_raw_buffer_load_b16(r, (uint32_t)m * 2u, 0, 0));
                 else return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (uint32_t)m * 4u, 0, 0));
@@ -381,7 +394,7 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
         // table loads of sensor i+D.  Loads past the wave's sensors re-read
         // its last records.
         TS T[D];
-        u32x2 Wr[LW];
+        u32x2 Wr[LW][FPW];
         Prep X[LW];
         // prologue in the loop's issue order (window j, then the table of
         // sensor D - LW + j), so that the loop's first waits are its steady ones
@@ -391,7 +404,8 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
 #pragma unroll
         for (int j = 0; j < LW; ++j) {
             prep(T[j], X[j]);
-            Wr[j] = wload(j, X[j].r0);
+#pragma unroll
+            for (int q = 0; q < FPW; ++q) Wr[j][q] = wload(j, X[j].r0, q);
             __builtin_amdgcn_sched_barrier(0);
             tload(D - LW + j, T[D - LW + j]);
             __builtin_amdgcn_sched_barrier(0);
@@ -403,11 +417,16 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
 #pragma unroll
             for (int k = 0; k < D; ++k) {
                 const int i = base + k;
-                wstore(Wr[k % LW], X[k % LW].r0);
+#pragma unroll
+                for (int q = 0; q < FPW; ++q) wstore(Wr[k % LW][q], X[k % LW].r0, q);
                 Prep nx;
                 prep(T[(k + LW) % D], nx);
-                Wr[k % LW] = wload(i + LW, nx.r0);
-                if (i < ns) gather(X[k % LW], i);
+#pragma unroll
+                for (int q = 0; q < FPW; ++q) Wr[k % LW][q] = wload(i + LW, nx.r0, q);
+                if (i < ns) {
+#pragma unroll
+                    for (int q = 0; q < FPW; ++q) gather(X[k % LW], i, q);
+                }
                 X[k % LW] = nx;
                 tload(i + D, T[k]);
             }
@@ -418,24 +437,38 @@ __global__ void __launch_bounds__(64 * WN_MAXW)
         else body(std::false_type{});
     }
 
-    const float sc = (F16 && scale) ? scale[f] : 1.0f;  // filter and interpolation are linear
-    float *out = img + (size_t)f * P;
-    if (nw == 1) {
+    // partial sums of the wave's frames in their own LDS slices (its windows
+    // are no longer read), then wave 0 adds the waves' sums in wave order
 #pragma unroll
-        for (int k = 0; k < PPL; ++k)
-            if (c0 + k < P) out[c0 + k] = acc[k] * sc;
-        return;
+    for (int q = 0; q < FPW; ++q) {
+        const int f = fb * FPW + q;
+        const float sc = (F16 && scale) ? scale[min(f, F - 1)] : 1.0f;  // filter and interpolation are linear
+        if (nw == 1) {
+            if (f < F) {
+                float *out = img + (size_t)f * P;
+#pragma unroll
+                for (int k = 0; k < PPL; ++k)
+                    if (c0 + k < P) out[c0 + k] = acc2[q][k] * sc;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) wwin[q][PPL * lane + k] = acc2[q][k] * sc;
+        }
     }
-    // partial sums in the wave's own slice (its window is no longer read)
-#pragma unroll
-    for (int k = 0; k < PPL; ++k) wwin[PPL * lane + k] = acc[k] * sc;
+    if (nw == 1) return;
     __syncthreads();
     if (wv == 0) {
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-            float s = 0.0f;
-            for (int m = 0; m < nw; ++m) s += wl[m * PIX + PPL * lane + k];
-            if (c0 + k < P) out[c0 + k] = s;
+        for (int q = 0; q < FPW; ++q) {
+            const int f = fb * FPW + q;
+            if (f >= F) continue;
+            float *out = img + (size_t)f * P;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) {
+                float sum = 0.0f;
+                for (int m = 0; m < nw; ++m) sum += wl[(m * FPW + q) * PIX + PPL * lane + k];
+                if (c0 + k < P) out[c0 + k] = sum;
+            }
         }
     }
 }
@@ -479,15 +512,16 @@ WinShape win_shape(int S, int P, int F, int cus, long per_cu, BlocksPerCu blocks
     return s;
 }
 
-template <class Delay, int SFMT, bool FILTERED, bool HAS_W>
-int launch_win_one(int S, int P, int F, const uint32_t *tab, const void *sig, const float *scale, const float *w,
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W, int FPW>
+int launch_win_fpw(int S, int P, int F, const uint32_t *tab, const void *sig, const float *scale, const float *w,
                    int N, Delay dec, float t0dt, float *img, hipStream_t st) {
-    auto kern = k_bp_win<Delay, SFMT, FILTERED, HAS_W, WN_PPL, WN_D, WN_LW>;
+    auto kern = k_bp_win<Delay, SFMT, FILTERED, HAS_W, WN_PPL, WN_D, WN_LW, FPW>;
     // occupancy per block size, computed once per kernel and device
     static std::mutex mu;
     static int cache_dev = -1, cache_cus = 0, cache_bpc[WN_MAXW + 1];
     int dev = 0;
     PAT_HIP(hipGetDevice(&dev));
+    const int FB = (F + FPW - 1) / FPW;
     WinShape sh;
     {
         std::lock_guard<std::mutex> lk(mu);
@@ -495,29 +529,55 @@ int launch_win_one(int S, int P, int F, const uint32_t *tab, const void *sig, co
             PAT_HIP(hipDeviceGetAttribute(&cache_cus, hipDeviceAttributeMultiprocessorCount, dev));
             for (int W = 1; W <= WN_MAXW; ++W)
                 PAT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&cache_bpc[W], kern, 64 * W,
-                                                                     (size_t)W * WN_PIX * sizeof(float)));
+                                                                     (size_t)W * FPW * WN_PIX * sizeof(float)));
             cache_dev = dev;
         }
-        sh = win_shape(S, P, F, cache_cus, WN_WAVES_PER_CU, [&](int W) { return cache_bpc[W]; });
+        sh = win_shape(S, P, FB, cache_cus, WN_WAVES_PER_CU, [&](int W) { return cache_bpc[W]; });
     }
-    const dim3 grid(xcd_slots(sh.groups * F));
-    kern<<<grid, dim3(64 * sh.waves), (size_t)sh.waves * WN_PIX * sizeof(float), st>>>(tab, sig, scale, w, S, P, N, F,
-                                                                                    sh.spw, dec, t0dt, img);
+    const dim3 grid(xcd_slots(sh.groups * FB));
+    kern<<<grid, dim3(64 * sh.waves), (size_t)sh.waves * FPW * WN_PIX * sizeof(float), st>>>(
+        tab, sig, scale, w, S, P, N, F, sh.spw, dec, t0dt, img);
     PAT_HIP(hipGetLastError());
     return PAT_OK;
 }
 
+// Frames per wave: a table larger than the 256 MB Infinity Cache streams
+// from HBM for every pass over it, so a wave that reads and decodes it once
+// for 4 frames (2 for 2-3 frames) gains most: 16 frames on the 1024^2
+// workload take 0.22 ms per frame against 0.36 with one frame per wave.  A
+// table that the cache partly holds gains less than the extra registers
+// cost (16 or 64 frames on the 512^2 serving map: 1 frame per wave is
+// within 5 % of the best), so it keeps one.
+template <class Delay, int SFMT, bool FILTERED, bool HAS_W>
+int launch_win_one(int S, int P, int F, const uint32_t *tab, const void *sig, const float *scale, const float *w,
+                   int N, Delay dec, float t0dt, float *img, hipStream_t st, size_t table_bytes) {
+    if (F >= 2 && table_bytes > PAT_INFINITY_CACHE_BYTES) {
+        if (F >= 4)
+            return launch_win_fpw<Delay, SFMT, FILTERED, HAS_W, 4>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
+        return launch_win_fpw<Delay, SFMT, FILTERED, HAS_W, 2>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
+    }
+    return launch_win_fpw<Delay, SFMT, FILTERED, HAS_W, 1>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
+}
+
 template <class Delay, int SFMT>
 int launch_win(bool filtered, int S, int P, int F, const uint32_t *tab, const void *sig, const float *scale,
-               const float *w, int N, Delay dec, float t0dt, float *img, hipStream_t st) {
+               const float *w, int N, Delay dec, float t0dt, float *img, hipStream_t st, size_t tb) {
     if (w)
-        return filtered ? launch_win_one<Delay, SFMT, true, true>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st)
-                        : launch_win_one<Delay, SFMT, false, true>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
-    return filtered ? launch_win_one<Delay, SFMT, true, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st)
-                    : launch_win_one<Delay, SFMT, false, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st);
+        return filtered ? launch_win_one<Delay, SFMT, true, true>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st, tb)
+                        : launch_win_one<Delay, SFMT, false, true>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st, tb);
+    return filtered ? launch_win_one<Delay, SFMT, true, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st, tb)
+                    : launch_win_one<Delay, SFMT, false, false>(S, P, F, tab, sig, scale, w, N, dec, t0dt, img, st, tb);
 }
 
 }  // namespace
+
+bool pat_win_preferred(int P, int F, size_t table_bytes) {
+    if (table_bytes <= PAT_CACHED_TABLE_BYTES) return false;
+    if (P >= PAT_WIN_MIN_P) return true;
+    // several frames on the 512^2 serving map (175 MB table, 335 groups):
+    // 64 frames 24 against 31 us per frame for the batched kernel
+    return F >= 2 && (long long)((P + WN_PIX - 1) / WN_PIX) * F >= 8LL * 256;
+}
 
 bool pat_win_eligible(int table_fmt, int sig_fmt, int S, int P, int N, int F, const void *sig) {
     if (table_fmt != PAT_TABLE_F32 && table_fmt != PAT_TABLE_Q16 && table_fmt != PAT_TABLE_R16) return false;
@@ -534,6 +594,7 @@ int pat_launch_backproject_win(const void *table, int table_fmt, const void *sig
     const float t0dt = (float)(t0 / dt);
     const bool filt = sig_is_filtered != 0;
     const uint32_t *tab = static_cast<const uint32_t *>(table);
+    const size_t tb = table_fmt == PAT_TABLE_R16 ? pat_r16_bytes(S, P) : (size_t)S * P * 4;
     if (table_fmt == PAT_TABLE_F32) {
         DelayF32 d;
         const double inv = 1.0 / dt;
@@ -542,17 +603,17 @@ int pat_launch_backproject_win(const void *table, int table_fmt, const void *sig
         d.off = (float)(-t0 / dt);
         d.umax = (float)(N - 1);
         return sig_fmt == PAT_SIG_F32
-                   ? launch_win<DelayF32, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
-                   : launch_win<DelayF32, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
+                   ? launch_win<DelayF32, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st, tb)
+                   : launch_win<DelayF32, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st, tb);
     }
     if (table_fmt == PAT_TABLE_R16) {
         DelayR16 d;
         return sig_fmt == PAT_SIG_F32
-                   ? launch_win<DelayR16, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
-                   : launch_win<DelayR16, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
+                   ? launch_win<DelayR16, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st, tb)
+                   : launch_win<DelayR16, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st, tb);
     }
     DelayQ16 d;
     return sig_fmt == PAT_SIG_F32
-               ? launch_win<DelayQ16, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st)
-               : launch_win<DelayQ16, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st);
+               ? launch_win<DelayQ16, PAT_SIG_F32>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st, tb)
+               : launch_win<DelayQ16, PAT_SIG_F16>(filt, S, P, F, tab, sig, frame_scale, w, N, d, t0dt, img, st, tb);
 }

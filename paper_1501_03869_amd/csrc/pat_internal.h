@@ -103,6 +103,8 @@ size_t pat_gather_counter_bytes(int P, int F);
 // Tables up to this size are taken to stay cached between frames (half of
 // the 256 MB Infinity Cache, leaving the rest to the frames streaming past).
 constexpr size_t PAT_CACHED_TABLE_BYTES = 128ull << 20;
+// The Infinity Cache: a larger table streams from HBM on every pass.
+constexpr size_t PAT_INFINITY_CACHE_BYTES = 256ull << 20;
 // one-pixel-per-lane gather (no LDS windows, no partial sums in global memory)
 bool pat_px_eligible(int sig_fmt, int S, int P, int N, int F, const void *sig);
 // the same with straight-ray delays |x - s| / c computed per gather (d_sxy: float32 metres)
@@ -116,13 +118,17 @@ int pat_launch_backproject_px(const void *table, int table_fmt, const void *sig,
                               double dt, float *img, hipStream_t st);
 // wave-window gather: one wave per run of table columns, the signal read
 // from a per-wave LDS window (float32, 16.16 or 16-bit tile-relative tables,
-// N >= 128).  Chosen for
-// tables that stream from HBM with at least PAT_WIN_MIN_P columns (two 256-
+// N >= 128).  Single frames take it from PAT_WIN_MIN_P columns (two 256-
 // column groups per compute unit): on the 1024^2 workload's first 128K
 // columns it took 0.11 ms against 0.13 for the split-sensor kernel, on its
 // first 64K 0.059 against 0.054.
 constexpr int PAT_WIN_MIN_P = 131072;
 bool pat_win_eligible(int table_fmt, int sig_fmt, int S, int P, int N, int F, const void *sig);
+// Whether the wave-window kernel is the one to take for a table of this
+// size: above PAT_CACHED_TABLE_BYTES, with PAT_WIN_MIN_P columns, or, for
+// several frames, at least 8 waves per compute unit of (256-column group,
+// frame) pairs.
+bool pat_win_preferred(int P, int F, size_t table_bytes);
 int pat_launch_backproject_win(const void *table, int table_fmt, const void *sig, int sig_fmt, int sig_is_filtered,
                                const float *frame_scale, const float *w, int S, int P, int N, int F, double t0,
                                double dt, float *img, hipStream_t st);

@@ -192,3 +192,21 @@ def test_small_shapes(ctx, orc, force_win, S, P, N, F, tfmt, sig):
     err = rel_l2(got, ref)
     print(f"[win] small shape S={S} P={P} N={N} F={F} {tfmt} {sig}: rel L2 {err:.3e}", flush=True)
     assert err <= IMG_TOL
+
+
+@pytest.mark.parametrize("F,sig,tfmt", [(3, "f32", "f32"), (5, "f16", "q16"), (4, "f32", "r16")])
+def test_frames_sharing_table_reads(ctx, orc, F, sig, tfmt):
+    # a table larger than the 256 MB Infinity Cache (520 x 140000 float32
+    # entries, 291 MB): each wave decodes its delays once for 2 (F = 3) or 4
+    # frames, the last block holding frames past F that are not stored
+    S, P, N, dt = 520, 140000, 512, 4e-8
+    rng = np.random.default_rng(300 + F)
+    base = rng.uniform(2.0, N - 150.0, (S, 1))
+    u = base + np.tile(np.linspace(0.0, 100.0, 256), P // 256 + 1)[:P][None, :] + rng.uniform(0.0, 8.0, (S, P))
+    T = (u * dt).astype(np.float32)
+    assert T.nbytes > (256 << 20)
+    p = inputs.random_signals(301 + F, S, N, F)
+    got, ref = _run(ctx, orc, T, p, dt, 0.0, tfmt, sig, False, None)
+    err = rel_l2(got, ref)
+    print(f"[win] frames sharing table reads F={F} {tfmt} {sig}: rel L2 {err:.3e}", flush=True)
+    assert err <= IMG_TOL
