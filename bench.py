@@ -56,11 +56,11 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_SOURCES = ("paper_1501_03869_amd/csrc/gather_px.hip", "paper_1501_03869_amd/csrc/gather_win.hip",
                    "paper_1501_03869_amd/csrc/gather_common.h")
 TRAFFIC_SHA = "8c446ee2bd9ad5d338dc358c7e9cf6af010f9d7089517fe2ee51b7a2be52e815:" \
-              "76b8f28b8524b8209f9f38a4f8aefe9f1a09f75da2d9ed60d8aecff5d9ba5feb:" \
+              "c13158e00f16cba69f8a19eda1d010ce6c8b0114344cf69ee605494d0366cedc:" \
               "04563295b4cefa9191f8ce39ecab8507bf4861fdb66ec84263b3126532f5fa18"
-FETCH_FACTOR = 250000.0 / 125012.33
+FETCH_FACTOR = 250000.0 / 125012.32
 WRITE_FACTOR = 1.0
-TRAFFIC_KIB = {"paper": (24265.93, 83.34), "large": (1725823.76, 3243.05),
+TRAFFIC_KIB = {"paper": (24265.93, 83.34), "large": (1725405.76, 3242.61),
                "paper_rotated": (24236.94, 83.36), "head3": (23670.92, 174.69),
                "head3_rotated": (23666.41, 174.69)}  # (FETCH_SIZE, WRITE_SIZE) per dispatch
 

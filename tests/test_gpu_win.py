@@ -1,9 +1,10 @@
 """The wave-window gather (k_bp_win) against the FP64 oracle.
 
 pat_backproject takes this kernel for float32, 16.16 and 16-bit tile-relative
-tables (not the interleaved form) that stream from HBM with at least 131072
-columns (the 1024^2 precision study runs it at full size).  Here the PAT_GATHER_FORCE=win hook sends smaller shapes to
-it, so that the oracle checks every pixel:
+tables (not the interleaved form) above 128 MiB, for a single frame with at
+least 131072 columns or for several frames that fill the GPU (the 1024^2
+precision study runs it at full size).  Here the PAT_GATHER_FORCE=win hook
+sends smaller shapes to it, so that the oracle checks every pixel:
   - a smooth table (the small geometry's fast-marching delays, tile-ordered
     ROI), where nearly every gather reads the wave's LDS window;
   - random delays with some outside the record, where nearly every gather
