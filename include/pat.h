@@ -127,13 +127,35 @@ size_t pat_backproject_scratch_bytes(int S, int P, int F);
  * Source seeding: nodes within 2h of the sensor are fixed at the straight-ray
  * time |x_k - s| / c(n*), n* the node nearest the sensor; the rest converge
  * to the upwind fixed point by tile-parallel relaxation in integer fixed
- * point.  Synchronises `stream`.  PAT_ENOCONV if the relaxation exceeds its
+ * point, with an update exact in integers (the first-order root rounded to
+ * the nearest unit of lsb_seconds, each node's slowness h/c in whole units),
+ * so the same inputs give the same table bit for bit.  Synchronises `stream`.  PAT_ENOCONV if the relaxation exceeds its
  * round cap, 100 (tiles_x + tiles_y) + 1000 rounds of 32 x 32 tiles (never
  * expected; PAT_EIK_ROUND_CAP lowers it); the context stays usable.
  */
 int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, int ny, double h,
                        const double *h_sensor_xy, int S, const int32_t *d_pix, int P,
                        float *d_table, void *stream);
+
+/*
+ * The local update of pat_eikonal_tables and pat_eikonal_tables_3d alone,
+ * for checking it against its definition (Section II-B, first-order upwind
+ * discretisation).  For entry i, with neighbour minima n_k = d_nbr[i][k]
+ * (k < dims; 0xFFFFFFFF = not reached; d_nbr[i][2] unused for dims = 2) and
+ * slowness F = d_F[i] in the same units, d_out[i] is the largest T with
+ *   sum_k max(2 (T - n_k) - 1, 0)^2 <= 4 F^2,
+ * the first-order root rounded to the nearest unit (halves up), held below
+ * 0xFFFFFFFF; 0xFFFFFFFF when every neighbour is unreached.  F must be at
+ * most 2^23 (entries above give 0).
+ *
+ *   d_nbr  uint32 [n][3] device, caller-owned.   d_F  uint32 [n] device.
+ *   d_out  uint32 [n] device.   dims  2 or 3.
+ *
+ * Asynchronous on `stream`.  PAT_EINVAL for n < 0, other dims or null
+ * buffers with n > 0.
+ */
+int pat_eikonal_update_eval(const uint32_t *d_nbr, const uint32_t *d_F, int n, int dims, uint32_t *d_out,
+                            void *stream);
 
 /*
  * Delay tables with the paper's second-order scheme (Section II-B): the fast
@@ -189,7 +211,8 @@ int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx, int ny, in
 typedef struct pat_eikonal_stats {
     int64_t rounds;          /* relaxation rounds (kernel launches), all chunks */
     int64_t tile_visits;     /* tiles (3-D: bricks) processed over all rounds */
-    int64_t guard_hits;      /* FP64 fallbacks of the quadratic solve */
+    int64_t guard_hits;      /* always 0: the update is exact in integers and has
+                                no floating-point fallback */
     int64_t sweeps;          /* in-tile relaxation sweeps over all tile visits; each
                                 sweep applies the local update to the tile's
                                 32 x 32 nodes (3-D: the brick's 8 x 8 x 8) once */

@@ -14,22 +14,23 @@
 //    (workgroup OR-reduction), then writes the changed nodes back and
 //    activates the neighbour tiles whose shared edge changed.  Rounds repeat
 //    until no tile is active.  Values only decrease, and a sweep that changes
-//    nothing leaves every node at its update.  The update rounds to whole
-//    fixed-point units, so it is monotone only to within a unit: the
-//    relaxation order (the workgroup schedule) can move a node by a unit or
-//    two, about one float32 ulp in a few entries per million.
-//  * The local update is computed in FP32 from the exact integer difference
-//    d = |a - b| of the two upwind neighbours:
-//    T = min(a, b) + F when d >= F, else min(a, b) + (d + sqrt(2 F^2 - d^2)) / 2,
-//    F = h / (c lsb).  The discriminant is then at least F^2, so the FP64
-//    fallback (taken below F^2 / 1024) is kept as a guard and counted.
+//    nothing leaves every node at its update.
+//  * The update is exact in integers (eik_update.h): with the node's
+//    F = round(h / (c lsb)) whole units it is the first-order root
+//    T = min(a, b) + F when |a - b| >= F, else
+//    min(a, b) + (|a - b| + sqrt(2 F^2 - (a - b)^2)) / 2, rounded to the
+//    nearest unit.  It is monotone in both neighbours, so the relaxation ends
+//    at the same fixed point whatever the workgroup schedule, and the tables
+//    are the same bit for bit from run to run.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
+#include "eik_update.h"
 #include "pat_internal.h"
 
 namespace {
@@ -45,29 +46,6 @@ constexpr int LOCAL_ITER_CAP = 6 * TS;  // a tile that has not settled re-queues
 struct EikGrid {
     int nx, ny, tiles_x, tiles_y, tiles_per_map;
 };
-
-__device__ __forceinline__ uint32_t godunov_q(uint32_t a, uint32_t b, float F, unsigned int *guard) {
-    const uint32_t m = min(a, b);
-    if (m == TQ_INF) return TQ_INF;
-    const uint32_t M = max(a, b);
-    float inc = F;
-    if (M != TQ_INF) {
-        const uint32_t di = M - m;
-        const float d = (float)di;
-        if (d < F) {
-            const float disc = fmaf(-d, d, 2.0f * F * F);
-            if (disc < F * F * (1.0f / 1024.0f)) {
-                const double dd = (double)di, FF = (double)F;
-                inc = (float)(0.5 * (dd + sqrt(2.0 * FF * FF - dd * dd)));
-                atomicAdd(guard, 1u);
-            } else {
-                inc = 0.5f * (d + sqrtf(disc));
-            }
-        }
-    }
-    const uint64_t r = (uint64_t)m + (uint32_t)(inc + 0.5f);
-    return r >= TQ_INF ? TQ_INF - 1 : (uint32_t)r;
-}
 
 __device__ __forceinline__ bool is_frozen(int gx, int gy, const int *seed_ij, const uint32_t *seed_val, int m,
                                           uint32_t &val) {
@@ -96,7 +74,7 @@ __device__ __forceinline__ void activate(uint32_t tile, uint32_t *flags_next, ui
     }
 }
 
-__global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ Tq, const float *__restrict__ Fmap,
+__global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ Tq, const uint32_t *__restrict__ Fmap,
                                                          EikGrid g, const int *__restrict__ seed_ij,
                                                          const uint32_t *__restrict__ seed_val,
                                                          const uint32_t *__restrict__ list_cur,
@@ -136,7 +114,7 @@ __global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ 
     // 4*strip+3 (layout R).  Sweeps alternate C down, R right, C up, R left:
     // information crosses a thread's four nodes within one sweep, along y in
     // layout C and along x in layout R, instead of along y only.
-    __shared__ float Fl[TS * TS];
+    __shared__ uint32_t Fl[TS * TS];
     const int lx = tid % TS;
     const int strip = tid / TS;
     const int gx = gx0 + lx;
@@ -147,7 +125,7 @@ __global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ 
         const int gy = gy0 + ly;
         const bool in = gx < g.nx && gy < g.ny;
         uint32_t v = TQ_INF;
-        float f = 0.0f;
+        uint32_t f = 0u;
         if (in) {
             v = map[(long)gy * g.nx + gx];
             f = Fmap[(long)gy * g.nx + gx];
@@ -163,38 +141,48 @@ __global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ 
         if (rx < g.nx && ry < g.ny && !is_frozen(rx, ry, seed_ij, seed_val, m, sv)) live_r |= 1u << q;
     }
     __syncthreads();
-    float Fc[ROWS_PER_THREAD], Fr[ROWS_PER_THREAD];
+    uint32_t Fc[ROWS_PER_THREAD], Fr[ROWS_PER_THREAD];
+    float F2c[ROWS_PER_THREAD], F2r[ROWS_PER_THREAD];  // 2 F^2 as floats
     for (int q = 0; q < ROWS_PER_THREAD; ++q) {
         Fc[q] = Fl[(strip * ROWS_PER_THREAD + q) * TS + lx];
         Fr[q] = Fl[lx * TS + strip * ROWS_PER_THREAD + q];
+        F2c[q] = pat_eik::eik_f2(Fc[q]);
+        F2r[q] = pat_eik::eik_f2(Fr[q]);
     }
 
-    unsigned int *guard = counters + 1;
-    int it = 0;
-    // one node of a sweep (q static, so the per-node registers stay registers)
-    auto relax = [&](bool rows, int q, int &any) {
-        if (!((rows ? live_r : live_c) & (1u << q))) return;
+    // one node of a sweep (layout and q static, so the per-node registers
+    // stay registers and nothing selects between the layouts per node)
+    auto relax = [&](auto rows_c, int q, int &any) {
+        constexpr bool ROWS = decltype(rows_c)::value;
+        if (!((ROWS ? live_r : live_c) & (1u << q))) return;
         const int n = strip * ROWS_PER_THREAD + q;
-        const int c = rows ? (lx + 1) * HS + n + 1 : (n + 1) * HS + lx + 1;
+        const int c = ROWS ? (lx + 1) * HS + n + 1 : (n + 1) * HS + lx + 1;
         const uint32_t a = min(T[c - 1], T[c + 1]);
         const uint32_t b = min(T[c - HS], T[c + HS]);
-        const uint32_t nv = godunov_q(a, b, rows ? Fr[q] : Fc[q], guard);
+        const uint32_t nv = pat_eik::godunov2_int(a, b, ROWS ? Fr[q] : Fc[q], ROWS ? F2r[q] : F2c[q]);
         if (nv < T[c]) {
             T[c] = nv;
             any = 1;
         }
     };
-    for (; it < LOCAL_ITER_CAP; ++it) {
+    // one sweep; false when it changed no node of the tile
+    auto sweep = [&](auto rows_c, auto rev_c) -> bool {
         int any = 0;
-        const bool rows = it & 1;  // layout R on odd sweeps
-        if ((it >> 1) & 1) {       // up / left on every other sweep of a layout
 #pragma unroll
-            for (int q = ROWS_PER_THREAD - 1; q >= 0; --q) relax(rows, q, any);
-        } else {
-#pragma unroll
-            for (int q = 0; q < ROWS_PER_THREAD; ++q) relax(rows, q, any);
-        }
-        if (!__syncthreads_or(any)) break;
+        for (int k = 0; k < ROWS_PER_THREAD; ++k) relax(rows_c, decltype(rev_c)::value ? ROWS_PER_THREAD - 1 - k : k, any);
+        return __syncthreads_or(any) != 0;
+    };
+    // sweeps cycle through C down, R right, C up, R left; it ends as the
+    // index of the sweep that changed nothing, or the cap
+    static_assert(LOCAL_ITER_CAP % 4 == 0, "whole sweep cycles");
+    using F_ = std::false_type;
+    using T_ = std::true_type;
+    int it = 0;
+    for (; it < LOCAL_ITER_CAP; it += 4) {
+        if (!sweep(F_{}, F_{})) break;
+        if (!sweep(T_{}, F_{})) { it += 1; break; }
+        if (!sweep(F_{}, T_{})) { it += 2; break; }
+        if (!sweep(T_{}, T_{})) { it += 3; break; }
     }
 
     unsigned sides = 0;
@@ -236,7 +224,36 @@ __global__ void __launch_bounds__(256) k_eik_extract(const uint32_t *__restrict_
     table[i] = v == TQ_INF ? INFINITY : (float)((double)v * lsb);
 }
 
+// The local update alone, for checking it against its definition: out[i] =
+// the 2-D or 3-D update of neighbour minima nbr[i][0..dims) with slowness
+// F[i] units (F above 2^23 gives 0).
+__global__ void __launch_bounds__(256) k_eik_update_eval(const uint32_t *__restrict__ nbr,
+                                                         const uint32_t *__restrict__ F, int n, int dims,
+                                                         uint32_t *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t f = F[i];
+    if (f > (1u << 23)) {
+        out[i] = 0u;
+        return;
+    }
+    const uint32_t a = nbr[3 * i], b = nbr[3 * i + 1], c = nbr[3 * i + 2];
+    out[i] = dims == 2 ? pat_eik::godunov2_int(a, b, f, pat_eik::eik_f2(f))
+                       : pat_eik::godunov3_int(a, b, c, f, pat_eik::eik_f2(f), pat_eik::eik_f3(f));
+}
+
 }  // namespace
+
+extern "C" int pat_eikonal_update_eval(const uint32_t *d_nbr, const uint32_t *d_F, int n, int dims,
+                                       uint32_t *d_out, void *stream) {
+    if (n < 0) return pat_fail(PAT_EINVAL, "negative count");
+    if (dims != 2 && dims != 3) return pat_fail(PAT_EINVAL, "dims must be 2 or 3 (got %d)", dims);
+    if (n == 0) return PAT_OK;
+    if (!d_nbr || !d_F || !d_out) return pat_fail(PAT_EINVAL, "null buffer");
+    k_eik_update_eval<<<dim3((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(d_nbr, d_F, n, dims, d_out);
+    PAT_HIP(hipGetLastError());
+    return PAT_OK;
+}
 
 extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, int ny, double h,
                                   const double *h_sensor_xy, int S, const int32_t *d_pix, int P, float *d_table,
@@ -280,15 +297,16 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
     }
     if (S == 0 || P == 0) return PAT_OK;
 
-    // fixed-point unit: the Dijkstra bound fits, and F = h/(c lsb) stays below 2^23
+    // fixed-point unit: the Dijkstra bound fits, and F = h/(c lsb) is at most 2^23
     const double tbound = 1.01 * (double)(nx + ny + 2) * h / cmin;
     const double lsb_range = tbound / 4294967294.0;
     const double lsb_prec = h / cmin / 8388608.0;
     const double lsb = std::exp2(std::ceil(std::log2(std::max(lsb_range, lsb_prec))));
     ctx->last_eik.lsb_seconds = lsb;
 
-    std::vector<float> Fh((size_t)n);
-    for (long k = 0; k < n; ++k) Fh[(size_t)k] = (float)(h / ((double)c[(size_t)k] * lsb));
+    // F in whole units (at most 2^23), the update's integer slowness
+    std::vector<uint32_t> Fh((size_t)n);
+    for (long k = 0; k < n; ++k) Fh[(size_t)k] = (uint32_t)std::llround(h / ((double)c[(size_t)k] * lsb));
 
     EikGrid g;
     g.nx = nx;
@@ -304,23 +322,23 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
     if (max_tiles > 0x7FFFFFFFL) return pat_fail(PAT_EINVAL, "too many tiles");
 
     if ((rc = ctx->eik_tq.grow((size_t)chunk * n * sizeof(uint32_t)))) return rc;
-    if ((rc = ctx->eik_f.grow((size_t)n * sizeof(float)))) return rc;
+    if ((rc = ctx->eik_f.grow((size_t)n * sizeof(uint32_t)))) return rc;
     if ((rc = ctx->eik_flags.grow((size_t)2 * max_tiles * sizeof(uint32_t)))) return rc;
     if ((rc = ctx->eik_lists.grow((size_t)2 * max_tiles * sizeof(uint32_t)))) return rc;
     if ((rc = ctx->eik_seeds.grow((size_t)chunk * (2 * sizeof(int) + SEED_BOX * SEED_BOX * sizeof(uint32_t))))) return rc;
     if ((rc = ctx->eik_count.grow(4 * sizeof(uint32_t)))) return rc;
 
     uint32_t *Tq = static_cast<uint32_t *>(ctx->eik_tq.ptr);
-    float *Fd = static_cast<float *>(ctx->eik_f.ptr);
+    uint32_t *Fd = static_cast<uint32_t *>(ctx->eik_f.ptr);
     uint32_t *flags[2] = { static_cast<uint32_t *>(ctx->eik_flags.ptr),
                            static_cast<uint32_t *>(ctx->eik_flags.ptr) + max_tiles };
     uint32_t *lists[2] = { static_cast<uint32_t *>(ctx->eik_lists.ptr),
                            static_cast<uint32_t *>(ctx->eik_lists.ptr) + max_tiles };
     int *seed_ij = static_cast<int *>(ctx->eik_seeds.ptr);
     uint32_t *seed_val = reinterpret_cast<uint32_t *>(seed_ij + 2 * chunk);
-    uint32_t *counters = static_cast<uint32_t *>(ctx->eik_count.ptr);  // [0] next count, [1] guard hits, [2..3] sweeps
+    uint32_t *counters = static_cast<uint32_t *>(ctx->eik_count.ptr);  // [0] next count, [1] unused (0), [2..3] sweeps
 
-    PAT_HIP(hipMemcpyAsync(Fd, Fh.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice, st));
+    PAT_HIP(hipMemcpyAsync(Fd, Fh.data(), (size_t)n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     PAT_HIP(hipMemsetAsync(ctx->eik_flags.ptr, 0, (size_t)2 * max_tiles * sizeof(uint32_t), st));
     PAT_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(uint32_t), st));
 

@@ -5,24 +5,24 @@
 // the method, which the paper anticipates for 3-D reconstruction (Section IV);
 // the delay-and-sum gather is the same for 2-D pixels and 3-D voxels.
 //
-// The scheme follows the 2-D tables: uint32 fixed-point working times, the
-// update computed in FP32 from exact integer differences to the smallest
-// upwind neighbour, values that only decrease, and active-brick lists that
-// repeat until no brick changes.  Bricks are 8x8x8 nodes with a one-node halo
-// in LDS.  The update, with a <= b <= c the upwind minima along the three
-// axes and F = h / (c lsb):
+// The scheme follows the 2-D tables: uint32 fixed-point working times,
+// values that only decrease, and active-brick lists that repeat until no
+// brick changes.  Bricks are 8x8x8 nodes with a one-node halo in LDS.  The
+// update is the integer-exact root of eik_update.h over the upwind minima
+// a <= b <= c along the three axes, F = round(h / (c lsb)):
 //   one-sided   a + F                                      if b - a >= F,
 //   two-sided   a + x, x = (d + sqrt(2F^2 - d^2)) / 2       if x <= c - a,
 //   three-sided a + ((d + e) + sqrt((d+e)^2 - 3(d^2 + e^2 - F^2))) / 3,
-// with d = b - a, e = c - a.  When the three-sided root is taken its
-// discriminant is at least 2F^2 - d^2 >= F^2, so (as in 2-D) the FP64
-// fallback below F^2 / 1024 is a counted guard that does not fire.
+// with d = b - a, e = c - a, rounded to the nearest unit.  It is monotone in
+// every neighbour, so the tables do not depend on the brick schedule.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
+#include "eik_update.h"
 #include "pat_internal.h"
 
 namespace {
@@ -38,38 +38,6 @@ constexpr int LOCAL_ITER_CAP3 = 6 * BS; // a brick that has not settled re-queue
 struct EikGrid3 {
     int nx, ny, nz, bx, by, bz, bricks_per_map;
 };
-
-__device__ __forceinline__ uint32_t godunov3_q(uint32_t a, uint32_t b, uint32_t c, float F, unsigned int *guard) {
-    uint32_t t;
-    if (b < a) { t = a; a = b; b = t; }
-    if (c < b) { t = b; b = c; c = t; }
-    if (b < a) { t = a; a = b; b = t; }
-    if (a == TQ_INF) return TQ_INF;
-    float inc = F;
-    if (b != TQ_INF) {
-        const float d = (float)(b - a);
-        if (d < F) {
-            inc = 0.5f * (d + sqrtf(fmaf(-d, d, 2.0f * F * F)));
-            if (c != TQ_INF) {
-                const uint32_t ei = c - a;
-                const float e = (float)ei;
-                if (inc > e) {
-                    const float sum = d + e;
-                    const float disc = fmaf(sum, sum, -3.0f * (fmaf(d, d, e * e) - F * F));
-                    if (disc < F * F * (1.0f / 1024.0f)) {
-                        const double dd = (double)(b - a), ee = (double)ei, FF = (double)F, ss = dd + ee;
-                        inc = (float)((ss + sqrt(ss * ss - 3.0 * (dd * dd + ee * ee - FF * FF))) / 3.0);
-                        atomicAdd(guard, 1u);
-                    } else {
-                        inc = (sum + sqrtf(disc)) * (1.0f / 3.0f);
-                    }
-                }
-            }
-        }
-    }
-    const uint64_t r = (uint64_t)a + (uint32_t)(inc + 0.5f);
-    return r >= TQ_INF ? TQ_INF - 1 : (uint32_t)r;
-}
 
 __device__ __forceinline__ bool is_frozen3(int gx, int gy, int gz, const int *seed_ijl, const uint32_t *seed_val,
                                            int m, uint32_t &val) {
@@ -104,7 +72,7 @@ __device__ __forceinline__ void activate3(uint32_t brick, uint32_t *flags_next, 
 
 __device__ __forceinline__ int hidx(int x, int y, int z) { return (z * HB + y) * HB + x; }
 
-__global__ void __launch_bounds__(E3_THREADS) k_eik3_brick(uint32_t *__restrict__ Tq, const float *__restrict__ Fmap,
+__global__ void __launch_bounds__(E3_THREADS) k_eik3_brick(uint32_t *__restrict__ Tq, const uint32_t *__restrict__ Fmap,
                                                            EikGrid3 g, const int *__restrict__ seed_ijl,
                                                            const uint32_t *__restrict__ seed_val,
                                                            const uint32_t *__restrict__ list_cur,
@@ -146,7 +114,8 @@ __global__ void __launch_bounds__(E3_THREADS) k_eik3_brick(uint32_t *__restrict_
     // this thread's nodes: column (lx, ly), z nodes 2*pair and 2*pair+1
     const int lx = tid % BS, ly = (tid / BS) % BS, pair = tid / (BS * BS);
     const int gx = gx0 + lx, gy = gy0 + ly;
-    float F[NODES_PER_THREAD];
+    uint32_t F[NODES_PER_THREAD];
+    float F2[NODES_PER_THREAD], F3[NODES_PER_THREAD];  // 2 F^2 and 3 F^2 as floats
     uint32_t own[NODES_PER_THREAD];
     unsigned live = 0;  // bit q: node q is inside the grid and not frozen
     for (int q = 0; q < NODES_PER_THREAD; ++q) {
@@ -154,7 +123,7 @@ __global__ void __launch_bounds__(E3_THREADS) k_eik3_brick(uint32_t *__restrict_
         const int gz = gz0 + lz;
         const bool in = gx < g.nx && gy < g.ny && gz < g.nz;
         uint32_t v = TQ_INF;
-        F[q] = 0.0f;
+        F[q] = 0u;
         if (in) {
             const long k = gz * nxy + (long)gy * g.nx + gx;
             v = map[k];
@@ -164,30 +133,41 @@ __global__ void __launch_bounds__(E3_THREADS) k_eik3_brick(uint32_t *__restrict_
         }
         own[q] = v;
         T[hidx(lx + 1, ly + 1, lz + 1)] = v;
+        F2[q] = pat_eik::eik_f2(F[q]);
+        F3[q] = pat_eik::eik_f3(F[q]);
     }
     __syncthreads();
 
     unsigned changed = 0;
-    unsigned int *guard = counters + 1;
-    int it = 0;
-    for (; it < LOCAL_ITER_CAP3; ++it) {
-        int any = 0;
-        for (int qq = 0; qq < NODES_PER_THREAD; ++qq) {
-            const int q = (it & 1) ? NODES_PER_THREAD - 1 - qq : qq;
-            if (!(live & (1u << q))) continue;
-            const int c = hidx(lx + 1, ly + 1, pair * NODES_PER_THREAD + q + 1);
-            const uint32_t a = min(T[c - 1], T[c + 1]);
-            const uint32_t b = min(T[c - HB], T[c + HB]);
-            const uint32_t cz = min(T[c - HB * HB], T[c + HB * HB]);
-            const uint32_t nv = godunov3_q(a, b, cz, F[q], guard);
-            if (nv < own[q]) {
-                own[q] = nv;
-                T[c] = nv;
-                changed |= 1u << q;
-                any = 1;
-            }
+    // one node (q static, so the per-node registers stay registers)
+    auto relax = [&](int q, int &any) {
+        if (!(live & (1u << q))) return;
+        const int c = hidx(lx + 1, ly + 1, pair * NODES_PER_THREAD + q + 1);
+        const uint32_t a = min(T[c - 1], T[c + 1]);
+        const uint32_t b = min(T[c - HB], T[c + HB]);
+        const uint32_t cz = min(T[c - HB * HB], T[c + HB * HB]);
+        const uint32_t nv = pat_eik::godunov3_int(a, b, cz, F[q], F2[q], F3[q]);
+        if (nv < own[q]) {
+            own[q] = nv;
+            T[c] = nv;
+            changed |= 1u << q;
+            any = 1;
         }
-        if (!__syncthreads_or(any)) break;
+    };
+    // sweeps alternate the order of the thread's nodes; false when a sweep
+    // changed no node of the brick
+    auto sweep = [&](auto rev_c) -> bool {
+        int any = 0;
+#pragma unroll
+        for (int k = 0; k < NODES_PER_THREAD; ++k) relax(decltype(rev_c)::value ? NODES_PER_THREAD - 1 - k : k, any);
+        return __syncthreads_or(any) != 0;
+    };
+    // it ends as the index of the sweep that changed nothing, or the cap
+    static_assert(LOCAL_ITER_CAP3 % 2 == 0, "whole sweep pairs");
+    int it = 0;
+    for (; it < LOCAL_ITER_CAP3; it += 2) {
+        if (!sweep(std::false_type{})) break;
+        if (!sweep(std::true_type{})) { it += 1; break; }
     }
 
     unsigned sides = 0;
@@ -278,12 +258,12 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
     }
     if (S == 0 || P == 0) return PAT_OK;
 
-    // fixed-point unit: the 6-neighbour Dijkstra bound fits, and F = h/(c lsb) stays below 2^23
+    // fixed-point unit: the 6-neighbour Dijkstra bound fits, and F = h/(c lsb) is at most 2^23
     const double tbound = 1.01 * (double)(nx + ny + nz + 3) * h / cmin;
     const double lsb = std::exp2(std::ceil(std::log2(std::max(tbound / 4294967294.0, h / cmin / 8388608.0))));
     ctx->last_eik.lsb_seconds = lsb;
-    std::vector<float> Fh((size_t)n);
-    for (long k = 0; k < n; ++k) Fh[(size_t)k] = (float)(h / ((double)c[(size_t)k] * lsb));
+    std::vector<uint32_t> Fh((size_t)n);  // whole units, at most 2^23
+    for (long k = 0; k < n; ++k) Fh[(size_t)k] = (uint32_t)std::llround(h / ((double)c[(size_t)k] * lsb));
 
     EikGrid3 g;
     g.nx = nx; g.ny = ny; g.nz = nz;
@@ -296,7 +276,7 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
     if (max_bricks > 0x7FFFFFFFL) return pat_fail(PAT_EINVAL, "too many bricks");
 
     if ((rc = ctx->eik_tq.grow((size_t)chunk * n * sizeof(uint32_t)))) return rc;
-    if ((rc = ctx->eik_f.grow((size_t)n * sizeof(float)))) return rc;
+    if ((rc = ctx->eik_f.grow((size_t)n * sizeof(uint32_t)))) return rc;
     if ((rc = ctx->eik_flags.grow((size_t)2 * max_bricks * sizeof(uint32_t)))) return rc;
     if ((rc = ctx->eik_lists.grow((size_t)2 * max_bricks * sizeof(uint32_t)))) return rc;
     if ((rc = ctx->eik_seeds.grow((size_t)chunk * (3 * sizeof(int) + SEED_BOX3 * SEED_BOX3 * SEED_BOX3 * sizeof(uint32_t)))))
@@ -304,16 +284,16 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
     if ((rc = ctx->eik_count.grow(4 * sizeof(uint32_t)))) return rc;
 
     uint32_t *Tq = static_cast<uint32_t *>(ctx->eik_tq.ptr);
-    float *Fd = static_cast<float *>(ctx->eik_f.ptr);
+    uint32_t *Fd = static_cast<uint32_t *>(ctx->eik_f.ptr);
     uint32_t *flags[2] = { static_cast<uint32_t *>(ctx->eik_flags.ptr),
                            static_cast<uint32_t *>(ctx->eik_flags.ptr) + max_bricks };
     uint32_t *lists[2] = { static_cast<uint32_t *>(ctx->eik_lists.ptr),
                            static_cast<uint32_t *>(ctx->eik_lists.ptr) + max_bricks };
     int *seed_ijl = static_cast<int *>(ctx->eik_seeds.ptr);
     uint32_t *seed_val = reinterpret_cast<uint32_t *>(seed_ijl + 3 * chunk);
-    uint32_t *counters = static_cast<uint32_t *>(ctx->eik_count.ptr);  // [0] next count, [1] guard hits, [2..3] sweeps
+    uint32_t *counters = static_cast<uint32_t *>(ctx->eik_count.ptr);  // [0] next count, [1] unused (0), [2..3] sweeps
 
-    PAT_HIP(hipMemcpyAsync(Fd, Fh.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice, st));
+    PAT_HIP(hipMemcpyAsync(Fd, Fh.data(), (size_t)n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     PAT_HIP(hipMemsetAsync(ctx->eik_flags.ptr, 0, (size_t)2 * max_bricks * sizeof(uint32_t), st));
     PAT_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(uint32_t), st));
 

@@ -24,7 +24,7 @@ SIG_F32, SIG_F16 = 0, 1
 EXPORTED = [
     "pat_last_error", "pat_version", "pat_ctx_create", "pat_ctx_destroy", "pat_ctx_reserve",
     "pat_backproject_scratch_bytes", "pat_eikonal_tables", "pat_eikonal_tables_o2", "pat_eikonal_tables_3d",
-    "pat_eikonal_last_stats", "pat_table_to_fixed", "pat_table_to_q16", "pat_table_to_r16", "pat_table_r16_bytes",
+    "pat_eikonal_last_stats", "pat_eikonal_update_eval", "pat_table_to_fixed", "pat_table_to_q16", "pat_table_to_r16", "pat_table_r16_bytes",
     "pat_table_to_x4", "pat_table_x4_bytes",
     "pat_tile_order", "pat_tile_order_3d", "pat_filter", "pat_backproject", "pat_backproject_noalloc",
     "pat_backproject_const",
@@ -85,6 +85,7 @@ def lib() -> C.CDLL:
         L.pat_eikonal_tables_o2.argtypes = [vp, vp, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
         L.pat_eikonal_tables_3d.argtypes = [vp, vp, i32, i32, i32, dbl, vp, i32, vp, i32, vp, vp]
         L.pat_eikonal_last_stats.argtypes = [vp, C.POINTER(EikonalStats)]
+        L.pat_eikonal_update_eval.argtypes = [vp, vp, i32, i32, vp, vp]
         L.pat_table_to_fixed.argtypes = [vp, vp, i32, i32, dbl, dbl, i32, vp, vp]
         L.pat_table_to_q16.argtypes = [vp, vp, i64, dbl, dbl, i32, vp, vp]
         L.pat_table_to_r16.argtypes = [vp, vp, i32, i32, dbl, dbl, i32, vp, vp]
@@ -433,6 +434,20 @@ def tile_order_3d(nx: int, ny: int, nz: int, vox: np.ndarray, tile_w: int = 4, t
     out = np.empty_like(src)
     check(lib().pat_tile_order_3d(nx, ny, nz, src.ctypes.data, src.shape[0], tile_w, tile_h, tile_d,
                                   out.ctypes.data))
+    return out
+
+
+def eikonal_update_eval(nbr, F, dims: int, stream=None):
+    """The tables' local update alone (pat_eikonal_update_eval): nbr int32
+    [n][3] device tensor of neighbour minima as uint32 bits, F int32 [n]
+    slowness units; returns int32 [n] (uint32 bits) on the same device."""
+    torch = _torch()
+    _need(nbr, torch.int32, "nbr")
+    _need(F, torch.int32, "F")
+    if nbr.dim() != 2 or nbr.shape[1] != 3 or F.shape != (nbr.shape[0],):
+        raise ValueError("nbr must be [n][3] and F [n]")
+    out = torch.empty(F.shape, dtype=torch.int32, device=F.device)
+    check(lib().pat_eikonal_update_eval(_ptr(nbr), _ptr(F), int(F.shape[0]), dims, _ptr(out), _stream(stream)))
     return out
 
 

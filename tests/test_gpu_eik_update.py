@@ -1,0 +1,227 @@
+"""The travel-time tables' local update, exact in integers, and the tables'
+independence of the relaxation schedule.
+
+pat_eikonal_update_eval evaluates the update the 2-D and 3-D solvers apply
+(Section II-B, first-order upwind scheme on uint32 fixed-point times).  Its
+definition: the largest T with sum_k max(2 (T - n_k) - 1, 0)^2 <= 4 F^2 over
+the neighbour minima n_k, that is the first-order root rounded to the nearest
+unit.  The checks here:
+  - against that definition by a vectorised binary search over T (not the
+    kernel's closed forms), exhaustively for small F and on random entries up
+    to F = 2^23, the largest slowness the solvers produce;
+  - monotone in every neighbour (raising one never lowers the result), the
+    property that makes the relaxation's fixed point independent of the order
+    of the node updates;
+  - within half a unit of the continuous first-order root, evaluated in FP64
+    by its textbook closed form over the sorted neighbours;
+  - the tables themselves: the same bits whether the sensors are built in one
+    call or in chunks (which changes how many maps each launch relaxes and so
+    the workgroup schedule), in 2-D and 3-D."""
+import numpy as np
+import pytest
+
+from paper_1501_03869_amd import inputs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+INF = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1501_03869_amd import pat
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pat.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_update(nbr, F, dims):
+    """nbr int64 [n][3] (uint32 values), F int64 [n] -> int64 [n]."""
+    from paper_1501_03869_amd import pat
+    nb = torch.from_numpy(np.ascontiguousarray(nbr.astype(np.uint32).view(np.int32))).cuda()
+    f = torch.from_numpy(np.ascontiguousarray(F.astype(np.uint32).view(np.int32))).cuda()
+    out = pat.eikonal_update_eval(nb, f, dims)
+    return out.cpu().numpy().view(np.uint32).astype(np.int64)
+
+
+def defined_update(nbr, F, dims):
+    """Largest T with sum_k max(2 (T - n_k) - 1, 0)^2 <= 4 F^2, held below
+    INF; INF when no neighbour is reached.  Binary search over [m, m + F]."""
+    n = nbr[:, :dims].astype(np.int64)
+    F = F.astype(np.int64)
+    reached = n != INF
+    m = np.where(reached, n, np.iinfo(np.int64).max).min(axis=1)
+    none = ~reached.any(axis=1)
+    m = np.where(none, 0, m)
+    lim = 4 * F * F
+
+    def G(T):
+        x = 2 * (T[:, None] - n) - 1
+        return np.where(reached & (x > 0), x * x, 0).sum(axis=1)
+
+    lo, hi = m.copy(), m + F  # G(lo) = 0; G(m + F + 1) > 4 F^2
+    while np.any(lo < hi):
+        mid = (lo + hi + 1) // 2
+        ok = G(mid) <= lim
+        lo = np.where(ok, mid, lo)
+        hi = np.where(ok, hi, mid - 1)
+    return np.where(none, INF, np.minimum(lo, INF - 1))
+
+
+def continuous_root(nbr, F, dims):
+    """The first-order root in FP64 over the sorted neighbours: one-, two-
+    or three-axis, whichever exceeds the neighbours it uses.  Solved over the
+    offsets from the smallest neighbour, so that FP64 keeps the fraction."""
+    out = np.empty(len(F))
+    for i in range(len(F)):
+        v = sorted(int(x) for x in nbr[i, :dims] if x != INF)
+        base = v[0]
+        o = [float(x - base) for x in v]
+        f = float(F[i])
+        T = f
+        for k in range(2, len(o) + 1):
+            if T <= o[k - 1]:
+                break
+            s = sum(o[:k])
+            q = sum(x * x for x in o[:k])
+            T = (s + np.sqrt(s * s - k * (q - f * f))) / k
+        out[i] = base + T
+    return out
+
+
+def cases_2d():
+    rows = []
+    for F in range(0, 201):
+        for d in range(0, 2 * F + 3):
+            for base in (1000, 2 ** 31 + 12345):
+                rows.append((base, base + d, 0, F))
+                rows.append((base + d, base, 0, F))
+    return np.array(rows, dtype=np.int64)
+
+
+def cases_3d():
+    rng = np.random.default_rng(7)
+    rows = []
+    for F in range(0, 41):
+        for d in range(0, 2 * F + 2):
+            for e in range(d, 2 * F + 2):
+                v = np.array([5000, 5000 + d, 5000 + e])
+                rng.shuffle(v)
+                rows.append((*v, F))
+    return np.array(rows, dtype=np.int64)
+
+
+def cases_large(dims, n, seed):
+    """Random slowness up to 2^23 with neighbour gaps spread over the three
+    regimes and packed near their boundaries."""
+    rng = np.random.default_rng(seed)
+    F = rng.integers(1, 2 ** 23 + 1, n)
+    F[: n // 8] = 2 ** 23 - rng.integers(0, 3, n // 8)
+    a = rng.integers(0, 2 ** 31, n)
+    d = (rng.random(n) * 2.2 * F).astype(np.int64)
+    near = rng.random(n) < 0.3
+    d = np.where(near, np.maximum(F - rng.integers(0, 4, n), 0), d)
+    e = d + (rng.random(n) * 1.5 * F).astype(np.int64)
+    c = a + e if dims == 3 else np.zeros(n, np.int64)
+    return np.stack([a, a + d, c, F], axis=1)
+
+
+def special_cases():
+    F = 100
+    return np.array([
+        (INF, INF, INF, F),          # nothing reached
+        (7, INF, INF, F),            # one neighbour: 7 + F
+        (INF, 7, INF, F),
+        (INF - 3, INF, INF, F),      # held below "not reached"
+        (INF - 3, INF - 2, INF, F),
+        (5, 5, INF, 0),              # zero slowness
+        (5, 5, 5, 0),
+        (0, 0, 0, 2 ** 23),          # the largest slowness
+        (0, 2 ** 23 - 1, 2 ** 23 - 1, 2 ** 23),
+    ], dtype=np.int64)
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_update_matches_its_definition(ctx, dims):
+    rows = np.concatenate([cases_2d() if dims == 2 else cases_3d(), cases_large(dims, 200000, 11 + dims),
+                           special_cases()])
+    nbr, F = rows[:, :3].copy(), rows[:, 3]
+    if dims == 2:
+        nbr[:, 2] = 0
+    got = gpu_update(nbr, F, dims)
+    want = defined_update(nbr, F, dims)
+    bad = np.flatnonzero(got != want)
+    print(f"[eik update] {dims}-D: {len(F)} entries, {len(bad)} differ from the definition", flush=True)
+    assert len(bad) == 0, f"first differing entries {rows[bad[:5]].tolist()}: got {got[bad[:5]]}, want {want[bad[:5]]}"
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_update_is_monotone(ctx, dims):
+    rows = np.concatenate([cases_2d() if dims == 2 else cases_3d(), cases_large(dims, 100000, 21 + dims)])
+    nbr, F = rows[:, :3].copy(), rows[:, 3]
+    if dims == 2:
+        nbr[:, 2] = 0
+    base = gpu_update(nbr, F, dims)
+    for k in range(dims):
+        up = nbr.copy()
+        up[:, k] += 1
+        raised = gpu_update(up, F, dims)
+        lowered = np.flatnonzero(raised < base)
+        print(f"[eik update] {dims}-D, neighbour {k} raised by one: {len(lowered)} results fall", flush=True)
+        assert len(lowered) == 0, f"entries {rows[lowered[:5]].tolist()}"
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_update_rounds_the_continuous_root(ctx, dims):
+    rows = cases_large(dims, 5000, 31 + dims)
+    nbr, F = rows[:, :3].copy(), rows[:, 3]
+    if dims == 2:
+        nbr[:, 2] = 0
+    got = gpu_update(nbr, F, dims).astype(np.float64)
+    root = continuous_root(nbr, F, dims)
+    # T is an integer within half a unit of the root; the FP64 root of values
+    # near 2^31 carries up to about 1e-6 of rounding
+    err = np.abs(got - root).max()
+    print(f"[eik update] {dims}-D: max |T - root| = {err:.6f} units", flush=True)
+    assert err <= 0.5 + 1e-5
+
+
+def test_update_rejects_bad_arguments(ctx):
+    from paper_1501_03869_amd import pat
+    nb = torch.zeros((4, 3), dtype=torch.int32, device="cuda")
+    f = torch.zeros(4, dtype=torch.int32, device="cuda")
+    with pytest.raises(pat.PatError):
+        pat.eikonal_update_eval(nb, f, 4)
+    assert pat.eikonal_update_eval(nb[:0], f[:0], 2).numel() == 0
+    # slowness above 2^23 gives 0
+    big = torch.full((4,), 2 ** 23 + 1, dtype=torch.int32, device="cuda")
+    assert (pat.eikonal_update_eval(nb, big, 2).cpu() == 0).all()
+
+
+def _tables(ctx, geo, sensors, pix, is3):
+    sp = torch.from_numpy(geo.speed).cuda()
+    px = torch.from_numpy(pix).cuda()
+    if is3:
+        return ctx.eikonal_tables_3d(sp, geo.h, sensors, px).cpu().numpy()
+    return ctx.eikonal_tables(sp, geo.h, sensors, px).cpu().numpy()
+
+
+@pytest.mark.parametrize("name,chunks", [("small", (1, 5, 17)), ("paper", (64, 100)), ("tiny3", (1, 4)),
+                                         ("head3", (32, 100))])
+def test_tables_same_bits_in_any_chunking(ctx, name, chunks):
+    is3 = name in ("tiny3", "head3")
+    geo = inputs.config3(name) if is3 else inputs.config(name)
+    sensors = geo.sensors if len(geo.sensors) <= 256 else geo.sensors[:256]
+    whole = _tables(ctx, geo, sensors, geo.pix, is3)
+    again = _tables(ctx, geo, sensors, geo.pix, is3)
+    assert np.array_equal(whole.view(np.uint32), again.view(np.uint32))
+    for ch in chunks:
+        parts = [_tables(ctx, geo, sensors[s:s + ch], geo.pix, is3) for s in range(0, len(sensors), ch)]
+        split = np.concatenate(parts, axis=0)
+        diff = int((split.view(np.uint32) != whole.view(np.uint32)).sum())
+        print(f"[eik tables] {name}: {len(sensors)} sensors in chunks of {ch}: {diff} entries differ", flush=True)
+        assert diff == 0
