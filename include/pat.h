@@ -349,6 +349,11 @@ int pat_filter(pat_ctx *ctx, const float *d_p, int rows, int N, double t0, doubl
  * the remaining shapes use LDS-windowed workgroups over sensor groups, which
  * add their partial sums in scratch.  PAT_TABLE_R16 and PAT_TABLE_F32X4
  * tables need N >= 4 and an aligned d_sig (else PAT_EINVAL).
+ * Sizes: the wave-window kernel takes P < 2^29 and the split-sensor kernel
+ * P < 2^26 (32-bit buffer offsets), so PAT_TABLE_F32X4 tables need
+ * P < 2^26; larger P in the other forms goes to the kernels with 64-bit
+ * offsets.  S, P, N and F are ints, with S*N, P*F and each table row's
+ * entries addressable as 64-bit offsets.
  */
 int pat_backproject(pat_ctx *ctx, const void *d_table, int table_fmt, const void *d_sig, int sig_fmt,
                     int sig_is_filtered, const float *d_frame_scale, const float *d_w, int S, int P,
