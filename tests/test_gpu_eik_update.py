@@ -225,3 +225,57 @@ def test_tables_same_bits_in_any_chunking(ctx, name, chunks):
         diff = int((split.view(np.uint32) != whole.view(np.uint32)).sum())
         print(f"[eik tables] {name}: {len(sensors)} sensors in chunks of {ch}: {diff} entries differ", flush=True)
         assert diff == 0
+
+
+@pytest.mark.parametrize("name", ["small", "paper", "large"])
+def test_tables_satisfy_the_scheme_at_every_node(ctx, name):
+    """Every non-frozen ROI node whose four neighbours are ROI nodes, for
+    every sensor and at full size: the table value T and the first-order root
+    of its final neighbours (FP64, the node's exact slowness h/c) differ by at
+    most ulp32(T) + lsb.  The bound follows from the arithmetic: the table
+    rounds each time to float32 (half an ulp for T and for each neighbour,
+    and the root moves by at most the largest neighbour change), and the
+    integer update rounds the root to the nearest unit (half a unit) with the
+    slowness rounded to whole units (at most half a unit more, since the
+    root's slope in F is at most 1)."""
+    geo = inputs.config(name)
+    nx, ny, h = geo.nx, geo.ny, geo.h
+    pix = geo.pix.astype(np.int64)
+    P = len(pix)
+    col_of = np.full(nx * ny, -1, np.int64)
+    col_of[pix] = np.arange(P)
+    i, j = pix % nx, pix // nx
+    nb = []
+    for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+        ii, jj = i + di, j + dj
+        ok = (ii >= 0) & (ii < nx) & (jj >= 0) & (jj < ny)
+        nb.append(np.where(ok, col_of[np.clip(jj, 0, ny - 1) * nx + np.clip(ii, 0, nx - 1)], -1))
+    inner = np.all(np.stack(nb) >= 0, axis=0)
+    cols = np.flatnonzero(inner)
+    W, E, Sn, N = (torch.from_numpy(x[inner]).cuda() for x in nb)
+    colt = torch.from_numpy(cols).cuda()
+    fh = torch.from_numpy(h / geo.speed.reshape(-1).astype(np.float64)[pix[inner]]).cuda()
+    xs = torch.from_numpy((i[inner] - (nx - 1) / 2.0) * h).cuda()
+    ys = torch.from_numpy((j[inner] - (ny - 1) / 2.0) * h).cuda()
+    T = ctx.eikonal_tables(torch.from_numpy(geo.speed).cuda(), h, geo.sensors, torch.from_numpy(geo.pix).cuda())
+    lsb = ctx.eikonal_stats()["lsb_seconds"]
+    worst, checked = 0.0, 0
+    for s0 in range(0, geo.S, 64):
+        Tc = T[s0:s0 + 64].double()
+        t = Tc[:, colt]
+        a = torch.minimum(Tc[:, W], Tc[:, E])
+        b = torch.minimum(Tc[:, Sn], Tc[:, N])
+        m, d = torch.minimum(a, b), (a - b).abs()
+        two = (a + b + torch.sqrt(torch.clamp(2 * fh * fh - d * d, min=0.0))) / 2
+        upd = torch.where(d >= fh, m + fh, two)
+        ulp = torch.pow(2.0, torch.floor(torch.log2(t)) - 23)
+        bound = ulp + lsb + 1e-15 * t
+        sens = torch.from_numpy(geo.sensors[s0:s0 + 64]).cuda()
+        r = torch.sqrt((xs[None] - sens[:, :1]) ** 2 + (ys[None] - sens[:, 1:]) ** 2)
+        live = r > 2.0 * h * (1 + 1e-9)
+        ratio = torch.where(live, (t - upd).abs() / bound, torch.zeros_like(t))
+        worst = max(worst, float(ratio.max()))
+        checked += int(live.sum())
+    print(f"[eik tables] {name}: {checked} node values of {geo.S} sensors checked, "
+          f"max |T - root| / (ulp32(T) + lsb) = {worst:.3f}", flush=True)
+    assert worst <= 1.0
