@@ -1,8 +1,9 @@
 """Precision study on the 1024^2 workload: every storage variant of the back
 projection gathered on the GPU from the oracle's own eikonal table (FP64 heap
 fast marching, all 1024 sensors, rounded to float32 seconds) and one
-synthetic frame, and checked against the FP64 oracle on 94 whole 32-pixel
-tiles (3008 pixels, the oracle recomputing them one by one).
+synthetic frame, and checked against the FP64 oracle: on the whole image
+(823592 pixels) against the oracle gathering the delays each variant stores,
+and on 94 whole 32-pixel tiles (3008 pixels) against the a-priori bounds.
 
 Variants: V0 float32 table + float32 frame; V1 16.16 table + float32 frame;
 V2 float32 table + binary16 frame (per-frame scale); V3 16.16 + binary16;
@@ -62,7 +63,6 @@ def test_large_grid_precision_variants(orc):
     ctx = pat.Context(0)
     try:
         Td = dev(T32)
-        del T32
         pd, hd = dev(p), dev(h16)
         sd = torch.tensor([scale], dtype=torch.float32, device="cuda")
         got = {"V0": ctx.backproject(Td, pd, dt, filtered=False),
@@ -75,7 +75,8 @@ def test_large_grid_precision_variants(orc):
         got["V4"] = ctx.backproject(r16, hd, dt, filtered=False, frame_scale=sd)
         got["V4a"] = ctx.backproject(r16, pd, dt, filtered=False)
         torch.cuda.synchronize()
-        got = {k: v.cpu().numpy()[sample] for k, v in got.items()}
+        got_full = {k: v.cpu().numpy() for k, v in got.items()}
+        got = {k: v[sample] for k, v in got_full.items()}
         del Td, r16
     finally:
         ctx.close()
@@ -109,3 +110,22 @@ def test_large_grid_precision_variants(orc):
         assert np.all(err <= bound), name
     # the V0 image is also within the FP32 target against the unrounded table
     assert rel_l2(got["V0"], ref64) <= IMG_TOL
+
+    # the whole image of every variant against the oracle gathering exactly
+    # the delays the variant stores
+    t = time.time()
+    full = {"V0": orc.gather(T32, b32, dt), "V2": orc.gather(T32, b16, dt)}
+    q = orc.table_to_q16(T32, dt, N)
+    full["V1"], full["V3"] = orc.gather_q16(q, b32), orc.gather_q16(q, b16)
+    del q
+    off, hdr = orc.table_to_r16(T32, dt, N)
+    qr = orc.r16_to_q16(off, hdr)
+    del off, hdr, T32
+    full["V4"], full["V4a"] = orc.gather_q16(qr, b16), orc.gather_q16(qr, b32)
+    del qr
+    print(f"[precision-1024] whole-image oracle references in {time.time() - t:.1f} s", flush=True)
+    for name in ("V0", "V1", "V2", "V3", "V4", "V4a"):
+        e = rel_l2(got_full[name], full[name])
+        print(f"[precision-1024] {name}: whole image ({P} pixels) rel L2 vs the oracle on the stored delays {e:.3e}",
+              flush=True)
+        assert e <= IMG_TOL, name
