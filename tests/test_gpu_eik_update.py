@@ -279,3 +279,63 @@ def test_tables_satisfy_the_scheme_at_every_node(ctx, name):
     print(f"[eik tables] {name}: {checked} node values of {geo.S} sensors checked, "
           f"max |T - root| / (ulp32(T) + lsb) = {worst:.3f}", flush=True)
     assert worst <= 1.0
+
+
+def _root3(a, b, c, fh):
+    """First-order root over the three axis minima (FP64 tensors), as the
+    textbook sorted form: one-, two- or three-axis."""
+    s = torch.stack([a, b, c])
+    s, _ = torch.sort(s, dim=0)
+    a, b, c = s[0], s[1], s[2]
+    t1 = a + fh
+    d = b - a
+    t2 = (a + b + torch.sqrt(torch.clamp(2 * fh * fh - d * d, min=0.0))) / 2
+    sm, sq = a + b + c, a * a + b * b + c * c
+    t3 = (sm + torch.sqrt(torch.clamp(sm * sm - 3 * (sq - fh * fh), min=0.0))) / 3
+    return torch.where(t1 <= b, t1, torch.where(t2 <= c, t2, t3))
+
+
+@pytest.mark.parametrize("name", ["tiny3", "head3"])
+def test_tables3_satisfy_the_scheme_at_every_node(ctx, name):
+    """The 3-D form of the check above: every non-frozen ROI voxel whose six
+    neighbours are ROI voxels, every sensor, within ulp32(T) + lsb of the
+    root of its final neighbours (the three-axis root is also 1-Lipschitz in
+    its neighbours, with slope at most 1 in F)."""
+    geo = inputs.config3(name)
+    nx, ny, nz, h = geo.nx, geo.ny, geo.nz, geo.h
+    vox = geo.pix.astype(np.int64)
+    P = len(vox)
+    col_of = np.full(nx * ny * nz, -1, np.int64)
+    col_of[vox] = np.arange(P)
+    i, j, l = vox % nx, (vox // nx) % ny, vox // (nx * ny)
+    nb = []
+    for di, dj, dl in ((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0), (0, 0, -1), (0, 0, 1)):
+        ii, jj, ll = i + di, j + dj, l + dl
+        ok = (ii >= 0) & (ii < nx) & (jj >= 0) & (jj < ny) & (ll >= 0) & (ll < nz)
+        k2 = (np.clip(ll, 0, nz - 1) * ny + np.clip(jj, 0, ny - 1)) * nx + np.clip(ii, 0, nx - 1)
+        nb.append(np.where(ok, col_of[k2], -1))
+    inner = np.all(np.stack(nb) >= 0, axis=0)
+    cols = torch.from_numpy(np.flatnonzero(inner)).cuda()
+    nbt = [torch.from_numpy(x[inner]).cuda() for x in nb]
+    fh = torch.from_numpy(h / geo.speed.reshape(-1).astype(np.float64)[vox[inner]]).cuda()
+    pos = torch.from_numpy(np.stack([(i[inner] - (nx - 1) / 2.0) * h, (j[inner] - (ny - 1) / 2.0) * h,
+                                     (l[inner] - (nz - 1) / 2.0) * h], axis=1)).cuda()
+    T = ctx.eikonal_tables_3d(torch.from_numpy(geo.speed).cuda(), h, geo.sensors, torch.from_numpy(geo.pix).cuda())
+    lsb = ctx.eikonal_stats()["lsb_seconds"]
+    worst, checked = 0.0, 0
+    for s0 in range(0, geo.S, 32):
+        Tc = T[s0:s0 + 32].double()
+        t = Tc[:, cols]
+        ax = [torch.minimum(Tc[:, nbt[2 * q]], Tc[:, nbt[2 * q + 1]]) for q in range(3)]
+        upd = _root3(ax[0], ax[1], ax[2], fh)
+        ulp = torch.pow(2.0, torch.floor(torch.log2(t)) - 23)
+        bound = ulp + lsb + 1e-15 * t
+        sens = torch.from_numpy(geo.sensors[s0:s0 + 32]).cuda()
+        r = torch.cdist(sens, pos)
+        live = r > 2.0 * h * (1 + 1e-9)
+        ratio = torch.where(live, (t - upd).abs() / bound, torch.zeros_like(t))
+        worst = max(worst, float(ratio.max()))
+        checked += int(live.sum())
+    print(f"[eik3 tables] {name}: {checked} voxel values of {geo.S} sensors checked, "
+          f"max |T - root| / (ulp32(T) + lsb) = {worst:.3f}", flush=True)
+    assert worst <= 1.0
