@@ -78,7 +78,8 @@ __device__ __forceinline__ float eik_f3(uint32_t F) {
 }
 
 // 2-D: a, b the upwind minima along x and y; F2 = 2F^2 as a float (exact
-// below 2^24, else within a relative 2^-24), kept per node by the caller.
+// while 2F^2 < 2^24, else within a relative 2^-24), kept per node by the
+// caller.
 // z = 2F^2 - d^2 lies in [F^2, 2F^2] for the two-sided root, its float
 // estimate is within a relative 2^-23 and the hardware square root within a
 // unit of the last place, so the estimate of isqrt(z) < 2^24 is within a few
