@@ -195,11 +195,18 @@ def test_small_shapes(ctx, orc, force_win, S, P, N, F, tfmt, sig):
     assert err <= IMG_TOL
 
 
-@pytest.mark.parametrize("F,sig,tfmt", [(3, "f32", "f32"), (5, "f16", "q16"), (4, "f32", "r16")])
-def test_frames_sharing_table_reads(ctx, orc, F, sig, tfmt):
+@pytest.mark.parametrize("F,sig,tfmt,filtered,weights", [
+    (3, "f32", "f32", False, False),
+    (5, "f16", "q16", False, False),
+    (4, "f32", "r16", False, False),
+    (4, "f16", "f32", True, True),     # pre-filtered FP16 frames with weights, 4 per wave
+    (2, "f32", "q16", True, False),    # pre-filtered FP32 frames, 2 per wave
+    (6, "f32", "f32", False, True),    # raw frames with weights; a last block of 2 past F
+])
+def test_frames_sharing_table_reads(ctx, orc, F, sig, tfmt, filtered, weights):
     # a table larger than the 256 MB Infinity Cache (520 x 140000 float32
-    # entries, 291 MB): each wave decodes its delays once for 2 (F = 3) or 4
-    # frames, the last block holding frames past F that are not stored
+    # entries, 291 MB): each wave decodes its delays once for 2 (F = 2, 3) or
+    # 4 frames, the last block holding frames past F that are not stored
     S, P, N, dt = 520, 140000, 512, 4e-8
     rng = np.random.default_rng(300 + F)
     base = rng.uniform(2.0, N - 150.0, (S, 1))
@@ -207,7 +214,11 @@ def test_frames_sharing_table_reads(ctx, orc, F, sig, tfmt):
     T = (u * dt).astype(np.float32)
     assert T.nbytes > (256 << 20)
     p = inputs.random_signals(301 + F, S, N, F)
-    got, ref = _run(ctx, orc, T, p, dt, 0.0, tfmt, sig, False, None)
+    if filtered:
+        p = orc.filt(p.astype(np.float64), dt).astype(np.float32)
+    w = np.random.default_rng(302 + F).uniform(0.5, 1.5, S).astype(np.float32) if weights else None
+    got, ref = _run(ctx, orc, T, p, dt, 0.0, tfmt, sig, filtered, w)
     err = rel_l2(got, ref)
-    print(f"[win] frames sharing table reads F={F} {tfmt} {sig}: rel L2 {err:.3e}", flush=True)
+    print(f"[win] frames sharing table reads F={F} {tfmt} {sig} filtered={filtered} weights={weights}: "
+          f"rel L2 {err:.3e}", flush=True)
     assert err <= IMG_TOL
