@@ -500,10 +500,10 @@ def main():
     ap.add_argument("--table", choices=("auto", "x4", "plain"), default="auto",
                     help="headline table form: auto = four sensors interleaved (pat_table_to_x4) while the table "
                          "stays in the Infinity Cache, the plain [S][P] table when it streams from HBM")
-    ap.add_argument("--only", choices=("headline", "rotated", "batch64"), default=None,
-                    help="profiling runs: build the tables, then only the headline single-frame launches, only "
-                         "the gather on rotated table copies (the table streamed from HBM), or only 64-frame "
-                         "launches; prints no JSON line")
+    ap.add_argument("--only", choices=("tables", "headline", "rotated", "batch64"), default=None,
+                    help="profiling runs: only the two table builds, or the table builds followed by only the "
+                         "headline single-frame launches, only the gather on rotated table copies (the table "
+                         "streamed from HBM), or only 64-frame launches; prints no JSON line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -553,6 +553,8 @@ def main():
     est = ctx.eikonal_stats()
     n_nodes = geo.nx * geo.ny * (geo.nz if vol else 1)
     print(f"[bench] tables built in {build_s:.3f} s ({est['rounds']} rounds)", file=sys.stderr, flush=True)
+    if args.only == "tables":
+        return
     build_o2_s = None
     if not vol and geo.nx * geo.ny <= 512 * 512:
         # the paper's second-order scheme (heap-ordered marching, one map per wave)
