@@ -339,3 +339,50 @@ def test_tables3_satisfy_the_scheme_at_every_node(ctx, name):
     print(f"[eik3 tables] {name}: {checked} voxel values of {geo.S} sensors checked, "
           f"max |T - root| / (ulp32(T) + lsb) = {worst:.3f}", flush=True)
     assert worst <= 1.0
+
+
+def test_random_media_satisfy_the_scheme_at_every_node(ctx):
+    """Random small grids (2 x N strips, sizes across tile edges), speeds
+    1000-4000 m/s per node, random sensors and every node in the ROI: every
+    non-frozen node, edges included (a missing neighbour counts as +inf),
+    is within ulp32(T) + lsb of the root of its final neighbours, and its
+    increment over the smaller upwind neighbour lies in [f h / sqrt(2), f h]
+    (causality), both up to the same bound."""
+    rng = np.random.default_rng(4242)
+    worst, worst_c = 0.0, 0.0
+    for case in range(16):
+        nx, ny = int(rng.integers(2, 41)), int(rng.integers(2, 41))
+        if case == 0:
+            nx, ny = 2, 37
+        if case == 1:
+            nx, ny = 40, 2
+        h = float(rng.uniform(0.05e-3, 0.5e-3))
+        c = rng.uniform(1000, 4000, size=(ny, nx)).astype(np.float32)
+        x, y = inputs.node_coords(nx, ny, h)
+        S = int(rng.integers(1, 6))
+        sens = np.stack([rng.uniform(x[0], x[-1], S), rng.uniform(y[0], y[-1], S)], 1)
+        pix = np.arange(nx * ny, dtype=np.int32)
+        T = ctx.eikonal_tables(torch.from_numpy(c).cuda(), h, sens, torch.from_numpy(pix).cuda())
+        lsb = ctx.eikonal_stats()["lsb_seconds"]
+        t = T.double().cpu().numpy().reshape(S, ny, nx)
+        pad = np.full((S, ny + 2, nx + 2), np.inf)
+        pad[:, 1:-1, 1:-1] = t
+        a = np.minimum(pad[:, 1:-1, :-2], pad[:, 1:-1, 2:])
+        b = np.minimum(pad[:, :-2, 1:-1], pad[:, 2:, 1:-1])
+        fh = h / c.astype(np.float64)
+        m, M = np.minimum(a, b), np.maximum(a, b)
+        d = M - m
+        with np.errstate(invalid="ignore"):
+            two = (a + b + np.sqrt(np.maximum(2 * fh * fh - d * d, 0.0))) / 2
+        upd = np.where(d >= fh, m + fh, two)
+        bound = 2.0 ** (np.floor(np.log2(t)) - 23) + lsb + 1e-15 * t
+        r = np.sqrt((x[None, None, :] - sens[:, 0, None, None]) ** 2 + (y[None, :, None] - sens[:, 1, None, None]) ** 2)
+        live = r > 2.0 * h * (1 + 1e-9)
+        res = np.where(live, np.abs(t - upd) / bound, 0.0)
+        inc = t - m
+        caus = np.where(live, np.maximum(fh / np.sqrt(2) - inc, inc - fh) / bound, 0.0)
+        worst, worst_c = max(worst, float(res.max())), max(worst_c, float(caus.max()))
+        assert res.max() <= 1.0, (case, nx, ny)
+        assert caus.max() <= 1.0, (case, nx, ny)
+    print(f"[eik tables] random media: max |T - root| / bound {worst:.3f}; causality excess / bound {worst_c:.3f}",
+          flush=True)
