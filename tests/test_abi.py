@@ -43,6 +43,18 @@ def test_null_context_is_rejected_without_gpu():
     assert L.pat_ctx_create(0, None) == pat.PAT_EINVAL
 
 
+def test_update_eval_validates_before_any_launch():
+    # argument errors return before the library touches the GPU
+    L = pat.lib()
+    assert L.pat_eikonal_update_eval(None, None, -1, 2, None, None) == pat.PAT_EINVAL
+    assert b"negative" in L.pat_last_error()
+    assert L.pat_eikonal_update_eval(None, None, 4, 4, None, None) == pat.PAT_EINVAL
+    assert b"dims" in L.pat_last_error()
+    assert L.pat_eikonal_update_eval(None, None, 4, 3, None, None) == pat.PAT_EINVAL
+    assert b"null" in L.pat_last_error()
+    assert L.pat_eikonal_update_eval(None, None, 0, 2, None, None) == pat.PAT_OK
+
+
 def _morton(i, j):
     r = 0
     for b in range(16):
