@@ -14,7 +14,9 @@
 //    (workgroup OR-reduction), then writes the changed nodes back and
 //    activates the neighbour tiles whose shared edge changed.  Rounds repeat
 //    until no tile is active.  Values only decrease, and a sweep that changes
-//    nothing leaves every node at its update.
+//    nothing leaves every node at its update.  Large rounds relax each tile
+//    with one wave sweeping anti-diagonals (k_eik_tile_diag), small ones with
+//    256 threads sweeping 4-node strips (k_eik_tile).
 //  * The update is exact in integers (eik_update.h): with the node's
 //    F = round(h / (c lsb)) whole units it is the first-order root
 //    T = min(a, b) + F when |a - b| >= F, else
@@ -38,6 +40,10 @@ namespace {
 constexpr int TS = 32;                  // tile edge (nodes)
 constexpr int HS = TS + 2;              // tile edge with halo
 constexpr int EK_THREADS = 256;         // 32 columns x 8 strips of 4 rows
+// Rounds with at least this many active tiles (4 per SIMD) take the
+// one-wave anti-diagonal kernel; smaller rounds, which it cannot fill the GPU
+// with, take the strip kernel.  Both reach the same fixed point.
+constexpr uint32_t EIK_DIAG_MIN_TILES = 4096;
 constexpr int ROWS_PER_THREAD = TS * TS / EK_THREADS;
 constexpr uint32_t TQ_INF = 0xFFFFFFFFu;
 constexpr int SEED_BOX = 5;             // frozen nodes lie in a 5x5 box around the nearest node
@@ -201,6 +207,130 @@ __global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ 
     __syncthreads();
     if (tid == 0) {
         atomicAdd(reinterpret_cast<unsigned long long *>(counters + 2), (unsigned long long)min(it + 1, LOCAL_ITER_CAP));
+        const unsigned sb = side_bits;
+        uint32_t *cnt_next = counters;
+        const uint32_t base = (uint32_t)m * g.tiles_per_map;
+        if ((sb & 1u) && ty > 0) activate(base + (ty - 1) * g.tiles_x + tx, flags_next, list_next, cnt_next);
+        if ((sb & 2u) && ty + 1 < g.tiles_y) activate(base + (ty + 1) * g.tiles_x + tx, flags_next, list_next, cnt_next);
+        if ((sb & 4u) && tx > 0) activate(base + ty * g.tiles_x + tx - 1, flags_next, list_next, cnt_next);
+        if ((sb & 8u) && tx + 1 < g.tiles_x) activate(base + ty * g.tiles_x + tx + 1, flags_next, list_next, cnt_next);
+        if (sb & 16u) activate(tile, flags_next, list_next, cnt_next);
+    }
+}
+
+// One wave per tile, sweeping anti-diagonals: in each pass the two half-waves
+// walk the tile's 63 diagonals in opposite directions (down-right and
+// up-left, then down-left and up-right), lane i of a half taking column i
+// of the current diagonal, so that a front moving with a sweep crosses the
+// whole tile in one pass.  Both halves update the tile at once; the update
+// is monotone, so the order in which their writes land changes the work,
+// not the result.  Passes repeat until one pair changes no node.
+constexpr int DG_PAIRS = 48;                 // a tile that has not settled re-queues itself
+constexpr uint32_t F_DEAD = 0xFFFFFFFFu;     // frozen or outside the grid: never updated
+
+__global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq, const uint32_t *__restrict__ Fmap,
+                                                      EikGrid g, const int *__restrict__ seed_ij,
+                                                      const uint32_t *__restrict__ seed_val,
+                                                      const uint32_t *__restrict__ list_cur,
+                                                      uint32_t *__restrict__ flags_cur,
+                                                      uint32_t *__restrict__ list_next,
+                                                      uint32_t *__restrict__ flags_next,
+                                                      uint32_t *__restrict__ counters) {
+    __shared__ uint32_t T[HS * HS];
+    __shared__ uint32_t Fl[TS * TS];   // F of each node, F_DEAD where not updated
+    __shared__ uint32_t chg[TS];       // bit x of word y: node (x, y) lowered during the visit
+    __shared__ uint32_t side_bits;
+
+    const int lane = threadIdx.x;
+    const uint32_t tile = list_cur[blockIdx.x];
+    const int m = (int)(tile / g.tiles_per_map);
+    const int r = (int)(tile % g.tiles_per_map);
+    const int ty = r / g.tiles_x, tx = r % g.tiles_x;
+    const int gx0 = tx * TS, gy0 = ty * TS;
+    uint32_t *map = Tq + (long)m * g.nx * g.ny;
+    if (lane == 0) {
+        flags_cur[tile] = 0u;
+        side_bits = 0u;
+    }
+    if (lane < TS) chg[lane] = 0u;
+    for (int idx = lane; idx < 4 * TS; idx += 64) {
+        const int side = idx / TS, o = idx % TS;
+        int gx, gy, l;
+        if (side == 0) { gx = gx0 + o; gy = gy0 - 1; l = o + 1; }
+        else if (side == 1) { gx = gx0 + o; gy = gy0 + TS; l = (TS + 1) * HS + o + 1; }
+        else if (side == 2) { gx = gx0 - 1; gy = gy0 + o; l = (o + 1) * HS; }
+        else { gx = gx0 + TS; gy = gy0 + o; l = (o + 1) * HS + TS + 1; }
+        const bool in = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny;
+        T[l] = in ? map[(long)gy * g.nx + gx] : TQ_INF;
+    }
+    // interior: two rows of 32 per load instruction
+    for (int j = 0; j < TS * TS / 64; ++j) {
+        const int node = j * 64 + lane, y = node / TS, x = node % TS;
+        const int gx = gx0 + x, gy = gy0 + y;
+        uint32_t v = TQ_INF, f = F_DEAD, sv;
+        if (gx < g.nx && gy < g.ny) {
+            const long k = (long)gy * g.nx + gx;
+            v = map[k];
+            if (!is_frozen(gx, gy, seed_ij, seed_val, m, sv)) f = Fmap[k];
+        }
+        T[(y + 1) * HS + x + 1] = v;
+        Fl[node] = f;
+    }
+    __syncthreads();
+
+    const int half = lane >> 5, i = lane & (TS - 1);
+    // x' = i, y' = k - i in the half's sweep frame; the frame flips x for
+    // half 1 and y for half 1 in the first pass and half 0 in the second
+    const int xs = half ? TS - 1 - i : i;
+    int pair = 0;
+    for (; pair < DG_PAIRS; ++pair) {
+        int any = 0;
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool flip_y = (pass == 0) == (half == 1);
+            for (int k = 0; k < 2 * TS - 1; ++k) {
+                const int yp = k - i;
+                if ((unsigned)yp < (unsigned)TS) {
+                    const int y = flip_y ? TS - 1 - yp : yp;
+                    const uint32_t f = Fl[y * TS + xs];
+                    if (f != F_DEAD) {
+                        const int c = (y + 1) * HS + xs + 1;
+                        const uint32_t a = min(T[c - 1], T[c + 1]);
+                        const uint32_t b = min(T[c - HS], T[c + HS]);
+                        const uint32_t nv = pat_eik::godunov2_int(a, b, f, pat_eik::eik_f2(f));
+                        if (nv < T[c]) {
+                            T[c] = nv;
+                            atomicOr(&chg[y], 1u << xs);
+                            any = 1;
+                        }
+                    }
+                }
+                // the wave's LDS accesses execute in order, so the next
+                // diagonal reads this one's writes; the pair's closing barrier
+                // settles everything before a pair can report no change
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (!__syncthreads_or(any)) break;
+    }
+
+    unsigned sides = 0;
+    for (int j = 0; j < TS * TS / 64; ++j) {
+        const int node = j * 64 + lane, y = node / TS, x = node % TS;
+        if (!((chg[y] >> x) & 1u)) continue;
+        map[(long)(gy0 + y) * g.nx + gx0 + x] = T[(y + 1) * HS + x + 1];
+        if (y == 0) sides |= 1u;
+        if (y == TS - 1) sides |= 2u;
+        if (x == 0) sides |= 4u;
+        if (x == TS - 1) sides |= 8u;
+    }
+    if (pair == DG_PAIRS) sides |= 16u;
+    if (sides) atomicOr(&side_bits, sides);
+    __syncthreads();
+    if (lane == 0) {
+        // two directional sweeps per pass, two passes per pair
+        atomicAdd(reinterpret_cast<unsigned long long *>(counters + 2),
+                  (unsigned long long)(4 * min(pair + 1, DG_PAIRS)));
         const unsigned sb = side_bits;
         uint32_t *cnt_next = counters;
         const uint32_t base = (uint32_t)m * g.tiles_per_map;
@@ -391,8 +521,12 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
             if (++chunk_rounds > round_cap)
                 return pat_fail(PAT_ENOCONV, "eikonal relaxation did not settle within %ld rounds", round_cap);
             PAT_HIP(hipMemsetAsync(counters, 0, sizeof(uint32_t), st));
-            k_eik_tile<<<dim3(cnt), EK_THREADS, 0, st>>>(Tq, Fd, g, seed_ij, seed_val, lists[cur], flags[cur],
-                                                         lists[cur ^ 1], flags[cur ^ 1], counters);
+            if (cnt >= EIK_DIAG_MIN_TILES)
+                k_eik_tile_diag<<<dim3(cnt), 64, 0, st>>>(Tq, Fd, g, seed_ij, seed_val, lists[cur], flags[cur],
+                                                          lists[cur ^ 1], flags[cur ^ 1], counters);
+            else
+                k_eik_tile<<<dim3(cnt), EK_THREADS, 0, st>>>(Tq, Fd, g, seed_ij, seed_val, lists[cur], flags[cur],
+                                                             lists[cur ^ 1], flags[cur ^ 1], counters);
             PAT_HIP(hipGetLastError());
             PAT_HIP(hipMemcpyAsync(ctx->eik_count_host, counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
             PAT_HIP(hipStreamSynchronize(st));
