@@ -40,10 +40,11 @@ namespace {
 constexpr int TS = 32;                  // tile edge (nodes)
 constexpr int HS = TS + 2;              // tile edge with halo
 constexpr int EK_THREADS = 256;         // 32 columns x 8 strips of 4 rows
-// Rounds with at least this many active tiles (4 per SIMD) take the
+// Rounds with at least this many active tiles (one per SIMD) take the
 // one-wave anti-diagonal kernel; smaller rounds, which it cannot fill the GPU
-// with, take the strip kernel.  Both reach the same fixed point.
-constexpr uint32_t EIK_DIAG_MIN_TILES = 4096;
+// with, take the strip kernel (4 waves per tile).  Both reach the same fixed
+// point.  Thresholds of 0 and 4096 tiles were 1-3 % slower.
+constexpr uint32_t EIK_DIAG_MIN_TILES = 1024;
 constexpr int ROWS_PER_THREAD = TS * TS / EK_THREADS;
 constexpr uint32_t TQ_INF = 0xFFFFFFFFu;
 constexpr int SEED_BOX = 5;             // frozen nodes lie in a 5x5 box around the nearest node
@@ -222,7 +223,7 @@ __global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ 
 // walk the tile's 63 diagonals in opposite directions (down-right and
 // up-left, then down-left and up-right), lane i of a half taking column i
 // of the current diagonal, so that a front moving with a sweep crosses the
-// whole tile in one pass.  Both halves update the tile at once; the update
+// tile in at most two passes.  Both halves update the tile at once; the update
 // is monotone, so the order in which their writes land changes the work,
 // not the result.  Passes repeat until one pair changes no node.
 constexpr int DG_PAIRS = 48;                 // a tile that has not settled re-queues itself
@@ -288,9 +289,13 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
             const bool flip_y = (pass == 0) == (half == 1);
-            for (int k = 0; k < 2 * TS - 1; ++k) {
-                const int yp = k - i;
-                if ((unsigned)yp < (unsigned)TS) {
+            // folded: in step k lane i takes diagonal k while i <= k, else
+            // diagonal k + 32, so every lane works in every step; each
+            // diagonal follows the one before it within the pass, except
+            // diagonal 32, which reads diagonal 31 from the pass before
+            for (int k = 0; k < TS; ++k) {
+                const int yp = i <= k ? k - i : k + TS - i;
+                {
                     const int y = flip_y ? TS - 1 - yp : yp;
                     const uint32_t f = Fl[y * TS + xs];
                     if (f != F_DEAD) {
