@@ -222,8 +222,8 @@ __global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ 
 // One wave per tile, sweeping anti-diagonals: in each pass the two half-waves
 // walk the tile's 63 diagonals in opposite directions (down-right and
 // up-left, then down-left and up-right), lane i of a half taking column i
-// of the current diagonal, so that a front moving with a sweep crosses the
-// tile in at most two passes.  Both halves update the tile at once; the update
+// of its diagonal (the diagonals folded into 32 steps per pass, below), so
+// that a front moving with a sweep crosses the tile in at most two passes.  Both halves update the tile at once; the update
 // is monotone, so the order in which their writes land changes the work,
 // not the result.  Passes repeat until one pair changes no node.
 constexpr int DG_PAIRS = 48;                 // a tile that has not settled re-queues itself
@@ -280,8 +280,8 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
     __syncthreads();
 
     const int half = lane >> 5, i = lane & (TS - 1);
-    // x' = i, y' = k - i in the half's sweep frame; the frame flips x for
-    // half 1 and y for half 1 in the first pass and half 0 in the second
+    // in the half's sweep frame lane i takes column x' = i; the frame flips x
+    // for half 1, and y for half 1 in the first pass and half 0 in the second
     const int xs = half ? TS - 1 - i : i;
     int pair = 0;
     for (; pair < DG_PAIRS; ++pair) {
@@ -289,25 +289,24 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
             const bool flip_y = (pass == 0) == (half == 1);
-            // folded: in step k lane i takes diagonal k while i <= k, else
-            // diagonal k + 32, so every lane works in every step; each
-            // diagonal follows the one before it within the pass, except
-            // diagonal 32, which reads diagonal 31 from the pass before
+            // folded diagonals: in step k lane i takes row y' = k - i of
+            // diagonal k while i <= k, else row k + 32 - i of diagonal k + 32,
+            // so every lane works in every step; each diagonal follows the one
+            // before it within the pass, except diagonal 32, which reads
+            // diagonal 31 from the pass before
             for (int k = 0; k < TS; ++k) {
                 const int yp = i <= k ? k - i : k + TS - i;
-                {
-                    const int y = flip_y ? TS - 1 - yp : yp;
-                    const uint32_t f = Fl[y * TS + xs];
-                    if (f != F_DEAD) {
-                        const int c = (y + 1) * HS + xs + 1;
-                        const uint32_t a = min(T[c - 1], T[c + 1]);
-                        const uint32_t b = min(T[c - HS], T[c + HS]);
-                        const uint32_t nv = pat_eik::godunov2_int(a, b, f, pat_eik::eik_f2(f));
-                        if (nv < T[c]) {
-                            T[c] = nv;
-                            atomicOr(&chg[y], 1u << xs);
-                            any = 1;
-                        }
+                const int y = flip_y ? TS - 1 - yp : yp;
+                const uint32_t f = Fl[y * TS + xs];
+                if (f != F_DEAD) {
+                    const int c = (y + 1) * HS + xs + 1;
+                    const uint32_t a = min(T[c - 1], T[c + 1]);
+                    const uint32_t b = min(T[c - HS], T[c + HS]);
+                    const uint32_t nv = pat_eik::godunov2_int(a, b, f, pat_eik::eik_f2(f));
+                    if (nv < T[c]) {
+                        T[c] = nv;
+                        atomicOr(&chg[y], 1u << xs);
+                        any = 1;
                     }
                 }
                 // the wave's LDS accesses execute in order, so the next
