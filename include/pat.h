@@ -129,7 +129,11 @@ size_t pat_backproject_scratch_bytes(int S, int P, int F);
  * to the upwind fixed point by tile-parallel relaxation in integer fixed
  * point, with an update exact in integers (the first-order root rounded to
  * the nearest unit of lsb_seconds, each node's slowness h/c in whole units),
- * so the same inputs give the same table bit for bit.  Synchronises `stream`.  PAT_ENOCONV if the relaxation exceeds its
+ * so the same inputs give the same table bit for bit.  The slowest node's
+ * slowness is at most 2^23 units, so a medium whose speeds span a ratio rho
+ * rounds its fastest nodes' slowness to about 0.5 rho / 2^23 relative or
+ * more (1e-5 at rho of about 23 on a 1024^2 grid, where the grid's extent
+ * sets the unit).  Synchronises `stream`.  PAT_ENOCONV if the relaxation exceeds its
  * round cap, 100 (tiles_x + tiles_y) + 1000 rounds of 32 x 32 tiles (never
  * expected; PAT_EIK_ROUND_CAP lowers it); the context stays usable.
  */
