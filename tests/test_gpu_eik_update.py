@@ -386,3 +386,30 @@ def test_random_media_satisfy_the_scheme_at_every_node(ctx):
         assert caus.max() <= 1.0, (case, nx, ny)
     print(f"[eik tables] random media: max |T - root| / bound {worst:.3f}; causality excess / bound {worst_c:.3f}",
           flush=True)
+
+
+def test_tables_across_internal_chunks(ctx, orc):
+    """A 2048^2 grid with 600 sensors: the working maps (16 MB each) exceed the
+    8 GiB a build holds at once, so one call relaxes the sensors in two
+    chunks (512 + 88).  The tables must be the same bits as two calls of 300
+    sensors each, and the first sensor and the last (in the second chunk)
+    must match the oracle's fast marching."""
+    n, h = 2048, 0.05e-3
+    rng = np.random.default_rng(2048)
+    # a smooth medium: 1540 m/s with a faster ring between r = 30 and 36 mm
+    x = (np.arange(n) - (n - 1) / 2.0) * h
+    r = np.hypot(x[None, :], x[:, None])
+    speed = np.where((r > 30e-3) & (r < 36e-3), 2600.0, 1540.0).astype(np.float32)
+    ang = np.linspace(0, 2 * np.pi, 600, endpoint=False) + rng.uniform(0, 1e-3, 600)
+    sensors = np.stack([40e-3 * np.cos(ang), 40e-3 * np.sin(ang)], 1)
+    pix = np.arange(0, n * n, 97, dtype=np.int32)
+    sp, px = torch.from_numpy(speed).cuda(), torch.from_numpy(pix).cuda()
+    whole = ctx.eikonal_tables(sp, h, sensors, px).cpu().numpy()
+    parts = np.concatenate([ctx.eikonal_tables(sp, h, sensors[s:s + 300], px).cpu().numpy() for s in (0, 300)])
+    diff = int((whole.view(np.uint32) != parts.view(np.uint32)).sum())
+    ref = orc.tables(speed, h, sensors[[0, 599]], pix)
+    err = float((np.abs(whole[[0, 599]] - ref) / ref).max())
+    print(f"[eik tables] 2048^2, 600 sensors in two internal chunks: {diff} entries differ from two calls; "
+          f"sensors 0 and 599 against the oracle: max rel err {err:.3e}", flush=True)
+    assert diff == 0
+    assert err <= 1e-5
