@@ -413,3 +413,24 @@ def test_tables_across_internal_chunks(ctx, orc):
           f"sensors 0 and 599 against the oracle: max rel err {err:.3e}", flush=True)
     assert diff == 0
     assert err <= 1e-5
+
+
+def test_tables3_across_internal_chunks(ctx):
+    """A 256^3 grid with 150 sensors: the working maps (67 MB each) exceed the
+    8 GiB a build holds at once, so one call relaxes the sensors in two
+    chunks (128 + 22); the tables must be the same bits as two calls of 75."""
+    n, h = 256, 0.5e-3
+    x = (np.arange(n) - (n - 1) / 2.0) * h
+    r = np.sqrt(x[None, None, :] ** 2 + x[None, :, None] ** 2 + x[:, None, None] ** 2)
+    speed = np.where((r > 40e-3) & (r < 48e-3), 2600.0, 1540.0).astype(np.float32)
+    rng = np.random.default_rng(256)
+    v = rng.standard_normal((150, 3))
+    sensors = 55e-3 * v / np.linalg.norm(v, axis=1, keepdims=True)
+    vox = np.arange(0, n ** 3, 101, dtype=np.int32)
+    sp, vx = torch.from_numpy(speed).cuda(), torch.from_numpy(vox).cuda()
+    whole = ctx.eikonal_tables_3d(sp, h, sensors, vx).cpu().numpy()
+    parts = np.concatenate([ctx.eikonal_tables_3d(sp, h, sensors[s:s + 75], vx).cpu().numpy() for s in (0, 75)])
+    diff = int((whole.view(np.uint32) != parts.view(np.uint32)).sum())
+    print(f"[eik3 tables] 256^3, 150 sensors in two internal chunks: {diff} entries differ from two calls", flush=True)
+    assert np.all(np.isfinite(whole))
+    assert diff == 0
