@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ 
 // is monotone, so the order in which their writes land changes the work,
 // not the result.  Passes repeat until one pair changes no node.
 constexpr int DG_PAIRS = 48;                 // a tile that has not settled re-queues itself
-constexpr uint32_t F_DEAD = 0xFFFFFFFFu;     // frozen or outside the grid: never updated
+constexpr uint32_t F_DEAD24 = 0xFFFFFFu;     // frozen or outside the grid: never updated (F <= 2^23)
 
 __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq, const uint32_t *__restrict__ Fmap,
                                                       EikGrid g, const int *__restrict__ seed_ij,
@@ -237,9 +237,12 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
                                                       uint32_t *__restrict__ list_next,
                                                       uint32_t *__restrict__ flags_next,
                                                       uint32_t *__restrict__ counters) {
+    // F of each node in 24 bits (F <= 2^23), split into a 16-bit and an 8-bit
+    // array, F_DEAD24 where not updated: with the tile, 7.7 KB of LDS per
+    // wave, so that LDS holds 20 waves per CU
     __shared__ uint32_t T[HS * HS];
-    __shared__ uint32_t Fl[TS * TS];   // F of each node, F_DEAD where not updated
-    __shared__ uint32_t chg[TS];       // bit x of word y: node (x, y) lowered during the visit
+    __shared__ uint16_t Flo[TS * TS];
+    __shared__ uint8_t Fhi[TS * TS];
     __shared__ uint32_t side_bits;
 
     const int lane = threadIdx.x;
@@ -253,7 +256,6 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
         flags_cur[tile] = 0u;
         side_bits = 0u;
     }
-    if (lane < TS) chg[lane] = 0u;
     for (int idx = lane; idx < 4 * TS; idx += 64) {
         const int side = idx / TS, o = idx % TS;
         int gx, gy, l;
@@ -268,14 +270,15 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
     for (int j = 0; j < TS * TS / 64; ++j) {
         const int node = j * 64 + lane, y = node / TS, x = node % TS;
         const int gx = gx0 + x, gy = gy0 + y;
-        uint32_t v = TQ_INF, f = F_DEAD, sv;
+        uint32_t v = TQ_INF, f = F_DEAD24, sv;
         if (gx < g.nx && gy < g.ny) {
             const long k = (long)gy * g.nx + gx;
             v = map[k];
             if (!is_frozen(gx, gy, seed_ij, seed_val, m, sv)) f = Fmap[k];
         }
         T[(y + 1) * HS + x + 1] = v;
-        Fl[node] = f;
+        Flo[node] = (uint16_t)(f & 0xFFFFu);
+        Fhi[node] = (uint8_t)(f >> 16);
     }
     __syncthreads();
 
@@ -283,6 +286,7 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
     // in the half's sweep frame lane i takes column x' = i; the frame flips x
     // for half 1, and y for half 1 in the first pass and half 0 in the second
     const int xs = half ? TS - 1 - i : i;
+    uint32_t mine = 0;  // bit y: this lane lowered node (xs, y)
     int pair = 0;
     for (; pair < DG_PAIRS; ++pair) {
         int any = 0;
@@ -297,15 +301,15 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
             for (int k = 0; k < TS; ++k) {
                 const int yp = i <= k ? k - i : k + TS - i;
                 const int y = flip_y ? TS - 1 - yp : yp;
-                const uint32_t f = Fl[y * TS + xs];
-                if (f != F_DEAD) {
+                const uint32_t f = (uint32_t)Flo[y * TS + xs] | ((uint32_t)Fhi[y * TS + xs] << 16);
+                if (f != F_DEAD24) {
                     const int c = (y + 1) * HS + xs + 1;
                     const uint32_t a = min(T[c - 1], T[c + 1]);
                     const uint32_t b = min(T[c - HS], T[c + HS]);
                     const uint32_t nv = pat_eik::godunov2_int(a, b, f, pat_eik::eik_f2(f));
                     if (nv < T[c]) {
                         T[c] = nv;
-                        atomicOr(&chg[y], 1u << xs);
+                        mine |= 1u << y;
                         any = 1;
                     }
                 }
@@ -318,15 +322,19 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
         if (!__syncthreads_or(any)) break;
     }
 
+    // column c was swept by lane c (half 0) and lane 63 - c (half 1); lane L
+    // writes back rows 16 (L / 32) .. +15 of column L % 32
+    const int col = lane & (TS - 1);
+    const uint32_t cm = (uint32_t)__shfl((int)mine, col) | (uint32_t)__shfl((int)mine, 63 - col);
     unsigned sides = 0;
-    for (int j = 0; j < TS * TS / 64; ++j) {
-        const int node = j * 64 + lane, y = node / TS, x = node % TS;
-        if (!((chg[y] >> x) & 1u)) continue;
-        map[(long)(gy0 + y) * g.nx + gx0 + x] = T[(y + 1) * HS + x + 1];
+    for (int q = 0; q < TS / 2; ++q) {
+        const int y = (lane >> 5) * (TS / 2) + q;
+        if (!((cm >> y) & 1u)) continue;
+        map[(long)(gy0 + y) * g.nx + gx0 + col] = T[(y + 1) * HS + col + 1];
         if (y == 0) sides |= 1u;
         if (y == TS - 1) sides |= 2u;
-        if (x == 0) sides |= 4u;
-        if (x == TS - 1) sides |= 8u;
+        if (col == 0) sides |= 4u;
+        if (col == TS - 1) sides |= 8u;
     }
     if (pair == DG_PAIRS) sides |= 16u;
     if (sides) atomicOr(&side_bits, sides);
