@@ -298,20 +298,25 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
             // so every lane works in every step; each diagonal follows the one
             // before it within the pass, except diagonal 32, which reads
             // diagonal 31 from the pass before
+            const int ymask = flip_y ? TS - 1 : 0;
             for (int k = 0; k < TS; ++k) {
-                const int yp = i <= k ? k - i : k + TS - i;
-                const int y = flip_y ? TS - 1 - yp : yp;
+                // (k - i) mod 32, mirrored by ymask (31 - y == y ^ 31)
+                const int y = ((k - i) & (TS - 1)) ^ ymask;
+                const int c = (y + 1) * HS + xs + 1;
+                // every read of the step issued at once, the dead test at the
+                // write; a dead node is evaluated with F = 0, which keeps the
+                // square root in range and is never written
                 const uint32_t f = (uint32_t)Flo[y * TS + xs] | ((uint32_t)Fhi[y * TS + xs] << 16);
-                if (f != F_DEAD24) {
-                    const int c = (y + 1) * HS + xs + 1;
-                    const uint32_t a = min(T[c - 1], T[c + 1]);
-                    const uint32_t b = min(T[c - HS], T[c + HS]);
-                    const uint32_t nv = pat_eik::godunov2_int(a, b, f, pat_eik::eik_f2(f));
-                    if (nv < T[c]) {
-                        T[c] = nv;
-                        mine |= 1u << y;
-                        any = 1;
-                    }
+                const uint32_t a = min(T[c - 1], T[c + 1]);
+                const uint32_t b = min(T[c - HS], T[c + HS]);
+                const uint32_t cur = T[c];
+                const bool live = f != F_DEAD24;
+                const uint32_t fl = live ? f : 0u;
+                const uint32_t nv = pat_eik::godunov2_int(a, b, fl, pat_eik::eik_f2(fl));
+                if (live && nv < cur) {
+                    T[c] = nv;
+                    mine |= 1u << y;
+                    any = 1;
                 }
                 // the wave's LDS accesses execute in order, so the next
                 // diagonal reads this one's writes; the pair's closing barrier
