@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(EK_THREADS) k_eik_tile(uint32_t *__restrict__ 
 // of its diagonal (the diagonals folded into 32 steps per pass, below), so
 // that a front moving with a sweep crosses the tile in at most two passes.  Both halves update the tile at once; the update
 // is monotone, so the order in which their writes land changes the work,
-// not the result.  Passes repeat until one pair changes no node.
+// not the result.  Passes repeat until one changes no node.
 constexpr int DG_PAIRS = 48;                 // a tile that has not settled re-queues itself
 constexpr uint32_t F_DEAD24 = 0xFFFFFFu;     // frozen or outside the grid: never updated (F <= 2^23)
 
@@ -287,11 +287,14 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
     // for half 1, and y for half 1 in the first pass and half 0 in the second
     const int xs = half ? TS - 1 - i : i;
     uint32_t mine = 0;  // bit y: this lane lowered node (xs, y)
-    int pair = 0;
-    for (; pair < DG_PAIRS; ++pair) {
-        int any = 0;
+    // a pass that changes no node ends the visit: every node was evaluated in
+    // it against neighbours that held their final values
+    int passes = 0;
+    bool settled = false;
+    for (int pair = 0; pair < DG_PAIRS && !settled; ++pair) {
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
+            int any = 0;
             const bool flip_y = (pass == 0) == (half == 1);
             // folded diagonals: in step k lane i takes row y' = k - i of
             // diagonal k while i <= k, else row k + 32 - i of diagonal k + 32,
@@ -319,12 +322,15 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
                     any = 1;
                 }
                 // the wave's LDS accesses execute in order, so the next
-                // diagonal reads this one's writes; the pair's closing barrier
-                // settles everything before a pair can report no change
+                // diagonal reads this one's writes
                 __builtin_amdgcn_wave_barrier();
             }
+            ++passes;
+            if (!__syncthreads_or(any)) {
+                settled = true;
+                break;
+            }
         }
-        if (!__syncthreads_or(any)) break;
     }
 
     // column c was swept by lane c (half 0) and lane 63 - c (half 1); lane L
@@ -341,13 +347,12 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
         if (col == 0) sides |= 4u;
         if (col == TS - 1) sides |= 8u;
     }
-    if (pair == DG_PAIRS) sides |= 16u;
+    if (!settled) sides |= 16u;
     if (sides) atomicOr(&side_bits, sides);
     __syncthreads();
     if (lane == 0) {
-        // two directional sweeps per pass, two passes per pair
-        atomicAdd(reinterpret_cast<unsigned long long *>(counters + 2),
-                  (unsigned long long)(4 * min(pair + 1, DG_PAIRS)));
+        // two directional sweeps per pass
+        atomicAdd(reinterpret_cast<unsigned long long *>(counters + 2), (unsigned long long)(2 * passes));
         const unsigned sb = side_bits;
         uint32_t *cnt_next = counters;
         const uint32_t base = (uint32_t)m * g.tiles_per_map;
