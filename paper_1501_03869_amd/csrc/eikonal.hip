@@ -256,29 +256,46 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
         flags_cur[tile] = 0u;
         side_bits = 0u;
     }
-    for (int idx = lane; idx < 4 * TS; idx += 64) {
-        const int side = idx / TS, o = idx % TS;
-        int gx, gy, l;
-        if (side == 0) { gx = gx0 + o; gy = gy0 - 1; l = o + 1; }
-        else if (side == 1) { gx = gx0 + o; gy = gy0 + TS; l = (TS + 1) * HS + o + 1; }
-        else if (side == 2) { gx = gx0 - 1; gy = gy0 + o; l = (o + 1) * HS; }
-        else { gx = gx0 + TS; gy = gy0 + o; l = (o + 1) * HS + TS + 1; }
+    // every global load of the visit is issued before the first is waited
+    // for: the halo (two per lane), then the tile's times and slowness (two
+    // rows of 32 per load instruction)
+    constexpr int HALO_PER_LANE = 4 * TS / 64, NODES_PER_LANE = TS * TS / 64;
+    uint32_t hv[HALO_PER_LANE], v[NODES_PER_LANE], f[NODES_PER_LANE];
+    int hl[HALO_PER_LANE];
+#pragma unroll
+    for (int j = 0; j < HALO_PER_LANE; ++j) {
+        const int idx = j * 64 + lane, side = idx / TS, o = idx % TS;
+        int gx, gy;
+        if (side == 0) { gx = gx0 + o; gy = gy0 - 1; hl[j] = o + 1; }
+        else if (side == 1) { gx = gx0 + o; gy = gy0 + TS; hl[j] = (TS + 1) * HS + o + 1; }
+        else if (side == 2) { gx = gx0 - 1; gy = gy0 + o; hl[j] = (o + 1) * HS; }
+        else { gx = gx0 + TS; gy = gy0 + o; hl[j] = (o + 1) * HS + TS + 1; }
         const bool in = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny;
-        T[l] = in ? map[(long)gy * g.nx + gx] : TQ_INF;
+        hv[j] = in ? map[(long)gy * g.nx + gx] : TQ_INF;
     }
-    // interior: two rows of 32 per load instruction
-    for (int j = 0; j < TS * TS / 64; ++j) {
-        const int node = j * 64 + lane, y = node / TS, x = node % TS;
-        const int gx = gx0 + x, gy = gy0 + y;
-        uint32_t v = TQ_INF, f = F_DEAD24, sv;
-        if (gx < g.nx && gy < g.ny) {
-            const long k = (long)gy * g.nx + gx;
-            v = map[k];
-            if (!is_frozen(gx, gy, seed_ij, seed_val, m, sv)) f = Fmap[k];
-        }
-        T[(y + 1) * HS + x + 1] = v;
-        Flo[node] = (uint16_t)(f & 0xFFFFu);
-        Fhi[node] = (uint8_t)(f >> 16);
+#pragma unroll
+    for (int j = 0; j < NODES_PER_LANE; ++j) {
+        const int node = j * 64 + lane, gx = gx0 + node % TS, gy = gy0 + node / TS;
+        const bool in = gx < g.nx && gy < g.ny;
+        const long k = in ? (long)gy * g.nx + gx : 0;
+        v[j] = in ? map[k] : TQ_INF;
+        f[j] = in ? Fmap[k] : F_DEAD24;
+    }
+#pragma unroll
+    for (int j = 0; j < HALO_PER_LANE; ++j) T[hl[j]] = hv[j];
+    // frozen nodes (the seed box of this sensor) are never updated
+    const int sbx = seed_ij[2 * m], sby = seed_ij[2 * m + 1];
+#pragma unroll
+    for (int j = 0; j < NODES_PER_LANE; ++j) {
+        const int node = j * 64 + lane, x = node % TS, y = node / TS;
+        const int bx = gx0 + x - sbx, by = gy0 + y - sby;
+        uint32_t fj = f[j];
+        if ((unsigned)bx < (unsigned)SEED_BOX && (unsigned)by < (unsigned)SEED_BOX &&
+            seed_val[m * SEED_BOX * SEED_BOX + by * SEED_BOX + bx] != TQ_INF)
+            fj = F_DEAD24;
+        T[(y + 1) * HS + x + 1] = v[j];
+        Flo[node] = (uint16_t)(fj & 0xFFFFu);
+        Fhi[node] = (uint8_t)(fj >> 16);
     }
     __syncthreads();
 
