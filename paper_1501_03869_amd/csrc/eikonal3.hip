@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "eik_update.h"
+#include "eik_round.h"
 #include "pat_internal.h"
 
 namespace {
@@ -281,7 +282,7 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
     if ((rc = ctx->eik_lists.grow((size_t)2 * max_bricks * sizeof(uint32_t)))) return rc;
     if ((rc = ctx->eik_seeds.grow((size_t)chunk * (3 * sizeof(int) + SEED_BOX3 * SEED_BOX3 * SEED_BOX3 * sizeof(uint32_t)))))
         return rc;
-    if ((rc = ctx->eik_count.grow(4 * sizeof(uint32_t)))) return rc;
+    if ((rc = ctx->eik_count.grow(pat_eik::EIK_COUNTERS * sizeof(uint32_t)))) return rc;
 
     uint32_t *Tq = static_cast<uint32_t *>(ctx->eik_tq.ptr);
     uint32_t *Fd = static_cast<uint32_t *>(ctx->eik_f.ptr);
@@ -291,11 +292,14 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
                            static_cast<uint32_t *>(ctx->eik_lists.ptr) + max_bricks };
     int *seed_ijl = static_cast<int *>(ctx->eik_seeds.ptr);
     uint32_t *seed_val = reinterpret_cast<uint32_t *>(seed_ijl + 3 * chunk);
-    uint32_t *counters = static_cast<uint32_t *>(ctx->eik_count.ptr);  // [0] next count, [1] unused (0), [2..3] sweeps
+    uint32_t *counters = static_cast<uint32_t *>(ctx->eik_count.ptr);  // laid out in eik_round.h
+    volatile uint32_t *host_counts = ctx->eik_count_host;
 
     PAT_HIP(hipMemcpyAsync(Fd, Fh.data(), (size_t)n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     PAT_HIP(hipMemsetAsync(ctx->eik_flags.ptr, 0, (size_t)2 * max_bricks * sizeof(uint32_t), st));
-    PAT_HIP(hipMemsetAsync(counters, 0, 4 * sizeof(uint32_t), st));
+    // every list entry holds a valid index (0) before its first append
+    PAT_HIP(hipMemsetAsync(ctx->eik_lists.ptr, 0, (size_t)2 * max_bricks * sizeof(uint32_t), st));
+    PAT_HIP(hipMemsetAsync(counters, 0, pat_eik::EIK_COUNTERS * sizeof(uint32_t), st));
 
     const long round_cap = pat_env_round_cap(100L * (g.bx + g.by + g.bz) + 1000);
     constexpr int B3 = SEED_BOX3 * SEED_BOX3 * SEED_BOX3;
@@ -353,14 +357,19 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
         while (cnt > 0) {
             if (++chunk_rounds > round_cap)
                 return pat_fail(PAT_ENOCONV, "eikonal relaxation did not settle within %ld rounds", round_cap);
-            PAT_HIP(hipMemsetAsync(counters, 0, sizeof(uint32_t), st));
+            // after the tile kernel, a one-thread kernel writes the next
+            // count to the pinned words and clears the device count
             k_eik3_brick<<<dim3(cnt), E3_THREADS, 0, st>>>(Tq, Fd, g, seed_ijl, seed_val, lists[cur], flags[cur],
                                                            lists[cur ^ 1], flags[cur ^ 1], counters);
             PAT_HIP(hipGetLastError());
-            PAT_HIP(hipMemcpyAsync(ctx->eik_count_host, counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+            pat_eik::k_eik_round_end<<<dim3(1), 64, 0, st>>>(counters, ctx->eik_count_host);
+            PAT_HIP(hipGetLastError());
             PAT_HIP(hipStreamSynchronize(st));
             visits += cnt;
-            cnt = ctx->eik_count_host[0];
+            cnt = host_counts[0];
+            if (cnt > (uint32_t)max_bricks)
+                return pat_fail(PAT_EDEVICE, "eikonal round reported %u active bricks, above the %ld the list holds",
+                                cnt, (long)max_bricks);
             cur ^= 1;
         }
         rounds += chunk_rounds;
@@ -372,8 +381,8 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
     PAT_HIP(hipStreamSynchronize(st));
     ctx->last_eik.rounds = rounds;
     ctx->last_eik.tile_visits = visits;
-    ctx->last_eik.guard_hits = ctx->eik_count_host[1];
-    ctx->last_eik.sweeps = (int64_t)ctx->eik_count_host[2] | ((int64_t)ctx->eik_count_host[3] << 32);
+    ctx->last_eik.guard_hits = host_counts[1];
+    ctx->last_eik.sweeps = (int64_t)host_counts[2] | ((int64_t)host_counts[3] << 32);
     ctx->last_eik.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     return PAT_OK;
 }
