@@ -10,6 +10,7 @@
 #include <new>
 #include <vector>
 
+#include "eik_round.h"
 #include "pat_internal.h"
 
 static thread_local char g_err[512] = "";
@@ -93,11 +94,13 @@ extern "C" int pat_ctx_create(int device, pat_ctx **out) {
     for (pat_devbuf *b : { &c->gather_scratch, &c->gather_done, &c->sensors, &c->eik_tq, &c->eik_f, &c->eik_flags,
                            &c->eik_lists, &c->eik_seeds, &c->eik_count })
         b->fault_bytes = fb;
-    hipError_t e = hipHostMalloc((void **)&c->eik_count_host, 4 * sizeof(uint32_t), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void **)&c->eik_count_host, pat_eik::EIK_HOST_WORDS * sizeof(uint32_t),
+                                 hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;
         return pat_hip_fail(e, "hipHostMalloc");
     }
+    for (int i = 0; i < pat_eik::EIK_HOST_WORDS; ++i) c->eik_count_host[i] = 0u;
     // the device's fixed scratch array (pat_backproject_noalloc), looked up
     // once per device with this device current
     int rc = pat_fixed_scratch_attach(device, &c->fixed_scratch);

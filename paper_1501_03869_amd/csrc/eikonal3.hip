@@ -294,6 +294,7 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
     uint32_t *seed_val = reinterpret_cast<uint32_t *>(seed_ijl + 3 * chunk);
     uint32_t *counters = static_cast<uint32_t *>(ctx->eik_count.ptr);  // laid out in eik_round.h
     volatile uint32_t *host_counts = ctx->eik_count_host;
+    uint32_t seq = host_counts[4];  // the last round's number, counted on per round
 
     PAT_HIP(hipMemcpyAsync(Fd, Fh.data(), (size_t)n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     PAT_HIP(hipMemsetAsync(ctx->eik_flags.ptr, 0, (size_t)2 * max_bricks * sizeof(uint32_t), st));
@@ -358,13 +359,14 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
             if (++chunk_rounds > round_cap)
                 return pat_fail(PAT_ENOCONV, "eikonal relaxation did not settle within %ld rounds", round_cap);
             // after the tile kernel, a one-thread kernel writes the next
-            // count to the pinned words and clears the device count
+            // count to the pinned words and clears the device count; the
+            // host polls the words' sequence number (eik_round.h)
             k_eik3_brick<<<dim3(cnt), E3_THREADS, 0, st>>>(Tq, Fd, g, seed_ijl, seed_val, lists[cur], flags[cur],
                                                            lists[cur ^ 1], flags[cur ^ 1], counters);
             PAT_HIP(hipGetLastError());
-            pat_eik::k_eik_round_end<<<dim3(1), 64, 0, st>>>(counters, ctx->eik_count_host);
+            pat_eik::k_eik_round_end<<<dim3(1), 64, 0, st>>>(counters, ctx->eik_count_host, ++seq);
             PAT_HIP(hipGetLastError());
-            PAT_HIP(hipStreamSynchronize(st));
+            PAT_HIP(pat_eik::wait_round(host_counts, seq, st));
             visits += cnt;
             cnt = host_counts[0];
             if (cnt > (uint32_t)max_bricks)

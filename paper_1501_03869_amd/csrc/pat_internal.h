@@ -51,7 +51,7 @@ struct pat_ctx {
     pat_devbuf sensors;
     // eikonal working memory
     pat_devbuf eik_tq, eik_f, eik_flags, eik_lists, eik_seeds, eik_count;
-    uint32_t *eik_count_host = nullptr;  // pinned: next-round count, guard hits, sweeps (64-bit)
+    uint32_t *eik_count_host = nullptr;  // pinned words of a relaxation round, laid out in eik_round.h
     pat_eikonal_stats last_eik{};
     // the device's fixed scratch array (pat_backproject_noalloc), and whether
     // the call in progress takes its gather scratch from there
