@@ -63,16 +63,17 @@ __device__ __forceinline__ bool is_frozen(int gx, int gy, const int *seed_ij, co
     return val != TQ_INF;
 }
 
-// Tq[m][k] = seed value on frozen nodes, "not reached" elsewhere.
-__global__ void __launch_bounds__(256) k_eik_init(uint32_t *__restrict__ Tq, int maps, EikGrid g,
-                                                  const int *__restrict__ seed_ij, const uint32_t *__restrict__ seed_val) {
-    const long n = (long)g.nx * g.ny;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * maps) return;
-    const int m = (int)(i / n);
-    const int k = (int)(i % n);
-    uint32_t v;
-    Tq[i] = is_frozen(k % g.nx, k / g.nx, seed_ij, seed_val, m, v) ? v : TQ_INF;
+// The seed values of the frozen nodes, over maps whose every word the host
+// has set to "not reached": one workgroup per map, a thread per node of its
+// seed box (a node is frozen where the box holds a value).
+__global__ void __launch_bounds__(64) k_eik_seed(uint32_t *__restrict__ Tq, EikGrid g, const int *__restrict__ seed_ij,
+                                                 const uint32_t *__restrict__ seed_val) {
+    const int m = blockIdx.x, t = threadIdx.x;
+    if (t >= SEED_BOX * SEED_BOX) return;
+    const int gx = seed_ij[2 * m] + t % SEED_BOX, gy = seed_ij[2 * m + 1] + t / SEED_BOX;
+    if (gx < 0 || gx >= g.nx || gy < 0 || gy >= g.ny) return;
+    const uint32_t v = seed_val[m * SEED_BOX * SEED_BOX + t];
+    if (v != TQ_INF) Tq[(long)m * g.nx * g.ny + (long)gy * g.nx + gx] = v;
 }
 
 __device__ __forceinline__ void activate(uint32_t tile, uint32_t *flags_next, uint32_t *list_next, uint32_t *cnt_next) {
@@ -382,16 +383,16 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
     }
 }
 
-// table[s0 + m][p] = Tq[m][pix[p]] * lsb, rounded once to float32 seconds.
+// table[s0 + m][p] = Tq[m][pix[p]] * lsb, rounded once to float32 seconds;
+// blockIdx.y is the map within a launch of at most 65535 maps from m0.
 __global__ void __launch_bounds__(256) k_eik_extract(const uint32_t *__restrict__ Tq, long n_nodes,
-                                                     const int32_t *__restrict__ pix, int P, int maps, double lsb,
+                                                     const int32_t *__restrict__ pix, int P, int m0, double lsb,
                                                      float *__restrict__ table) {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long)P * maps) return;
-    const int m = (int)(i / P);
-    const int p = (int)(i % P);
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int m = m0 + (int)blockIdx.y;
+    if (p >= P) return;
     const uint32_t v = Tq[(long)m * n_nodes + pix[p]];
-    table[i] = v == TQ_INF ? INFINITY : (float)((double)v * lsb);
+    table[(long)m * P + p] = v == TQ_INF ? INFINITY : (float)((double)v * lsb);
 }
 
 // The local update alone, for checking it against its definition: out[i] =
@@ -554,8 +555,9 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
         PAT_HIP(hipMemcpyAsync(seed_val, hval.data(), (size_t)maps * SEED_BOX * SEED_BOX * sizeof(uint32_t),
                                hipMemcpyHostToDevice, st));
         PAT_HIP(hipMemcpyAsync(lists[0], init_list.data(), init_list.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
-        const long tot = (long)maps * n;
-        k_eik_init<<<dim3((unsigned)((tot + 255) / 256)), 256, 0, st>>>(Tq, maps, g, seed_ij, seed_val);
+        // every word "not reached" (all ones), then the seed values
+        PAT_HIP(hipMemsetAsync(Tq, 0xFF, (size_t)maps * n * sizeof(uint32_t), st));
+        k_eik_seed<<<dim3((unsigned)maps), 64, 0, st>>>(Tq, g, seed_ij, seed_val);
         PAT_HIP(hipGetLastError());
 
         uint32_t cnt = (uint32_t)init_list.size();
@@ -585,10 +587,12 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
             cur ^= 1;
         }
         rounds += chunk_rounds;
-        const long tp = (long)P * maps;
-        k_eik_extract<<<dim3((unsigned)((tp + 255) / 256)), 256, 0, st>>>(Tq, n, d_pix, P, maps, lsb,
-                                                                         d_table + (long)s0 * P);
-        PAT_HIP(hipGetLastError());
+        for (int m0 = 0; m0 < maps; m0 += 65535) {
+            const int mg = std::min(65535, maps - m0);
+            k_eik_extract<<<dim3((unsigned)((P + 255) / 256), (unsigned)mg), 256, 0, st>>>(Tq, n, d_pix, P, m0, lsb,
+                                                                                         d_table + (long)s0 * P);
+            PAT_HIP(hipGetLastError());
+        }
     }
     PAT_HIP(hipStreamSynchronize(st));
     ctx->last_eik.rounds = rounds;

@@ -50,17 +50,20 @@ __device__ __forceinline__ bool is_frozen3(int gx, int gy, int gz, const int *se
     return val != TQ_INF;
 }
 
-__global__ void __launch_bounds__(256) k_eik3_init(uint32_t *__restrict__ Tq, int maps, EikGrid3 g,
+// The seed values of the frozen nodes, over maps whose every word the host
+// has set to "not reached": one workgroup per map, a thread per node of its
+// seed box (a node is frozen where the box holds a value).
+__global__ void __launch_bounds__(128) k_eik3_seed(uint32_t *__restrict__ Tq, EikGrid3 g,
                                                    const int *__restrict__ seed_ijl,
                                                    const uint32_t *__restrict__ seed_val) {
-    const long n = (long)g.nx * g.ny * g.nz;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * maps) return;
-    const int m = (int)(i / n);
-    const long k = i % n;
-    const int gx = (int)(k % g.nx), gy = (int)((k / g.nx) % g.ny), gz = (int)(k / ((long)g.nx * g.ny));
-    uint32_t v;
-    Tq[i] = is_frozen3(gx, gy, gz, seed_ijl, seed_val, m, v) ? v : TQ_INF;
+    constexpr int B = SEED_BOX3;
+    const int m = blockIdx.x, t = threadIdx.x;
+    if (t >= B * B * B) return;
+    const int gx = seed_ijl[3 * m] + t % B, gy = seed_ijl[3 * m + 1] + (t / B) % B;
+    const int gz = seed_ijl[3 * m + 2] + t / (B * B);
+    if (gx < 0 || gx >= g.nx || gy < 0 || gy >= g.ny || gz < 0 || gz >= g.nz) return;
+    const uint32_t v = seed_val[m * B * B * B + t];
+    if (v != TQ_INF) Tq[((long)m * g.nz + gz) * ((long)g.nx * g.ny) + (long)gy * g.nx + gx] = v;
 }
 
 __device__ __forceinline__ void activate3(uint32_t brick, uint32_t *flags_next, uint32_t *list_next,
@@ -203,16 +206,16 @@ __global__ void __launch_bounds__(E3_THREADS) k_eik3_brick(uint32_t *__restrict_
     }
 }
 
-// table[s0 + m][p] = Tq[m][vox[p]] * lsb, rounded once to float32 seconds.
+// table[s0 + m][p] = Tq[m][vox[p]] * lsb, rounded once to float32 seconds;
+// blockIdx.y is the map within a launch of at most 65535 maps from m0.
 __global__ void __launch_bounds__(256) k_eik3_extract(const uint32_t *__restrict__ Tq, long n_nodes,
-                                                      const int32_t *__restrict__ vox, int P, int maps, double lsb,
+                                                      const int32_t *__restrict__ vox, int P, int m0, double lsb,
                                                       float *__restrict__ table) {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (long)P * maps) return;
-    const int m = (int)(i / P);
-    const int p = (int)(i % P);
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int m = m0 + (int)blockIdx.y;
+    if (p >= P) return;
     const uint32_t v = Tq[(long)m * n_nodes + vox[p]];
-    table[i] = v == TQ_INF ? INFINITY : (float)((double)v * lsb);
+    table[(long)m * P + p] = v == TQ_INF ? INFINITY : (float)((double)v * lsb);
 }
 
 }  // namespace
@@ -349,7 +352,9 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
         PAT_HIP(hipMemcpyAsync(seed_val, hval.data(), (size_t)maps * B3 * sizeof(uint32_t), hipMemcpyHostToDevice, st));
         PAT_HIP(hipMemcpyAsync(lists[0], init_list.data(), init_list.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
         const long tot = (long)maps * n;
-        k_eik3_init<<<dim3((unsigned)((tot + 255) / 256)), 256, 0, st>>>(Tq, maps, g, seed_ijl, seed_val);
+        // every word "not reached" (all ones), then the seed values
+        PAT_HIP(hipMemsetAsync(Tq, 0xFF, (size_t)tot * sizeof(uint32_t), st));
+        k_eik3_seed<<<dim3((unsigned)maps), 128, 0, st>>>(Tq, g, seed_ijl, seed_val);
         PAT_HIP(hipGetLastError());
 
         uint32_t cnt = (uint32_t)init_list.size();
@@ -375,10 +380,12 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
             cur ^= 1;
         }
         rounds += chunk_rounds;
-        const long tp = (long)P * maps;
-        k_eik3_extract<<<dim3((unsigned)((tp + 255) / 256)), 256, 0, st>>>(Tq, n, d_vox, P, maps, lsb,
-                                                                           d_table + (long)s0 * P);
-        PAT_HIP(hipGetLastError());
+        for (int m0 = 0; m0 < maps; m0 += 65535) {
+            const int mg = std::min(65535, maps - m0);
+            k_eik3_extract<<<dim3((unsigned)((P + 255) / 256), (unsigned)mg), 256, 0, st>>>(Tq, n, d_vox, P, m0, lsb,
+                                                                                           d_table + (long)s0 * P);
+            PAT_HIP(hipGetLastError());
+        }
     }
     PAT_HIP(hipStreamSynchronize(st));
     ctx->last_eik.rounds = rounds;
