@@ -48,6 +48,7 @@ constexpr int EK_THREADS = 256;         // 32 columns x 8 strips of 4 rows
 constexpr uint32_t EIK_DIAG_MIN_TILES = 1024;
 constexpr int ROWS_PER_THREAD = TS * TS / EK_THREADS;
 constexpr uint32_t TQ_INF = 0xFFFFFFFFu;
+constexpr int EX_MAPS = 4;                 // maps per thread in the table extraction
 constexpr int SEED_BOX = 5;             // frozen nodes lie in a 5x5 box around the nearest node
 constexpr int LOCAL_ITER_CAP = 6 * TS;  // a tile that has not settled re-queues itself
 
@@ -383,16 +384,24 @@ __global__ void __launch_bounds__(64) k_eik_tile_diag(uint32_t *__restrict__ Tq,
     }
 }
 
-// table[s0 + m][p] = Tq[m][pix[p]] * lsb, rounded once to float32 seconds;
-// blockIdx.y is the map within a launch of at most 65535 maps from m0.
+// table[s0 + m][p] = Tq[m][pix[p]] * lsb, rounded once to float32 seconds.
+// A thread takes one pixel of EX_MAPS maps (its index read once, the maps'
+// loads in flight together); blockIdx.y is the group of EX_MAPS maps within a
+// launch that starts at map m0 of the chunk's maps.
 __global__ void __launch_bounds__(256) k_eik_extract(const uint32_t *__restrict__ Tq, long n_nodes,
-                                                     const int32_t *__restrict__ pix, int P, int m0, double lsb,
+                                                     const int32_t *__restrict__ pix, int P, int m0, int maps, double lsb,
                                                      float *__restrict__ table) {
     const int p = blockIdx.x * 256 + threadIdx.x;
-    const int m = m0 + (int)blockIdx.y;
     if (p >= P) return;
-    const uint32_t v = Tq[(long)m * n_nodes + pix[p]];
-    table[(long)m * P + p] = v == TQ_INF ? INFINITY : (float)((double)v * lsb);
+    const int mb = m0 + (int)blockIdx.y * EX_MAPS;
+    const long k = pix[p];
+    uint32_t v[EX_MAPS];
+#pragma unroll
+    for (int j = 0; j < EX_MAPS; ++j)
+        if (mb + j < maps) v[j] = Tq[(long)(mb + j) * n_nodes + k];
+#pragma unroll
+    for (int j = 0; j < EX_MAPS; ++j)
+        if (mb + j < maps) table[(long)(mb + j) * P + p] = v[j] == TQ_INF ? INFINITY : (float)((double)v[j] * lsb);
 }
 
 // The local update alone, for checking it against its definition: out[i] =
@@ -587,10 +596,10 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
             cur ^= 1;
         }
         rounds += chunk_rounds;
-        for (int m0 = 0; m0 < maps; m0 += 65535) {
-            const int mg = std::min(65535, maps - m0);
-            k_eik_extract<<<dim3((unsigned)((P + 255) / 256), (unsigned)mg), 256, 0, st>>>(Tq, n, d_pix, P, m0, lsb,
-                                                                                         d_table + (long)s0 * P);
+        for (int m0 = 0; m0 < maps; m0 += 65535 * EX_MAPS) {
+            const int groups = (std::min(65535 * EX_MAPS, maps - m0) + EX_MAPS - 1) / EX_MAPS;
+            const dim3 grid((unsigned)((P + 255) / 256), (unsigned)groups);
+            k_eik_extract<<<grid, 256, 0, st>>>(Tq, n, d_pix, P, m0, maps, lsb, d_table + (long)s0 * P);
             PAT_HIP(hipGetLastError());
         }
     }

@@ -33,6 +33,7 @@ constexpr int HB = BS + 2;              // brick edge with halo
 constexpr int E3_THREADS = 256;         // 8 x 8 columns x 4 pairs of z nodes
 constexpr int NODES_PER_THREAD = BS * BS * BS / E3_THREADS;
 constexpr uint32_t TQ_INF = 0xFFFFFFFFu;
+constexpr int EX_MAPS = 4;                 // maps per thread in the table extraction
 constexpr int SEED_BOX3 = 5;            // frozen nodes lie in a 5^3 box around the nearest node
 constexpr int LOCAL_ITER_CAP3 = 6 * BS; // a brick that has not settled re-queues itself
 
@@ -206,16 +207,24 @@ __global__ void __launch_bounds__(E3_THREADS) k_eik3_brick(uint32_t *__restrict_
     }
 }
 
-// table[s0 + m][p] = Tq[m][vox[p]] * lsb, rounded once to float32 seconds;
-// blockIdx.y is the map within a launch of at most 65535 maps from m0.
+// table[s0 + m][p] = Tq[m][vox[p]] * lsb, rounded once to float32 seconds.
+// A thread takes one pixel of EX_MAPS maps (its index read once, the maps'
+// loads in flight together); blockIdx.y is the group of EX_MAPS maps within a
+// launch that starts at map m0 of the chunk's maps.
 __global__ void __launch_bounds__(256) k_eik3_extract(const uint32_t *__restrict__ Tq, long n_nodes,
-                                                      const int32_t *__restrict__ vox, int P, int m0, double lsb,
+                                                      const int32_t *__restrict__ vox, int P, int m0, int maps, double lsb,
                                                       float *__restrict__ table) {
     const int p = blockIdx.x * 256 + threadIdx.x;
-    const int m = m0 + (int)blockIdx.y;
     if (p >= P) return;
-    const uint32_t v = Tq[(long)m * n_nodes + vox[p]];
-    table[(long)m * P + p] = v == TQ_INF ? INFINITY : (float)((double)v * lsb);
+    const int mb = m0 + (int)blockIdx.y * EX_MAPS;
+    const long k = vox[p];
+    uint32_t v[EX_MAPS];
+#pragma unroll
+    for (int j = 0; j < EX_MAPS; ++j)
+        if (mb + j < maps) v[j] = Tq[(long)(mb + j) * n_nodes + k];
+#pragma unroll
+    for (int j = 0; j < EX_MAPS; ++j)
+        if (mb + j < maps) table[(long)(mb + j) * P + p] = v[j] == TQ_INF ? INFINITY : (float)((double)v[j] * lsb);
 }
 
 }  // namespace
@@ -380,10 +389,10 @@ extern "C" int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx,
             cur ^= 1;
         }
         rounds += chunk_rounds;
-        for (int m0 = 0; m0 < maps; m0 += 65535) {
-            const int mg = std::min(65535, maps - m0);
-            k_eik3_extract<<<dim3((unsigned)((P + 255) / 256), (unsigned)mg), 256, 0, st>>>(Tq, n, d_vox, P, m0, lsb,
-                                                                                           d_table + (long)s0 * P);
+        for (int m0 = 0; m0 < maps; m0 += 65535 * EX_MAPS) {
+            const int groups = (std::min(65535 * EX_MAPS, maps - m0) + EX_MAPS - 1) / EX_MAPS;
+            const dim3 grid((unsigned)((P + 255) / 256), (unsigned)groups);
+            k_eik3_extract<<<grid, 256, 0, st>>>(Tq, n, d_vox, P, m0, maps, lsb, d_table + (long)s0 * P);
             PAT_HIP(hipGetLastError());
         }
     }
