@@ -135,7 +135,10 @@ size_t pat_backproject_scratch_bytes(int S, int P, int F);
  * more (1e-5 at rho of about 23 on a 1024^2 grid, where the grid's extent
  * sets the unit).  Synchronises `stream`.  PAT_ENOCONV if the relaxation exceeds its
  * round cap, 100 (tiles_x + tiles_y) + 1000 rounds of 32 x 32 tiles (never
- * expected; PAT_EIK_ROUND_CAP lowers it); the context stays usable.
+ * expected; PAT_EIK_ROUND_CAP lowers it); the context stays usable.  Between
+ * rounds the host waits on a pinned word the device writes (spinning, then
+ * synchronising the stream after 50 ms); PAT_EDEVICE if a round reports more
+ * active tiles than the maps have (never expected).
  */
 int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, int ny, double h,
                        const double *h_sensor_xy, int S, const int32_t *d_pix, int P,
@@ -204,7 +207,8 @@ int pat_eikonal_tables_o2(pat_ctx *ctx, const float *d_speed, int nx, int ny, do
  * time at the nearest node's speed).  Relaxation runs on 8 x 8 x 8 bricks;
  * statistics (pat_eikonal_last_stats) count bricks as tiles.  Synchronises
  * `stream`.  PAT_EINVAL for bad sizes, speeds, sensors or voxel indices;
- * PAT_ENOCONV if the relaxation exceeds its round cap (never expected).
+ * PAT_ENOCONV if the relaxation exceeds its round cap (never expected);
+ * PAT_EDEVICE if a round reports more active bricks than the maps have.
  */
 int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx, int ny, int nz, double h,
                           const double *h_sensor_xyz, int S, const int32_t *d_vox, int P,
@@ -213,7 +217,7 @@ int pat_eikonal_tables_3d(pat_ctx *ctx, const float *d_speed, int nx, int ny, in
 /* Statistics of the calling context's last pat_eikonal_tables or
  * pat_eikonal_tables_3d call. */
 typedef struct pat_eikonal_stats {
-    int64_t rounds;          /* relaxation rounds (kernel launches), all chunks */
+    int64_t rounds;          /* relaxation rounds, all chunks */
     int64_t tile_visits;     /* tiles (3-D: bricks) processed over all rounds */
     int64_t guard_hits;      /* always 0: the update is exact in integers and has
                                 no floating-point fallback */
