@@ -41,6 +41,10 @@
  *       PAT_EIK_ROUND_CAP=r  read at each pat_eikonal_tables /
  *         pat_eikonal_tables_3d call: the relaxation stops with PAT_ENOCONV
  *         after r rounds when r is below the built-in cap.
+ *   - PAT_EIK_SPIN_MS=t (0 <= t <= 50, default 50), read at each
+ *     pat_eikonal_tables / pat_eikonal_tables_3d call: how long the host polls
+ *     the device's pinned word between relaxation rounds before it
+ *     synchronises the stream instead; 0 synchronises at once.
  */
 #ifndef PAT_H
 #define PAT_H

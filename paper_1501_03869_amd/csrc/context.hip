@@ -47,6 +47,14 @@ long pat_env_round_cap(long builtin_cap) {
     return (end && *end == 0 && r >= 1 && r < builtin_cap) ? r : builtin_cap;
 }
 
+double pat_env_eik_spin_ms() {
+    const char *v = std::getenv("PAT_EIK_SPIN_MS");
+    if (!v || !*v) return 50.0;
+    char *end = nullptr;
+    const double ms = std::strtod(v, &end);
+    return (end && *end == 0 && ms >= 0.0 && ms <= 50.0) ? ms : 50.0;
+}
+
 bool pat_env_force_win() {
     const char *v = std::getenv("PAT_GATHER_FORCE");
     return v && std::strcmp(v, "win") == 0;

@@ -39,10 +39,12 @@ __global__ void __launch_bounds__(64) k_eik_round_end(uint32_t *__restrict__ cou
 }
 
 // Waits on the host until round seq's words are in: it polls the sequence
-// word for up to spin_ms, then falls back to synchronising the stream, after
-// which the words are final either way.  The GPU never waits on the host.
+// word for up to spin_ms (0: not at all), then falls back to synchronising
+// the stream, after which the words are final either way.  The GPU never
+// waits on the host.
 static inline hipError_t wait_round(volatile const uint32_t *host, uint32_t seq, hipStream_t st,
-                                    double spin_ms = 50.0) {
+                                    double spin_ms) {
+    if (spin_ms <= 0.0) return hipStreamSynchronize(st);
     const auto t0 = std::chrono::steady_clock::now();
     for (unsigned it = 1;; ++it) {
         if (host[4] == seq) return hipSuccess;

@@ -519,6 +519,7 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
     uint32_t *counters = static_cast<uint32_t *>(ctx->eik_count.ptr);  // laid out in eik_round.h
     volatile uint32_t *host_counts = ctx->eik_count_host;
     uint32_t seq = host_counts[4];  // the last round's number, counted on per round
+    const double spin_ms = pat_env_eik_spin_ms();
 
     PAT_HIP(hipMemcpyAsync(Fd, Fh.data(), (size_t)n * sizeof(uint32_t), hipMemcpyHostToDevice, st));
     PAT_HIP(hipMemsetAsync(ctx->eik_flags.ptr, 0, (size_t)2 * max_tiles * sizeof(uint32_t), st));
@@ -587,7 +588,7 @@ extern "C" int pat_eikonal_tables(pat_ctx *ctx, const float *d_speed, int nx, in
             PAT_HIP(hipGetLastError());
             pat_eik::k_eik_round_end<<<dim3(1), 64, 0, st>>>(counters, ctx->eik_count_host, ++seq);
             PAT_HIP(hipGetLastError());
-            PAT_HIP(pat_eik::wait_round(host_counts, seq, st));
+            PAT_HIP(pat_eik::wait_round(host_counts, seq, st, spin_ms));
             visits += cnt;
             cnt = host_counts[0];
             if (cnt > (uint32_t)max_tiles)

@@ -27,6 +27,9 @@ size_t pat_env_fault_alloc_bytes();
 // PAT_EIK_ROUND_CAP=r, read at each table-build call: the relaxation gives up
 // with PAT_ENOCONV after r rounds when r is below the built-in cap.
 long pat_env_round_cap(long builtin_cap);
+// how long the eikonal round loop polls the device's pinned words before it
+// synchronises the stream instead: PAT_EIK_SPIN_MS in [0, 50], else 50
+double pat_env_eik_spin_ms();
 // Test hook: PAT_GATHER_FORCE=win makes pat_backproject take the wave-window
 // gather wherever that kernel can run, so tests reach it at sizes the oracle
 // checks.

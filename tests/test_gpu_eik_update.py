@@ -16,7 +16,8 @@ unit.  The checks here:
     by its textbook closed form over the sorted neighbours;
   - the tables themselves: the same bits whether the sensors are built in one
     call or in chunks (which changes how many maps each launch relaxes and so
-    the workgroup schedule), in 2-D and 3-D."""
+    the workgroup schedule), in 2-D and 3-D, and whether the host learns each
+    round's size by polling or by synchronising the stream."""
 import numpy as np
 import pytest
 
@@ -225,6 +226,31 @@ def test_tables_same_bits_in_any_chunking(ctx, name, chunks):
         diff = int((split.view(np.uint32) != whole.view(np.uint32)).sum())
         print(f"[eik tables] {name}: {len(sensors)} sensors in chunks of {ch}: {diff} entries differ", flush=True)
         assert diff == 0
+
+
+@pytest.mark.parametrize("name", ["paper", "tiny3"])
+def test_tables_same_bits_when_rounds_synchronise(ctx, name, monkeypatch):
+    """Between relaxation rounds the host polls a pinned word the device
+    writes, and synchronises the stream instead when the word is late;
+    PAT_EIK_SPIN_MS=0 takes that second path every round.  Both paths, and a
+    short spin window, give the same tables (the rounds and visits, which
+    follow the schedule, are printed)."""
+    is3 = name == "tiny3"
+    geo = inputs.config3(name) if is3 else inputs.config(name)
+    sensors = geo.sensors if len(geo.sensors) <= 256 else geo.sensors[:256]
+    monkeypatch.delenv("PAT_EIK_SPIN_MS", raising=False)
+    polled = _tables(ctx, geo, sensors, geo.pix, is3)
+    st_polled = ctx.eikonal_stats()
+    for spin in ("0", "0.001"):
+        monkeypatch.setenv("PAT_EIK_SPIN_MS", spin)
+        other = _tables(ctx, geo, sensors, geo.pix, is3)
+        st = ctx.eikonal_stats()
+        diff = int((other.view(np.uint32) != polled.view(np.uint32)).sum())
+        print(f"[eik tables] {name}: spin {spin} ms against polling: {diff} entries differ, rounds "
+              f"{st['rounds']} / {st_polled['rounds']}, visits {st['tile_visits']} / {st_polled['tile_visits']}",
+              flush=True)
+        assert diff == 0
+        assert st["rounds"] > 0 and st["tile_visits"] > 0
 
 
 @pytest.mark.parametrize("name", ["small", "paper", "large"])
